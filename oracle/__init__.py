@@ -1,0 +1,40 @@
+"""FP64 CPU oracle for the R-matrix outer-region energy sweep.
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only ``tests/``, the package's
+``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg may import,
+call or execute anything in this directory.  The HIP library never links it and
+the Python binding never falls back to it.
+
+The oracle is a plain, slow, double-precision restatement of what the method
+computes at each scattering energy E (McLaughlin & Ballance, "Petascale
+computations for large-scale atomic and molecular collisions", Sec. 6, Eq. 1-2,
+plus the standard R-matrix matching of Burke, "R-Matrix Theory of Atomic
+Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
+
+* ``rmatrix.r_matrix``            boundary R-matrix from poles (Eq. 1, as the
+                                   product X*Y of Eq. 2)
+* ``coulomb.open_channel_functions``  Coulomb F, G and derivatives at r = a
+* ``coulomb.closed_channel_logderiv``  log-derivative of the decaying
+                                   Whittaker function at r = a
+* ``rmatrix.k_matrix``            matching of R to the asymptotic functions
+* ``rmatrix.t_matrix``            T = 2iK (1 - iK)^-1
+* ``rmatrix.collision_strengths`` Omega = sum (g/2) |T|^2 per target pair
+* ``rmatrix.sweep``               all of the above over an energy mesh
+
+It shares no code with the HIP path (``paper_1403_5524_amd``) and imports
+nothing from it; both sides receive the same seeded arrays from
+``paper_1403_5524_amd.workloads``, which holds no arithmetic of the method.
+"""
+from .coulomb import (coulomb_fg, open_channel_functions,
+                      closed_channel_logderiv)
+from .rmatrix import (r_matrix, channel_data, k_matrix, k_matrix_elimination,
+                      k_matrix_lambda, t_matrix, s_matrix, eigenphases, collision_strengths,
+                      omega_pair_index, sweep)
+
+__all__ = [
+    "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
+    "r_matrix", "channel_data", "k_matrix", "k_matrix_elimination",
+    "k_matrix_lambda",
+    "t_matrix", "s_matrix", "eigenphases", "collision_strengths",
+    "omega_pair_index", "sweep",
+]

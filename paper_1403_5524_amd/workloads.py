@@ -1,0 +1,165 @@
+"""Seeded synthetic inputs for the outer-region sweep.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic, so both the HIP path and the CPU oracle can be fed from
+it.  The paper's own workloads (B II, Ca II, Fe III; Sec. 3 Tables 1-2,
+Sec. 6 Table 3) need inner-region data that is not published; these seeded
+systems stand in for them with the same kind of shape: n channels, N_H poles
+per symmetry (N_H ~ 30-60 n), a fine uniform energy mesh (Sec. 3 asks for
+millions of points at meV resolution).
+
+Conventions (units Ry and a0):
+* "M energies uniform in [lo, hi]" is the midpoint grid
+  E_m = lo + (m + 1/2)(hi - lo)/M.
+* poles: i.i.d. uniform draws, sorted ascending; amplitudes w_ik ~ N(0, s^2);
+  thresholds ~ U[0, 2]; l ~ U{0..5}; numpy PCG64 with the stated seed, drawn
+  in the order poles, amplitudes, thresholds, l.
+* a threshold or pole closer than 1e-9 Ry to a mesh point is redrawn, so no
+  energy sits on a threshold or on a pole.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MIN_GAP = 1e-9
+
+
+def uniform_mesh(lo, hi, M):
+    """Midpoint grid of M energies on [lo, hi]."""
+    return lo + (np.arange(M, dtype=np.float64) + 0.5) * ((hi - lo) / M)
+
+
+def _mesh_gap(x, lo, hi, M):
+    h = (hi - lo) / M
+    idx = np.clip(np.rint((x - lo) / h - 0.5), 0, M - 1)
+    return np.abs(x - (lo + (idx + 0.5) * h))
+
+
+def _redraw_near_mesh(x, draw, mesh):
+    if mesh is None:
+        return x
+    lo, hi, M = mesh
+    bad = _mesh_gap(x, lo, hi, M) < MIN_GAP
+    while bad.any():
+        x[bad] = draw(int(bad.sum()))
+        bad = _mesh_gap(x, lo, hi, M) < MIN_GAP
+    return x
+
+
+@dataclass
+class Symmetry:
+    """One LS-pi / J-pi symmetry: what the inner region hands to the sweep."""
+    E_pole: np.ndarray          # [N_H] ascending
+    w: np.ndarray               # [n, N_H] row-major, w[i, k] = w_ik
+    e_thr: np.ndarray           # [n]
+    l: np.ndarray               # [n] int32
+    a: float = 20.0
+    z: float = 1.0
+    g: float = 1.0
+    target: np.ndarray = None   # [n] int32 or None (identity)
+
+    @property
+    def n(self):
+        return self.e_thr.size
+
+    @property
+    def n_poles(self):
+        return self.E_pole.size
+
+    def as_dict(self):
+        return {"E_pole": self.E_pole, "w": self.w, "a": self.a,
+                "e_thr": self.e_thr, "l": self.l, "z": self.z, "g": self.g,
+                "target": self.target}
+
+
+@dataclass
+class Workload:
+    name: str
+    syms: list
+    mesh: np.ndarray
+    n_target: int
+    mesh_spec: tuple = field(default=None)
+
+
+def random_symmetry(rng, n, n_poles, pole_lo, pole_hi, w_sigma=0.1, a=20.0,
+                    z=1.0, g=1.0, e_lo=0.0, e_hi=2.0, lmax=5, mesh=None,
+                    thresholds=None, target=None):
+    """Draw one symmetry.  ``thresholds``/``target`` override the per-channel
+    threshold draw with shared target levels (batched workloads)."""
+    def poles(k):
+        return rng.uniform(pole_lo, pole_hi, size=k)
+    E_pole = _redraw_near_mesh(poles(n_poles), poles, mesh)
+    E_pole.sort()
+    w = rng.normal(0.0, w_sigma, size=(n, n_poles))
+    if thresholds is None:
+        def thr(k):
+            return rng.uniform(e_lo, e_hi, size=k)
+        e_thr = _redraw_near_mesh(thr(n), thr, mesh)
+    else:
+        e_thr = np.asarray(thresholds, dtype=np.float64)[target]
+    l = rng.integers(0, lmax + 1, size=n).astype(np.int32)
+    return Symmetry(E_pole=E_pole, w=np.ascontiguousarray(w), e_thr=e_thr,
+                    l=l, a=a, z=z, g=g,
+                    target=None if target is None else
+                    np.asarray(target, dtype=np.int32))
+
+
+def single(n, n_poles, pole_lo, pole_hi, mesh_lo, mesh_hi, M, seed,
+           name="single", w_sigma=0.1):
+    rng = np.random.default_rng(seed)
+    spec = (mesh_lo, mesh_hi, M)
+    sym = random_symmetry(rng, n, n_poles, pole_lo, pole_hi, w_sigma=w_sigma,
+                          mesh=spec)
+    return Workload(name, [sym], uniform_mesh(*spec), n, spec)
+
+
+def config1():
+    """8 channels, 200 poles in [-2, 50], 2000 energies in [0, 10], seed 1."""
+    return single(8, 200, -2.0, 50.0, 0.0, 10.0, 2000, 1, "c1_n8_nh200_m2000")
+
+
+def config2(M=100000):
+    """200 channels, 8000 poles in [-5, 200], 1e5 energies in [0, 20], seed 2."""
+    return single(200, 8000, -5.0, 200.0, 0.0, 20.0, M, 2,
+                  "c2_n200_nh8000_m%d" % M)
+
+
+def config3(M=50000, n_sym=40, n_target=20, seed=3):
+    """40 symmetries, n_s log-uniform in [20, 600], N_H = 30 n_s, 20 shared
+    target levels with thresholds U[0, 2], one mesh of M energies in [0, 15],
+    g_s = 1 + (s mod 10)."""
+    rng = np.random.default_rng(seed)
+    spec = (0.0, 15.0, M)
+    ns = np.rint(np.exp(rng.uniform(np.log(20.0), np.log(600.0),
+                                    size=n_sym))).astype(int)
+
+    def thr(k):
+        return rng.uniform(0.0, 2.0, size=k)
+    levels = np.sort(_redraw_near_mesh(thr(n_target), thr, spec))
+    syms = []
+    for s, n in enumerate(ns):
+        target = rng.integers(0, n_target, size=n)
+        syms.append(random_symmetry(rng, int(n), 30 * int(n), -5.0, 200.0,
+                                    g=float(1 + s % 10), mesh=spec,
+                                    thresholds=levels, target=target))
+    return Workload("c3_batched_%dsym_m%d" % (n_sym, M), syms,
+                    uniform_mesh(*spec), n_target, spec)
+
+
+def config4(M=20000):
+    """1500 channels, 40000 poles in [-5, 200], 2e4 energies in [0, 20], seed 4."""
+    return single(1500, 40000, -5.0, 200.0, 0.0, 20.0, M, 4,
+                  "c4_n1500_nh40000_m%d" % M)
+
+
+def tiny(n=3, n_poles=12, M=40, seed=11, pole_lo=-2.0, pole_hi=30.0,
+         mesh_lo=0.0, mesh_hi=6.0):
+    """Small system for quick checks."""
+    return single(n, n_poles, pole_lo, pole_hi, mesh_lo, mesh_hi, M, seed,
+                  "tiny_n%d_nh%d_m%d" % (n, n_poles, M))
+
+
+def sample_indices(M, count, seed=0):
+    """Seeded sorted subset of mesh indices (for oracle comparisons)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(M, size=min(count, M), replace=False))
