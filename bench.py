@@ -1,0 +1,161 @@
+"""Benchmark: energy points per second of the outer-region sweep (K -> Omega)
+on the 200-channel, 8000-pole symmetry over a 1e5-point mesh in [0, 20] Ry,
+plus the max relative error of Omega against the FP64 CPU oracle.
+
+One step = one rm_sweep_energies call over the whole mesh (channel functions,
+pole sum, matching, K, T, Omega for every energy), inputs resident in HBM.
+Prints ONE JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # TFLOP/s dense MFMA
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+def note(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        info = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if info:
+            return int(info[0]["num_threads"])
+    except Exception:
+        pass
+    return os.cpu_count()
+
+
+def cpu_baseline(sym, mesh, count):
+    """The oracle as it stands, timed on this host on a bounded sample."""
+    import oracle
+    idx = np.linspace(0, mesh.size - 1, count).round().astype(int)
+    t0 = time.perf_counter()
+    oracle.sweep(sym.as_dict(), mesh[idx])
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "energies/s", "cores": blas_threads(),
+            "kind": "oracle",
+            "sample": "%d of %d mesh energies, evenly spaced (%.1f s)"
+                      % (count, mesh.size, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=sorted(PREC_CODE))
+    ap.add_argument("--M", type=int, default=100000)
+    ap.add_argument("--err-sample", type=int, default=32)
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: every energy is independent, so "
+              "more GPUs would split the mesh (see the sharding note in the "
+              "design document); no multi-GPU run is provided.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_1403_5524_amd import native, workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.config2(M=args.M)
+    sym = w.syms[0]
+    n, nh, M = sym.n, sym.n_poles, w.mesh.size
+    P = n * (n + 1) // 2
+    note("loading %s" % w.name)
+    h = native.load_symmetry(sym)
+    E = torch.as_tensor(w.mesh, dtype=torch.float64, device=dev)
+    omega = torch.empty((M, P), dtype=torch.float64, device=dev)
+    status = torch.empty((M,), dtype=torch.int32, device=dev)
+    opts = native.make_opts(prec=PREC_CODE[args.prec])
+
+    for i in range(args.warmup):
+        native.rm_sweep_energies([h], n, E, opts, omega, status)
+        torch.cuda.synchronize()
+        note("warmup %d done" % (i + 1))
+    native.rm_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        native.rm_sweep_energies([h], n, E, opts, omega, status)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    native.rm_profile(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    note("timed %d steps: %.2f ms/step" % (args.steps, ms))
+    stage = {k: native.rm_profile_query(k) for k in ("chanfn", "polesum",
+                                                     "match")}
+
+    # accuracy against the oracle on a seeded sample of the mesh
+    idx = workloads.sample_indices(M, args.err_sample, seed=7)
+    ref = oracle.sweep(sym.as_dict(), w.mesh[idx])
+    got = omega[torch.as_tensor(idx, device=dev)].cpu().numpy()
+    den = np.maximum(np.abs(ref["omega"]).max(axis=1), 1e-300)
+    err = float((np.abs(got - ref["omega"]).max(axis=1) / den).max())
+    st = status.cpu().numpy()
+    note("max rel err of Omega on %d sampled energies: %.3e" % (idx.size, err))
+
+    n_open = np.searchsorted(np.sort(sym.e_thr), w.mesh, side="left")
+    pairs = float((n_open * (n_open + 1) // 2).sum())
+    ps_ms, ps_launch = stage["polesum"]
+    flops_step = float(n) * (n + 1) * nh * M          # symmetric count
+    ps_launch_per_step = ps_launch / args.steps
+    achieved = (flops_step * args.steps) / (ps_ms * 1e-3) / 1e12 \
+        if ps_ms > 0 else None
+    roof = {"bound": "mfma", "kernel": "polesum_%s" % args.prec,
+            "achieved": achieved, "peak": PEAK[args.prec], "unit": "TFLOP/s",
+            "frac": (achieved / PEAK[args.prec]) if achieved else None,
+            "traffic": None,
+            "flops_per_launch": flops_step / ps_launch_per_step
+            if ps_launch_per_step else None,
+            "avg_launch_ms": ps_ms / ps_launch if ps_launch else None}
+    out = {
+        "metric": "energy points/sec (K->Omega) at n=200 ch, N_H=8000; "
+                  "max rel err of Omega vs FP64 oracle",
+        "value": M / (ms * 1e-3),
+        "unit": "energies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f64+%s" % args.prec,
+        "data": "synthetic (seeded poles/amplitudes, C2 shape)",
+        "config": {"workload": w.name, "n_chan": n, "n_poles": nh,
+                   "energies": M, "mesh_Ry": [0.0, 20.0],
+                   "precision": args.prec},
+        "max_rel_err_omega": err,
+        "err_sample": int(idx.size),
+        "omega_per_s": pairs / (ms * 1e-3),
+        "status_flagged": int((st != 0).sum()),
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stage.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        note("cpu baseline on %d energies" % args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(sym, w.mesh, args.cpu_sample)
+    h.free()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * rmatrix.h -- C ABI of the MI355X (gfx950) R-matrix outer-region sweep.
+ *
+ * The library evaluates, for every energy E of a mesh and every symmetry
+ * (LS-pi or J-pi partial wave) of a scattering system, the chain that the
+ * outer-region module of the parallel Breit-Pauli / DARC R-matrix codes runs
+ * (McLaughlin & Ballance, "Petascale computations for large-scale atomic and
+ * molecular collisions", Sec. 3 and Sec. 6):
+ *
+ *   R_ij(E) = (1/2a) sum_k w_ik w_jk / (E_k - E)        Sec. 6, Eq. 1-2
+ *   match R(E) at r = a to Coulomb functions F_l, G_l (open channels) and
+ *   decaying Whittaker functions (closed channels)  ->  K-matrix (open-open)
+ *   T = 2iK (1 - iK)^-1
+ *   Omega(t, t') += (g/2) sum_{i in t, j in t', open} |T_ij|^2
+ *
+ * Eq. 1 is printed as sum_k W_ik W_kj / (E - E_k) with no prefactor; the
+ * library uses the Bloch-operator normalisation above (Rydberg energies,
+ * Bohr radii, Bloch constant b = 0), which is -1/(2a) times the printed form.
+ *
+ * Units: energies in Rydberg, radii in Bohr.  All functions are host
+ * functions; device pointers must address memory of the current HIP device,
+ * and `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ * on `stream` and the call returns without synchronising, except where
+ * stated.  No function throws; each returns an rm_status code and, when it is
+ * not RM_OK, rm_last_error() describes the failure (thread-local).
+ *
+ * Argument validation happens before anything is enqueued: an RM_ERR_ARG
+ * return has touched no device memory.
+ */
+#ifndef RMATRIX_H
+#define RMATRIX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+enum rm_status {
+  RM_OK = 0,
+  RM_ERR_ARG = 1,      /* invalid argument; nothing enqueued                */
+  RM_ERR_NOMEM = 2,    /* device allocation failed                          */
+  RM_ERR_HIP = 3,      /* a HIP runtime call failed                         */
+  RM_ERR_NUMERIC = 4,  /* reserved: per-energy trouble goes to status[]     */
+  RM_ERR_STATE = 5     /* handle used on the wrong device or after rm_free  */
+};
+
+/* Arithmetic of the pole sum (Sec. 6, Eq. 1-2).  The matching and T steps
+ * are always FP64 unless rm_opts.solve_fp32 is set. */
+enum rm_precision {
+  RM_PREC_FP64 = 0,    /* FP64 MFMA over every pole                          */
+  RM_PREC_FP32 = 1,    /* FP32 MFMA, FP32 accumulation, far poles only;
+                          |E_k - E| < near_delta summed in FP64             */
+  RM_PREC_BF16X3 = 2   /* split-BF16 (hi*hi + hi*lo + lo*hi) MFMA, FP32
+                          accumulation, far poles only; near poles in FP64   */
+};
+
+/* Per-energy status bits (status[] of rm_sweep_energies / rm_kmatrix).
+ * A flagged energy still gets a value; NO_OPEN energies get Omega = 0. */
+#define RM_E_NO_OPEN        0x01  /* no channel open: K is 0x0, Omega = 0   */
+#define RM_E_SINGULAR       0x02  /* zero pivot in the matching solve       */
+#define RM_E_CF_NOCONV      0x04  /* a channel-function iteration hit its cap*/
+#define RM_E_NONFINITE      0x08  /* non-finite value in K or T             */
+#define RM_E_ON_THRESHOLD   0x10  /* E equals a channel threshold exactly   */
+#define RM_E_REFINE_NOCONV  0x20  /* FP32 solve: refinement did not converge*/
+
+typedef struct rm_sym *rm_sym_t;  /* one symmetry, device-resident, opaque */
+
+/* One symmetry as the inner region hands it over (all host pointers).
+ *   E_pole  [n_poles]          poles E_k, strictly ascending, finite
+ *   w       [n_chan*n_poles]   surface amplitudes, row-major: w[i*n_poles+k]
+ *   a       boundary radius (> 0)
+ *   e_thr   [n_chan]           channel thresholds e_i (finite)
+ *   l       [n_chan]           orbital angular momenta, 0 <= l <= 12
+ *   target  [n_chan] or NULL   target level of each channel (>= 0); NULL maps
+ *                              channel i to level i
+ *   z       residual charge seen by the scattered electron (>= 0)
+ *   g       statistical weight of the symmetry, e.g. 2J+1 (> 0)
+ * Validity domain of the channel functions: z >= 0 and 2 z a > l(l+1) for
+ * every channel (r = a lies beyond the centrifugal turning point at all
+ * energies); z = 0 requires l = 0 channels or energies with k a > sqrt(l(l+1)).
+ */
+typedef struct {
+  int32_t n_chan;
+  int32_t n_poles;
+  const double *E_pole;
+  const double *w;
+  double a;
+  const double *e_thr;
+  const int32_t *l;
+  const int32_t *target;
+  double z;
+  double g;
+} rm_poles_desc;
+
+/* Options; a zero-initialised struct selects the defaults. */
+typedef struct {
+  int32_t prec;          /* rm_precision                                   */
+  double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-3           */
+  int32_t solve_fp32;    /* 1: matching solved in FP32 with FP64 iterative
+                            refinement of the FP64 system                  */
+  int32_t refine_iters;  /* max refinement steps for solve_fp32; 0 -> 8    */
+  int32_t chunk;         /* energies per internal chunk; 0 -> automatic    */
+  uint32_t flags;        /* reserved, must be 0                            */
+} rm_opts;
+
+/* Load one symmetry (Sec. 3: the poles and amplitudes produced by the
+ * inner-region diagonalisation; Sec. 6 Eq. 2: W is the shared operand of
+ * every energy's product).  Copies every input to the current device
+ * (caller may free its arrays when the call returns; the call synchronises
+ * `stream`), sorts channels by threshold internally and stages W in the
+ * layouts the kernels read (FP64, FP32 and split BF16).
+ * Errors: RM_ERR_ARG (n_chan < 1, n_poles < 1, a <= 0, z < 0, g <= 0,
+ * non-ascending or non-finite poles, non-finite amplitudes or thresholds,
+ * l outside [0, 12], negative target), RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_load_poles(const rm_poles_desc *desc, rm_sym_t *out, void *stream);
+
+/* Release a handle (synchronises the device first).  NULL is accepted. */
+int rm_free(rm_sym_t sym);
+
+/* Channel count, pole count and number of target levels of a handle. */
+int rm_sym_info(rm_sym_t sym, int32_t *n_chan, int32_t *n_poles,
+                int32_t *n_target);
+
+/* The fused sweep: for each energy E[e] (device, [M]) and each of the n_sym
+ * symmetries, pole sum -> channel functions -> matching -> K -> T, summing
+ * (g/2)|T_ij|^2 over symmetries into omega (device,
+ * [M][n_target*(n_target+1)/2], FP64, overwritten).  Target pair (t, u),
+ * t <= u, sits at t*n_target - t(t-1)/2 + (u - t) of each energy's row.
+ * status (device [M] int32, or NULL) receives the OR of the RM_E_* bits.
+ * Every handle must have been loaded on the current device, and its target
+ * levels must be < n_target.  Energies need no ordering.
+ * Errors: RM_ERR_ARG, RM_ERR_STATE, RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
+                      const double *E, int64_t M, const rm_opts *opts,
+                      double *omega, int32_t *status, void *stream);
+
+/* K-matrix of one symmetry at m energies (device E [m]).
+ * K (device, [m][n][n] FP64, n = n_chan): the open-open block occupies the
+ * leading n_open[e] x n_open[e] rows/columns (row-major, leading dimension
+ * n), open channels in ascending input-channel order; other entries are 0.
+ * n_open (device [m] int32) receives the open-channel counts.
+ * R_opt (device [m][n][n] or NULL) receives R(E) in input-channel order.
+ * status (device [m] or NULL) receives RM_E_* bits. */
+int rm_kmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
+               double *K, int32_t *n_open, double *R_opt, int32_t *status,
+               void *stream);
+
+/* Collision strengths from given K-matrices (device, layout of rm_kmatrix):
+ * T = 2iK(1 - iK)^-1 and omega[e][pair(t,u)] += (g/2)|T_ij|^2 over open
+ * channels i of level t and j of level u (device omega [m][n_target*(
+ * n_target+1)/2], accumulated, not cleared).  n_open and E must be the ones
+ * rm_kmatrix used. */
+int rm_collision_strengths(rm_sym_t sym, const double *K,
+                           const int32_t *n_open, const double *E, int64_t m,
+                           int32_t n_target, double *omega, void *stream);
+
+/* Boundary R-matrix alone (Sec. 6, Eq. 1-2) at m energies: R (device,
+ * [m][n][n], input-channel order).  opts->prec selects the arithmetic. */
+int rm_rmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
+               double *R, void *stream);
+
+/* Channel functions at r = a, input-channel order: out (device [m][n][4]).
+ * Open channel (E > e_i): (s, c, a s', a c') with s = k^-1/2 F_l(eta, ka),
+ * c = k^-1/2 G_l, primes d/dr, eta = -z/k.  Closed channel: (e, a e', 0, 0),
+ * the decaying Whittaker function W_{z/phi, l+1/2}(2 phi r) and a times its
+ * r-derivative at r = a scaled to unit length.  status as above. */
+int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m,
+                         double *out, int32_t *status, void *stream);
+
+/* Stage timing (diagnostics).  rm_profile(1) clears the record and makes
+ * every later call of this process bracket each kernel launch with HIP
+ * events on the caller's stream; rm_profile(0) stops recording.
+ * rm_profile_query synchronises on the recorded events and returns, for
+ * stage 0 (channel functions), 1 (pole sum) or 2 (matching, K, T, Omega),
+ * the summed kernel time in milliseconds and the number of launches.
+ * Not thread-safe with concurrent sweeps while enabled. */
+int rm_profile(int32_t enable);
+int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches);
+
+/* Message for the last non-RM_OK return on this thread ("" if none). */
+const char *rm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMATRIX_H */

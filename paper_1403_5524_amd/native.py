@@ -1,0 +1,230 @@
+"""ctypes binding of librmatrix (include/rmatrix.h), same names as the C ABI.
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels.
+PyTorch supplies device memory and the current stream.  If the shared
+library is missing the import fails loudly; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librmatrix.so")
+
+RM_OK, RM_ERR_ARG, RM_ERR_NOMEM, RM_ERR_HIP, RM_ERR_NUMERIC, RM_ERR_STATE = \
+    range(6)
+RM_PREC_FP64, RM_PREC_FP32, RM_PREC_BF16X3 = 0, 1, 2
+RM_E_NO_OPEN = 0x01
+RM_E_SINGULAR = 0x02
+RM_E_CF_NOCONV = 0x04
+RM_E_NONFINITE = 0x08
+RM_E_ON_THRESHOLD = 0x10
+RM_E_REFINE_NOCONV = 0x20
+
+EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
+            "rm_kmatrix", "rm_collision_strengths", "rm_rmatrix",
+            "rm_channel_functions", "rm_profile", "rm_profile_query",
+            "rm_last_error")
+
+
+class RmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rmatrix error %d: %s" % (code, msg))
+        self.code = code
+
+
+class PolesDesc(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("n_poles", ctypes.c_int32),
+                ("E_pole", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("a", ctypes.c_double), ("e_thr", ctypes.c_void_p),
+                ("l", ctypes.c_void_p), ("target", ctypes.c_void_p),
+                ("z", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("near_delta", ctypes.c_double),
+                ("solve_fp32", ctypes.c_int32),
+                ("refine_iters", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librmatrix.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librmatrix.so not built: run "
+                              "python -c 'import __graft_entry__ as g; g.build()'")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.rm_load_poles.argtypes = [ctypes.POINTER(PolesDesc),
+                                    ctypes.POINTER(vp), vp]
+        L.rm_free.argtypes = [vp]
+        L.rm_sym_info.argtypes = [vp, vp, vp, vp]
+        L.rm_sweep_energies.argtypes = [vp, i32, i32, vp, i64,
+                                        ctypes.POINTER(Opts), vp, vp, vp]
+        L.rm_kmatrix.argtypes = [vp, vp, i64, ctypes.POINTER(Opts), vp, vp,
+                                 vp, vp, vp]
+        L.rm_collision_strengths.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp]
+        L.rm_rmatrix.argtypes = [vp, vp, i64, ctypes.POINTER(Opts), vp, vp]
+        L.rm_channel_functions.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.rm_profile.argtypes = [i32]
+        L.rm_profile_query.argtypes = [i32, vp, vp]
+        L.rm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name != "rm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != RM_OK:
+        raise RmError(code, lib().rm_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(prec=RM_PREC_FP64, near_delta=0.0, solve_fp32=0, refine_iters=0,
+              chunk=0):
+    return Opts(prec, near_delta, solve_fp32, refine_iters, chunk, 0)
+
+
+class Symmetry:
+    """A loaded symmetry (rm_sym_t); freed with rm_free when released."""
+
+    def __init__(self, handle, n, n_poles, n_target):
+        self.handle = handle
+        self.n = n
+        self.n_poles = n_poles
+        self.n_target = n_target
+
+    def free(self):
+        if self.handle:
+            lib().rm_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def rm_load_poles(E_pole, w, a, e_thr, l, z, g, target=None, stream=None):
+    """Host numpy arrays in, device-resident handle out."""
+    E_pole = np.ascontiguousarray(E_pole, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    e_thr = np.ascontiguousarray(e_thr, dtype=np.float64)
+    l = np.ascontiguousarray(l, dtype=np.int32)
+    tg = None if target is None else np.ascontiguousarray(target,
+                                                          dtype=np.int32)
+    n = int(e_thr.size)
+    nh = int(E_pole.size)
+    if w.size != n * nh:
+        raise RmError(RM_ERR_ARG, "w must hold n_chan*n_poles values")
+    d = PolesDesc(n, nh, E_pole.ctypes.data, w.ctypes.data, float(a),
+                  e_thr.ctypes.data, l.ctypes.data,
+                  None if tg is None else tg.ctypes.data, float(z), float(g))
+    h = ctypes.c_void_p()
+    st = _stream() if stream is None else stream
+    _check(lib().rm_load_poles(ctypes.byref(d), ctypes.byref(h), st))
+    nt = ctypes.c_int32()
+    _check(lib().rm_sym_info(h, None, None, ctypes.byref(nt)))
+    return Symmetry(h, n, nh, int(nt.value))
+
+
+def load_symmetry(sym):
+    """Load a workloads.Symmetry (or mapping with the same keys)."""
+    d = sym.as_dict() if hasattr(sym, "as_dict") else sym
+    return rm_load_poles(d["E_pole"], d["w"], d["a"], d["e_thr"], d["l"],
+                         d["z"], d["g"], d.get("target"))
+
+
+def rm_sweep_energies(syms, n_target, E, opts=None, omega=None, status=None):
+    """E: CUDA float64 tensor [M].  Returns (omega [M, P], status [M])."""
+    import torch
+    M = int(E.numel())
+    P = n_target * (n_target + 1) // 2
+    if omega is None:
+        omega = torch.empty((M, P), dtype=torch.float64, device=E.device)
+    if status is None:
+        status = torch.empty((M,), dtype=torch.int32, device=E.device)
+    arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
+    o = opts if opts is not None else make_opts()
+    _check(lib().rm_sweep_energies(arr, len(syms), n_target, _ptr(E), M,
+                                   ctypes.byref(o), _ptr(omega), _ptr(status),
+                                   _stream()))
+    return omega, status
+
+
+def rm_kmatrix(sym, E, opts=None, want_R=False):
+    """Returns (K [m, n, n], n_open [m], R [m, n, n] or None, status [m])."""
+    import torch
+    m, n = int(E.numel()), sym.n
+    K = torch.empty((m, n, n), dtype=torch.float64, device=E.device)
+    no = torch.empty((m,), dtype=torch.int32, device=E.device)
+    st = torch.empty((m,), dtype=torch.int32, device=E.device)
+    R = torch.empty((m, n, n), dtype=torch.float64, device=E.device) \
+        if want_R else None
+    o = opts if opts is not None else make_opts()
+    _check(lib().rm_kmatrix(sym.handle, _ptr(E), m, ctypes.byref(o), _ptr(K),
+                            _ptr(no), _ptr(R), _ptr(st), _stream()))
+    return K, no, R, st
+
+
+def rm_collision_strengths(sym, K, n_open, E, n_target, omega):
+    """Accumulates into omega [m, P] (device float64)."""
+    m = int(E.numel())
+    _check(lib().rm_collision_strengths(sym.handle, _ptr(K), _ptr(n_open),
+                                        _ptr(E), m, n_target, _ptr(omega),
+                                        _stream()))
+    return omega
+
+
+def rm_rmatrix(sym, E, opts=None):
+    import torch
+    m, n = int(E.numel()), sym.n
+    R = torch.empty((m, n, n), dtype=torch.float64, device=E.device)
+    o = opts if opts is not None else make_opts()
+    _check(lib().rm_rmatrix(sym.handle, _ptr(E), m, ctypes.byref(o), _ptr(R),
+                            _stream()))
+    return R
+
+
+def rm_channel_functions(sym, E):
+    """Returns (out [m, n, 4], status [m])."""
+    import torch
+    m, n = int(E.numel()), sym.n
+    out = torch.empty((m, n, 4), dtype=torch.float64, device=E.device)
+    st = torch.empty((m,), dtype=torch.int32, device=E.device)
+    _check(lib().rm_channel_functions(sym.handle, _ptr(E), m, _ptr(out),
+                                      _ptr(st), _stream()))
+    return out, st
+
+
+STAGES = {"chanfn": 0, "polesum": 1, "match": 2}
+
+
+def rm_profile(enable):
+    _check(lib().rm_profile(1 if enable else 0))
+
+
+def rm_profile_query(stage):
+    """(total_ms, launches) of a stage recorded since rm_profile(1)."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().rm_profile_query(STAGES.get(stage, stage), ctypes.byref(ms),
+                                  ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,91 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/rmatrix.h declares, and rejects invalid arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1403_5524_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rmatrix.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(rm_\w+)\(",
+                                 txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(native.LIB_PATH):
+        pytest.fail("librmatrix.so is not built (run __graft_entry__.build())")
+    return native.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "rm_sweep_energies" in names and len(names) >= 9
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(native.EXPORTED)
+
+
+def _desc(n=2, nh=3, **kw):
+    E = np.array(kw.pop("E", [0.5, 1.5, 4.0][:nh]), dtype=np.float64)
+    w = np.array(kw.pop("w", np.ones(n * nh)), dtype=np.float64)
+    e = np.array(kw.pop("e", [0.0, 0.3][:n]), dtype=np.float64)
+    l = np.array(kw.pop("l", [0, 1][:n]), dtype=np.int32)
+    keep = (E, w, e, l)
+    d = native.PolesDesc(kw.pop("n_chan", n), kw.pop("n_poles", nh),
+                         E.ctypes.data, w.ctypes.data, kw.pop("a", 20.0),
+                         e.ctypes.data, l.ctypes.data, None,
+                         kw.pop("z", 1.0), kw.pop("g", 1.0))
+    return d, keep
+
+
+@pytest.mark.parametrize("bad", [
+    {"n_chan": 0}, {"n_poles": 0}, {"a": 0.0}, {"a": -1.0}, {"z": -1.0},
+    {"g": 0.0}, {"E": [0.5, 0.5, 4.0]}, {"E": [0.5, float("nan"), 4.0]},
+    {"w": [1, 1, float("inf"), 1, 1, 1]}, {"l": [0, 13]}, {"l": [-1, 0]},
+    {"e": [0.0, float("nan")]},
+])
+def test_load_rejects_invalid(L, bad):
+    d, keep = _desc(**bad)
+    h = ctypes.c_void_p()
+    rc = L.rm_load_poles(ctypes.byref(d), ctypes.byref(h), None)
+    assert rc == native.RM_ERR_ARG
+    assert h.value is None
+    assert len(L.rm_last_error()) > 0
+
+
+def test_sweep_rejects_invalid(L):
+    o = native.make_opts()
+    assert L.rm_sweep_energies(None, 0, 1, None, 0, ctypes.byref(o), None,
+                               None, None) == native.RM_ERR_ARG
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(o), None,
+                               None, None) == native.RM_ERR_ARG
+    bad = native.make_opts(prec=9)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(bad), None,
+                               None, None) == native.RM_ERR_ARG
+    assert b"precision" in L.rm_last_error()
+    neg = native.make_opts(near_delta=-1.0)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(neg), None,
+                               None, None) == native.RM_ERR_ARG
+
+
+def test_null_handles_rejected(L):
+    o = native.make_opts()
+    assert L.rm_kmatrix(None, None, 0, ctypes.byref(o), None, None, None,
+                        None, None) == native.RM_ERR_ARG
+    assert L.rm_rmatrix(None, None, 0, ctypes.byref(o), None, None) == \
+        native.RM_ERR_ARG
+    assert L.rm_channel_functions(None, None, 0, None, None, None) == \
+        native.RM_ERR_ARG
+    assert L.rm_collision_strengths(None, None, None, None, 0, 1, None,
+                                    None) == native.RM_ERR_ARG
+    assert L.rm_free(None) == native.RM_OK

@@ -1,0 +1,244 @@
+"""HIP path vs the FP64 CPU oracle, through the C ABI (needs an MI355X).
+
+Tolerances: Omega of the FP64 path within 1e-6 normwise per energy (the
+target stated for the plain path); intermediate quantities are held to the
+tighter bounds their arithmetic allows (FP64 pole sum 1e-12, channel
+functions 1e-10, K 1e-8 relative to max(1, |K|)).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import (log, omega_normwise_err, oracle_channel_table,
+                         oracle_sweep_multi)
+from paper_1403_5524_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+OMEGA_TOL_FP64 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1403_5524_amd import native
+    native.lib()
+    return native
+
+
+@pytest.fixture(scope="module")
+def c1(nat):
+    w = wl.config1()
+    return w, nat.load_symmetry(w.syms[0])
+
+
+@pytest.fixture(scope="module")
+def c2(nat):
+    w = wl.config2()
+    return w, nat.load_symmetry(w.syms[0])
+
+
+def _dev(torch_dev, arr):
+    torch, dev = torch_dev
+    return torch.as_tensor(np.ascontiguousarray(arr), dtype=torch.float64,
+                           device=dev)
+
+
+# ---------------------------------------------------------------- a5
+
+def test_channel_functions_c1(torch_dev, nat, c1):
+    w, h = c1
+    sym = w.syms[0].as_dict()
+    E = w.mesh[::5]
+    log("chanfn c1 m=%d" % E.size)
+    out, st = nat.rm_channel_functions(h, _dev(torch_dev, E))
+    got = out.cpu().numpy()
+    ref, op = oracle_channel_table(sym, E)
+    scale = np.maximum(np.abs(ref).max(axis=2, keepdims=True), 1.0)
+    err = np.abs(got - ref) / scale
+    assert err.max() < 1e-10, err.max()
+    assert (st.cpu().numpy() == 0).all()
+
+
+def test_channel_functions_edge_energies(torch_dev, nat):
+    """Just above and below thresholds: large |eta| (CF2 needs ~4|eta| terms)
+    and weakly closed channels (kappa up to ~3e3, U-series branch)."""
+    s = wl.tiny(n=6, n_poles=20).syms[0]
+    E = []
+    for e in s.e_thr:
+        for d in (1e-3, 1e-5, 1e-7, -1e-2, -1e-4, -1e-7):
+            E.append(e + d)
+    E = np.array(E)
+    log("chanfn edges m=%d" % E.size)
+    h = nat.load_symmetry(s)
+    out, st = nat.rm_channel_functions(h, _dev(torch_dev, E))
+    got = out.cpu().numpy()
+    ref, op = oracle_channel_table(s.as_dict(), E)
+    scale = np.maximum(np.abs(ref).max(axis=2, keepdims=True), 1.0)
+    err = np.abs(got - ref) / scale
+    assert err.max() < 1e-7, err.max()
+
+
+# ---------------------------------------------------------------- a3/a4
+
+def test_rmatrix_fp64_c1(torch_dev, nat, c1):
+    w, h = c1
+    s = w.syms[0]
+    E = w.mesh[::10]
+    log("rmatrix c1 m=%d" % E.size)
+    R = nat.rm_rmatrix(h, _dev(torch_dev, E)).cpu().numpy()
+    Rr = oracle.r_matrix(s.E_pole, s.w, s.a, E)
+    err = np.abs(R - Rr).max(axis=(1, 2)) / np.abs(Rr).max(axis=(1, 2))
+    assert err.max() < 1e-12, err.max()
+
+
+def test_rmatrix_fp64_c2_sample(torch_dev, nat, c2):
+    w, h = c2
+    s = w.syms[0]
+    idx = wl.sample_indices(w.mesh.size, 24, seed=2)
+    E = w.mesh[idx]
+    log("rmatrix c2 m=%d" % E.size)
+    R = nat.rm_rmatrix(h, _dev(torch_dev, E)).cpu().numpy()
+    Rr = oracle.r_matrix(s.E_pole, s.w, s.a, E)
+    err = np.abs(R - Rr).max(axis=(1, 2)) / np.abs(Rr).max(axis=(1, 2))
+    assert err.max() < 1e-12, err.max()
+    assert np.abs(R - R.transpose(0, 2, 1)).max() == 0.0
+
+
+# ---------------------------------------------------------------- a6-a8
+
+def _k_compare(h, sym, E, nat, torch_dev, tol=1e-8):
+    K, no, R, st = nat.rm_kmatrix(h, _dev(torch_dev, E), want_R=True)
+    K, no = K.cpu().numpy(), no.cpu().numpy()
+    res = oracle.sweep(sym, E, keep=("K",))
+    worst = 0.0
+    for m_, (Kr, P) in enumerate(res["K"]):
+        assert no[m_] == P.size
+        if P.size == 0:
+            continue
+        Kg = K[m_, :P.size, :P.size]
+        sc = max(1.0, np.abs(Kr).max())
+        worst = max(worst, np.abs(Kg - Kr).max() / sc)
+        assert np.abs(K[m_, P.size:, :]).max(initial=0.0) == 0.0
+    assert worst < tol, worst
+    return worst
+
+
+def test_kmatrix_c1(torch_dev, nat, c1):
+    w, h = c1
+    E = w.mesh[::7]
+    log("kmatrix c1 m=%d" % E.size)
+    _k_compare(h, w.syms[0].as_dict(), E, nat, torch_dev)
+
+
+def test_kmatrix_c2_sample(torch_dev, nat, c2):
+    w, h = c2
+    idx = wl.sample_indices(w.mesh.size, 12, seed=3)
+    E = w.mesh[idx]
+    log("kmatrix c2 m=%d" % E.size)
+    _k_compare(h, w.syms[0].as_dict(), E, nat, torch_dev)
+
+
+# ---------------------------------------------------------------- a9 / sweep
+
+def test_sweep_c1_all_energies(torch_dev, nat, c1):
+    """Every energy of the 8-channel, 200-pole, 2000-energy system."""
+    w, h = c1
+    log("sweep c1 m=%d" % w.mesh.size)
+    om, st = nat.rm_sweep_energies([h], 8, _dev(torch_dev, w.mesh))
+    om, st = om.cpu().numpy(), st.cpu().numpy()
+    ref = oracle.sweep(w.syms[0].as_dict(), w.mesh)
+    err, _, _ = omega_normwise_err(om, ref["omega"])
+    log("c1 omega normwise err %.3e" % err)
+    assert err < OMEGA_TOL_FP64
+    assert np.array_equal(st, ref["status"])
+
+
+def test_sweep_c1_ragged_chunks(torch_dev, nat, c1):
+    """Chunk of 7 energies: several chunks and a ragged tail give the same
+    Omega bit for bit as the default chunking."""
+    w, h = c1
+    E = _dev(torch_dev, w.mesh[:101])
+    a, _ = nat.rm_sweep_energies([h], 8, E)
+    b, _ = nat.rm_sweep_energies([h], 8, E, opts=nat.make_opts(chunk=7))
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_sweep_c2_full_mesh_sampled(torch_dev, nat, c2):
+    """The benchmark workload at full size (200 channels, 8000 poles,
+    1e5 energies) in the launch configuration the benchmark times; sampled
+    energies are checked against the oracle one by one."""
+    torch, _ = torch_dev
+    w, h = c2
+    log("sweep c2 m=%d" % w.mesh.size)
+    om, st = nat.rm_sweep_energies([h], 200, _dev(torch_dev, w.mesh))
+    torch.cuda.synchronize()
+    idx = wl.sample_indices(w.mesh.size, 16, seed=4)
+    ref = oracle.sweep(w.syms[0].as_dict(), w.mesh[idx])
+    got = om[torch.as_tensor(idx, device=om.device)].cpu().numpy()
+    err, _, _ = omega_normwise_err(got, ref["omega"])
+    log("c2 omega normwise err %.3e" % err)
+    assert err < OMEGA_TOL_FP64
+    assert np.array_equal(st.cpu().numpy()[idx], ref["status"])
+    assert torch.isfinite(om).all()
+
+
+def test_collision_strengths_from_k(torch_dev, nat, c1):
+    """rm_collision_strengths(rm_kmatrix(E)) equals the fused sweep."""
+    torch, _ = torch_dev
+    w, h = c1
+    E = _dev(torch_dev, w.mesh[::13])
+    K, no, _, _ = nat.rm_kmatrix(h, E)
+    om = torch.zeros((E.numel(), 36), dtype=torch.float64, device=E.device)
+    nat.rm_collision_strengths(h, K, no, E, 8, om)
+    ref, _ = nat.rm_sweep_energies([h], 8, E)
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref.cpu().numpy())
+    assert err < 1e-10
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_no_open_channel_and_single_channel(torch_dev, nat):
+    s = wl.tiny(n=1, n_poles=1, M=5).syms[0]
+    d = s.as_dict()
+    d["e_thr"] = np.array([1.0])
+    h = nat.load_symmetry(d)
+    E = np.array([0.2, 0.9, 1.5, 3.0, 7.0])
+    om, st = nat.rm_sweep_energies([h], 1, _dev(torch_dev, E))
+    om, st = om.cpu().numpy(), st.cpu().numpy()
+    ref = oracle.sweep(d, E)
+    assert (st[:2] & nat.RM_E_NO_OPEN).all() and (om[:2] == 0).all()
+    err, _, _ = omega_normwise_err(om[2:], ref["omega"][2:])
+    assert err < 1e-10
+
+
+def test_empty_mesh_is_noop(torch_dev, nat, c1):
+    torch, dev = torch_dev
+    w, h = c1
+    E = torch.empty((0,), dtype=torch.float64, device=dev)
+    om, st = nat.rm_sweep_energies([h], 8, E)
+    assert om.shape == (0, 36)
+
+
+def test_batched_symmetries_c3_sample(torch_dev, nat):
+    """All 40 symmetries of uneven size summed into 20 shared target levels,
+    on sampled energies of the 5e4-point mesh."""
+    w = wl.config3()
+    hs = [nat.load_symmetry(s) for s in w.syms]
+    idx = wl.sample_indices(w.mesh.size, 6, seed=5)
+    E = w.mesh[idx]
+    log("sweep c3 m=%d syms=%d" % (E.size, len(hs)))
+    om, st = nat.rm_sweep_energies(hs, w.n_target, _dev(torch_dev, E))
+    ref, rst = oracle_sweep_multi(w.syms, E, w.n_target)
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref)
+    log("c3 omega normwise err %.3e" % err)
+    assert err < OMEGA_TOL_FP64
+    assert np.array_equal(st.cpu().numpy(), rst)
