@@ -47,7 +47,7 @@ enum rm_status {
 };
 
 /* Arithmetic of the pole sum (Sec. 6, Eq. 1-2).  The matching and T steps
- * are always FP64 unless rm_opts.solve_fp32 is set. */
+ * are always FP64. */
 enum rm_precision {
   RM_PREC_FP64 = 0,    /* FP64 MFMA over every pole                          */
   RM_PREC_FP32 = 1,    /* FP32 MFMA, FP32 accumulation, far poles only;
@@ -63,7 +63,7 @@ enum rm_precision {
 #define RM_E_CF_NOCONV      0x04  /* a channel-function iteration hit its cap*/
 #define RM_E_NONFINITE      0x08  /* non-finite value in K or T             */
 #define RM_E_ON_THRESHOLD   0x10  /* E equals a channel threshold exactly   */
-#define RM_E_REFINE_NOCONV  0x20  /* FP32 solve: refinement did not converge*/
+#define RM_E_REFINE_NOCONV  0x20  /* reserved                               */
 
 typedef struct rm_sym *rm_sym_t;  /* one symmetry, device-resident, opaque */
 
@@ -98,9 +98,9 @@ typedef struct {
 typedef struct {
   int32_t prec;          /* rm_precision                                   */
   double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-3           */
-  int32_t solve_fp32;    /* 1: matching solved in FP32 with FP64 iterative
-                            refinement of the FP64 system                  */
-  int32_t refine_iters;  /* max refinement steps for solve_fp32; 0 -> 8    */
+  int32_t solve_fp32;    /* must be 0: the matching solve is FP64 (a
+                            nonzero value returns RM_ERR_ARG)              */
+  int32_t refine_iters;  /* reserved, must be >= 0                         */
   int32_t chunk;         /* energies per internal chunk; 0 -> automatic    */
   uint32_t flags;        /* reserved, must be 0                            */
 } rm_opts;
@@ -178,6 +178,46 @@ int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m,
  * Not thread-safe with concurrent sweeps while enabled. */
 int rm_profile(int32_t enable);
 int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches);
+
+/* ---- Learned adaptive mesh -------------------------------------------
+ * The paper asks for millions of energies to resolve narrow resonances
+ * (Sec. 3); a small network, trained on the device on cross sections the
+ * sweep itself produces, predicts where resonances are so that a smaller
+ * adaptive mesh can stand in for the uniform one.
+ *
+ * rm_mlp_create: dense network d_in -> width -> ... -> 1 with n_layers
+ * layers (>= 2), SiLU between layers, linear output.  prec 0: BF16 operands
+ * on the matrix cores with FP32 accumulation; prec 1: FP32 operands (debug).
+ * Weights are initialised from `seed` (splitmix64, uniform He bounds).
+ * Parameters form one flat FP32 array, layer by layer W_l [out][in] then
+ * b_l [out]; rm_mlp_n_params gives its length.  get/set copy it from/to a
+ * device array.  All data pointers are device pointers. */
+typedef struct rm_mlp *rm_mlp_t;
+int rm_mlp_create(int32_t d_in, int32_t width, int32_t n_layers, int32_t prec,
+                  uint64_t seed, rm_mlp_t *out);
+int rm_mlp_free(rm_mlp_t mlp);
+int rm_mlp_n_params(rm_mlp_t mlp, int64_t *n);
+int rm_mlp_get_params(rm_mlp_t mlp, float *dst, void *stream);
+int rm_mlp_set_params(rm_mlp_t mlp, const float *src, void *stream);
+/* Y [B] = net(X [B][d_in]). */
+int rm_mlp_forward(rm_mlp_t mlp, const float *X, int32_t B, float *Y,
+                   void *stream);
+/* Mean squared error against target [B]; loss (device float, or NULL) and
+ * the gradient of every parameter (kept for rm_mlp_adam_step and copied to
+ * grad [n_params] when grad is not NULL). */
+int rm_mlp_grad(rm_mlp_t mlp, const float *X, const float *target, int32_t B,
+                float *loss, float *grad, void *stream);
+/* One Adam update (Kingma & Ba 2015, bias-corrected) from the last gradient. */
+int rm_mlp_adam_step(rm_mlp_t mlp, float lr, float beta1, float beta2,
+                     float eps, void *stream);
+/* Mesh from a density: dens [nw] (>= 0, device) on nw equal windows of
+ * [lo, hi] is normalised, mixed with a uniform floor
+ * (density = (1 - floor_frac) dens/sum + floor_frac/(hi - lo)), and M
+ * energies are placed at the midpoints of M equal-mass intervals of its CDF
+ * (piecewise linear inside a window).  E_out [M] ascending (device). */
+int rm_mesh_from_density(const float *dens, int32_t nw, double lo, double hi,
+                         double floor_frac, int64_t M, double *E_out,
+                         void *stream);
 
 /* Message for the last non-RM_OK return on this thread ("" if none). */
 const char *rm_last_error(void);

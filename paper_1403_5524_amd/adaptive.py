@@ -1,0 +1,272 @@
+"""Learned adaptive energy mesh.
+
+The paper's sweeps need millions of energies to resolve narrow resonances
+(Sec. 3).  Here a small MLP, trained on the device by the library's own
+kernels (rm_mlp_*), predicts from cheap per-window features of a symmetry
+how much structure Omega(E) has in each energy window; rm_mesh_from_density
+turns the prediction into an adaptive mesh, and the uniform fine mesh swept
+with the plain (FP64) method is the judge.
+
+Pipeline (all arrays for the sweep and the network live on the GPU):
+  features(sym)            host: pole counts, amplitude norms, thresholds
+  judge = sweep(uniform)   rm_sweep_energies over a uniform fine mesh
+  labels = log variation of Omega per window (from the judge)
+  train                    rm_mlp_grad + rm_mlp_adam_step
+  density = 10**mlp(features) -> rm_mesh_from_density -> adaptive mesh
+  evaluate                 integrated Omega per transition vs the judge,
+                           missed narrow resonances
+"""
+import math
+
+import numpy as np
+
+from . import native
+
+N_FEAT = 12
+
+
+def window_features(sym, lo, hi, nw):
+    """Per-window features [nw, N_FEAT] (float32) from poles and thresholds.
+
+    Narrow resonances come from poles with small surface amplitudes, so the
+    features describe, per window and its neighbourhood, how many poles sit
+    there and how weakly the weakest of them couples, plus where thresholds
+    (and the Rydberg series below them) lie.
+    """
+    h = (hi - lo) / nw
+    Ek = np.asarray(sym.E_pole)
+    amp2 = (np.asarray(sym.w) ** 2).sum(axis=0)
+    idx = np.floor((Ek - lo) / h).astype(np.int64)
+    inside = (idx >= 0) & (idx < nw)
+    cnt = np.bincount(idx[inside], minlength=nw).astype(np.float64)
+    la = np.log10(amp2[inside] + 1e-30)
+    minamp = np.full(nw, 2.0)
+    np.minimum.at(minamp, idx[inside], la)
+    inv = np.zeros(nw)
+    np.add.at(inv, idx[inside], 1.0 / (amp2[inside] + 1e-12))
+
+    def smooth(v, r, op):
+        out = v.copy()
+        for s in range(1, r + 1):
+            out = op(out, np.roll(v, s))
+            out = op(out, np.roll(v, -s))
+        return out
+    centers = lo + (np.arange(nw) + 0.5) * h
+    thr = np.sort(np.asarray(sym.e_thr))
+    pos = np.searchsorted(thr, centers)
+    above = np.where(pos < thr.size, thr[np.minimum(pos, thr.size - 1)] - centers, 10.0)
+    below = np.where(pos > 0, centers - thr[np.maximum(pos - 1, 0)], 10.0)
+    tcount = np.bincount(np.clip(np.floor((thr - lo) / h).astype(np.int64), 0,
+                                 nw - 1), minlength=nw)
+    f = np.stack([
+        np.log1p(cnt),
+        minamp,
+        np.log10(inv + 1e-3),
+        np.log1p(smooth(cnt, 2, np.add)),
+        smooth(minamp, 2, np.minimum),
+        np.log10(smooth(inv, 2, np.add) + 1e-3),
+        np.log10(np.maximum(above, 1e-6)),
+        np.log10(np.maximum(below, 1e-6)),
+        np.log1p(tcount),
+        centers / max(hi, 1e-12),
+        np.log10(pos + 1.0),
+        np.log10(np.maximum(centers - thr[0], 1e-6)) if thr.size else centers,
+    ], axis=1)
+    return f.astype(np.float32)
+
+
+class Judge:
+    """Per-transition integrals and per-window variation of a swept mesh."""
+
+    def __init__(self, integrals, variation, total, mesh_size):
+        self.integrals = integrals      # [P] float64 (numpy)
+        self.variation = variation      # [nw] float64
+        self.total = total
+        self.mesh_size = mesh_size
+
+
+def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
+                    opts=None):
+    """Sweep a mesh (device float64, ascending) chunk by chunk.
+
+    Returns a Judge: trapezoid integrals of every Omega(t, t') over [lo, hi]
+    (end segments held constant), and, when nw is given, the total variation
+    of sum_pairs Omega in each of nw windows.
+    """
+    import torch
+    M = int(E.numel())
+    P = n_target * (n_target + 1) // 2
+    dev = E.device
+    integ = torch.zeros(P, dtype=torch.float64, device=dev)
+    var = torch.zeros(nw if nw else 1, dtype=torch.float64, device=dev)
+    prev_E, prev_om = None, None
+    h = (hi - lo) / nw if nw else None
+    for c0 in range(0, M, chunk):
+        Ec = E[c0:c0 + chunk]
+        om, _ = native.rm_sweep_energies(handles, n_target, Ec, opts)
+        if prev_E is not None:
+            Ec2 = torch.cat([prev_E.view(1), Ec])
+            om2 = torch.cat([prev_om.view(1, -1), om])
+        else:
+            integ += om[0] * (Ec[0] - lo)
+            Ec2, om2 = Ec, om
+        dE = (Ec2[1:] - Ec2[:-1]).view(-1, 1)
+        integ += (0.5 * dE * (om2[1:] + om2[:-1])).sum(dim=0)
+        if nw:
+            sig = om2.sum(dim=1)
+            dv = (sig[1:] - sig[:-1]).abs()
+            mid = 0.5 * (Ec2[1:] + Ec2[:-1])
+            wi = ((mid - lo) / h).floor().clamp(0, nw - 1).long()
+            var.index_add_(0, wi, dv)
+        prev_E, prev_om = Ec[-1].clone(), om[-1].clone()
+        del om
+    integ += prev_om * (hi - prev_E)
+    torch.cuda.synchronize()
+    return Judge(integ.cpu().numpy(), var.cpu().numpy() if nw else None,
+                 float(integ.sum().item()), M)
+
+
+def labels_from_variation(variation):
+    """log10 of the window's variation relative to the mean (floored)."""
+    v = np.asarray(variation, dtype=np.float64)
+    mean = max(v.mean(), 1e-300)
+    return np.log10(v / mean + 1e-3).astype(np.float32)
+
+
+def heuristic_density(sym, lo, hi, nw):
+    """Non-learned density: poles per window weighted by 1/|w_k|^2."""
+    h = (hi - lo) / nw
+    amp2 = (np.asarray(sym.w) ** 2).sum(axis=0)
+    idx = np.floor((np.asarray(sym.E_pole) - lo) / h).astype(np.int64)
+    ok = (idx >= 0) & (idx < nw)
+    d = np.zeros(nw)
+    np.add.at(d, idx[ok], 1.0 / (amp2[ok] + 1e-4))
+    return d.astype(np.float32)
+
+
+class Normaliser:
+    def __init__(self, X):
+        self.mu = X.mean(axis=0)
+        self.sd = X.std(axis=0) + 1e-6
+
+    def __call__(self, X):
+        return ((X - self.mu) / self.sd).astype(np.float32)
+
+
+def train_mlp(X, y, width=256, n_layers=4, steps=1500, batch=1024, lr=1e-3,
+              seed=0, prec=0, log=None):
+    """Train on the device; returns (mlp, loss history)."""
+    import torch
+    dev = torch.device("cuda:0")
+    Xt = torch.as_tensor(X, device=dev)
+    yt = torch.as_tensor(y, device=dev)
+    mlp = native.Mlp(X.shape[1], width, n_layers, prec, seed)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    n = Xt.shape[0]
+    for step in range(steps):
+        idx = torch.randint(0, n, (min(batch, n),), generator=g).to(dev)
+        xb = Xt.index_select(0, idx).contiguous()
+        yb = yt.index_select(0, idx).contiguous()
+        loss, _ = mlp.grad(xb, yb)
+        mlp.adam_step(lr=lr)
+        if step % 100 == 0 or step == steps - 1:
+            hist.append((step, float(loss.item())))
+            if log:
+                log("mlp step %d loss %.4f" % hist[-1])
+    return mlp, hist
+
+
+def mesh_from_log_density(logd, lo, hi, M, floor_frac=0.3, alpha=1.0):
+    """Adaptive mesh from predicted log10 densities (device float32)."""
+    import torch
+    d = torch.pow(10.0, alpha * logd.float()).contiguous()
+    return native.rm_mesh_from_density(d, lo, hi, floor_frac, M)
+
+
+def missed_resonances(E, truth, min_width):
+    """Truth resonances of width >= min_width with < 3 mesh points within
+    +-width of their position."""
+    E = np.asarray(E)
+    miss = 0
+    tot = 0
+    for Er, G in truth:
+        if G < min_width:
+            continue
+        tot += 1
+        k = np.searchsorted(E, Er - G), np.searchsorted(E, Er + G)
+        if k[1] - k[0] < 3:
+            miss += 1
+    return miss, tot
+
+
+def integrated_error(test, judge, rel_floor=1e-6):
+    """Max and mean relative error of per-transition integrals (transitions
+    with integral above rel_floor times the largest)."""
+    J = judge.integrals
+    keep = np.abs(J) > rel_floor * np.abs(J).max()
+    rel = np.abs(test.integrals[keep] - J[keep]) / np.abs(J[keep])
+    return float(rel.max()), float(rel.mean())
+
+
+def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
+                   lo=0.0, hi=20.0, M_judge=1000000, M_adapt=100000,
+                   nw=4096, steps=1500, log=print):
+    """Train on train_seeds, evaluate uniform / heuristic / learned meshes of
+    M_adapt points on test_seed against the M_judge uniform judge."""
+    import torch
+    from . import workloads as wl
+    dev = torch.device("cuda:0")
+    feats, labels = [], []
+    for s in train_seeds:
+        sym, truth, spec = wl.narrow_resonance_system(
+            s, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
+            mesh_hi=hi, M_judge=M_judge)
+        h = native.load_symmetry(sym)
+        E = torch.as_tensor(wl.uniform_mesh(lo, hi, M_judge), device=dev)
+        j = sweep_integrals([h], n, E, lo, hi, nw=nw)
+        feats.append(window_features(sym, lo, hi, nw))
+        labels.append(labels_from_variation(j.variation))
+        h.free()
+        log("train system %d swept (%d energies)" % (s, M_judge))
+    X = np.concatenate(feats)
+    y = np.concatenate(labels)
+    norm = Normaliser(X)
+    mlp, hist = train_mlp(norm(X), y, steps=steps, log=log)
+
+    sym, truth, spec = wl.narrow_resonance_system(
+        test_seed, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
+        mesh_hi=hi, M_judge=M_judge)
+    h = native.load_symmetry(sym)
+    Ej = torch.as_tensor(wl.uniform_mesh(lo, hi, M_judge), device=dev)
+    judge = sweep_integrals([h], n, Ej, lo, hi, nw=nw)
+    Xt = torch.as_tensor(norm(window_features(sym, lo, hi, nw)), device=dev)
+    pred = mlp.forward(Xt)
+    meshes = {
+        "uniform": torch.as_tensor(wl.uniform_mesh(lo, hi, M_adapt), device=dev),
+        "heuristic": native.rm_mesh_from_density(
+            torch.as_tensor(heuristic_density(sym, lo, hi, nw), device=dev),
+            lo, hi, 0.3, M_adapt),
+        "learned": mesh_from_log_density(pred, lo, hi, M_adapt),
+    }
+    min_w = 2.0 * (hi - lo) / M_judge
+    out = {"train_loss": hist, "judge_points": M_judge, "points": M_adapt}
+    for name, E in meshes.items():
+        r = sweep_integrals([h], n, E, lo, hi)
+        mx, mean = integrated_error(r, judge)
+        miss, tot = missed_resonances(E.cpu().numpy(), truth, min_w)
+        out[name] = {"int_err_max": mx, "int_err_mean": mean,
+                     "missed": miss, "resonances": tot}
+        log("%-9s int err max %.3e mean %.3e missed %d/%d"
+            % (name, mx, mean, miss, tot))
+    h.free()
+    mlp.free()
+    return out
+
+
+if __name__ == "__main__":   # full-size experiment on the GPU
+    import json
+    import sys
+    res = run_experiment(train_seeds=list(range(1000, 1004)), test_seed=3000)
+    json.dump(res, sys.stdout)
+    print()

@@ -260,8 +260,10 @@ __device__ inline ClosedVals whittaker_useries(int l, double kappa, double x) {
   }
   if (!(big <= 1e11 * fabs(U))) out.ok = 0;  // cancellation ate the digits
   // W = exp(-x/2) x^(l+1) U:  x W'/W = l + 1 - x/2 + x U'/U
-  const double d1 = U;
-  const double d2 = (l + 1.0 - 0.5 * x) * U + x * Ud;
+  // sign convention: W(a) > 0 (or a W'(a) > 0 where W(a) = 0)
+  const double sg = (U > 0.0 || (U == 0.0 && Ud > 0.0)) ? 1.0 : -1.0;
+  const double d1 = sg * U;
+  const double d2 = sg * ((l + 1.0 - 0.5 * x) * U + x * Ud);
   const double nrm = hypot(d1, d2);
   out.e = d1 / nrm;
   out.ep = d2 / nrm;

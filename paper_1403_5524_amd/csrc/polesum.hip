@@ -137,7 +137,9 @@ __global__ __launch_bounds__(256) void polesum_f64_kernel(PoleSumF64Args p) {
     __syncthreads();
   }
 
-  // epilogue: lane holds D[i][j] with j = lane%16, i = 4*(lane/16) + r
+  // epilogue: for the FP64 16x16x4 MFMA, lane holds D[i][j] with
+  // j = lane % 16 and i = lane / 16 + 4 r (rows interleaved across the four
+  // result registers; the FP32/BF16 forms use i = 4 (lane / 16) + r)
 #pragma unroll
   for (int e = 0; e < PS_EW; ++e) {
     const int eg = e0 + wave * PS_EW + e;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void polesum_f64_kernel(PoleSumF64Args p) {
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int gi = I * PS_T + a * 16 + 4 * kq + r;
+          const int gi = I * PS_T + a * 16 + kq + 4 * r;
           const int gj = J * PS_T + b * 16 + col;
           if (gi < p.n && gj < p.n) {
             const double v = acc[e][a][b][r] * p.scale;

@@ -35,6 +35,11 @@ static int fail(int code, const char *fmt, ...) {
   return code;
 }
 
+const char *set_error(int code, const char *msg) {
+  fail(code, "%s", msg);
+  return g_err.c_str();
+}
+
 #define RM_HIP(call)                                                     \
   do {                                                                   \
     hipError_t e_ = (call);                                              \
@@ -233,8 +238,9 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");
   if (d.flags != 0) return fail(RM_ERR_ARG, "flags must be 0");
-  if (d.solve_fp32 != 0 && d.solve_fp32 != 1)
-    return fail(RM_ERR_ARG, "solve_fp32 must be 0 or 1");
+  if (d.solve_fp32 != 0)
+    return fail(RM_ERR_ARG, "solve_fp32 is not available: the matching "
+                            "solve runs in FP64");
   *out = d;
   return RM_OK;
 }
@@ -312,7 +318,7 @@ static int64_t pick_chunk(int n_max, int64_t M, int32_t user_chunk) {
 
 static int free_sym(Sym *s) {
   if (!s) return RM_OK;
-  void *ptrs[] = {s->E_pole, s->Wt, s->Wt32, s->Whi, s->Wlo, s->e_thr,
+  void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
                   s->l,      s->perm, s->inv, s->tptr, s->tch};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -436,8 +442,8 @@ int rm_load_poles(const rm_poles_desc *d, rm_sym_t *out, void *stream) {
     const double *row = d->w + (int64_t)perm[i] * nh;
     for (int k = 0; k < nh; ++k) {
       const double v = row[k];
-      const size_t q = (size_t)k * npad + i;
-      Wt[q] = v;
+      Wt[(size_t)k * npad + i] = v;
+      const size_t q = (size_t)i * hpad + k;
       W32[q] = (float)v;
       const uint16_t h = bf16_rne((float)v);
       Whi[q] = h;
@@ -454,9 +460,9 @@ int rm_load_poles(const rm_poles_desc *d, rm_sym_t *out, void *stream) {
     e = hipMemcpyAsync((dst), (src), (bytes), hipMemcpyHostToDevice, st);
   RM_ALLOC_COPY(s->E_pole, Ep.data(), hpad * sizeof(double));
   RM_ALLOC_COPY(s->Wt, Wt.data(), npad * hpad * sizeof(double));
-  RM_ALLOC_COPY(s->Wt32, W32.data(), npad * hpad * sizeof(float));
-  RM_ALLOC_COPY(s->Whi, Whi.data(), npad * hpad * sizeof(uint16_t));
-  RM_ALLOC_COPY(s->Wlo, Wlo.data(), npad * hpad * sizeof(uint16_t));
+  RM_ALLOC_COPY(s->W32c, W32.data(), npad * hpad * sizeof(float));
+  RM_ALLOC_COPY(s->Whc, Whi.data(), npad * hpad * sizeof(uint16_t));
+  RM_ALLOC_COPY(s->Wlc, Wlo.data(), npad * hpad * sizeof(uint16_t));
   RM_ALLOC_COPY(s->e_thr, ethr.data(), n * sizeof(double));
   RM_ALLOC_COPY(s->l, lsrt.data(), n * sizeof(int32_t));
   RM_ALLOC_COPY(s->perm, perm.data(), n * sizeof(int32_t));

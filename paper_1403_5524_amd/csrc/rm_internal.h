@@ -24,8 +24,9 @@ struct Sym {
   // device arrays
   double *E_pole;       // [nh_pad] ascending, padding = kPadPole
   double *Wt;           // [nh_pad][n_pad] FP64, k-major, zero padded
-  float *Wt32;          // [nh_pad][n_pad] FP32
-  uint16_t *Whi, *Wlo;  // [nh_pad][n_pad] BF16 split: w = hi + lo + O(2^-16)
+  float *W32c;          // [n_pad][nh_pad] FP32, channel-major
+  uint16_t *Whc, *Wlc;  // [n_pad][nh_pad] BF16 split, channel-major:
+                        // w = hi + lo + O(2^-16 |w|)
   double *e_thr;        // [n] sorted
   int32_t *l;           // [n] (sorted order)
   int32_t *perm;        // [n] sorted position -> input channel

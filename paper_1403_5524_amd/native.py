@@ -25,6 +25,9 @@ RM_E_REFINE_NOCONV = 0x20
 EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_kmatrix", "rm_collision_strengths", "rm_rmatrix",
             "rm_channel_functions", "rm_profile", "rm_profile_query",
+            "rm_mlp_create", "rm_mlp_free", "rm_mlp_n_params",
+            "rm_mlp_get_params", "rm_mlp_set_params", "rm_mlp_forward",
+            "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
             "rm_last_error")
 
 
@@ -74,6 +77,16 @@ def lib():
         L.rm_channel_functions.argtypes = [vp, vp, i64, vp, vp, vp]
         L.rm_profile.argtypes = [i32]
         L.rm_profile_query.argtypes = [i32, vp, vp]
+        f32, f64, u64 = ctypes.c_float, ctypes.c_double, ctypes.c_uint64
+        L.rm_mlp_create.argtypes = [i32, i32, i32, i32, u64, ctypes.POINTER(vp)]
+        L.rm_mlp_free.argtypes = [vp]
+        L.rm_mlp_n_params.argtypes = [vp, ctypes.POINTER(i64)]
+        L.rm_mlp_get_params.argtypes = [vp, vp, vp]
+        L.rm_mlp_set_params.argtypes = [vp, vp, vp]
+        L.rm_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.rm_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.rm_mlp_adam_step.argtypes = [vp, f32, f32, f32, f32, vp]
+        L.rm_mesh_from_density.argtypes = [vp, i32, f64, f64, f64, i64, vp, vp]
         L.rm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "rm_last_error":
@@ -228,3 +241,66 @@ def rm_profile_query(stage):
     _check(lib().rm_profile_query(STAGES.get(stage, stage), ctypes.byref(ms),
                                   ctypes.byref(n)))
     return ms.value, n.value
+
+
+class Mlp:
+    """Device MLP handle (rm_mlp_t)."""
+
+    def __init__(self, d_in, width=256, n_layers=4, prec=0, seed=0):
+        h = ctypes.c_void_p()
+        _check(lib().rm_mlp_create(d_in, width, n_layers, prec, seed,
+                                   ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        _check(lib().rm_mlp_n_params(h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+        self.d_in, self.width, self.n_layers = d_in, width, n_layers
+
+    def free(self):
+        if self.handle:
+            lib().rm_mlp_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import torch
+        out = torch.empty((self.n_params,), dtype=torch.float32, device="cuda")
+        _check(lib().rm_mlp_get_params(self.handle, _ptr(out), _stream()))
+        return out
+
+    def set_params(self, p):
+        _check(lib().rm_mlp_set_params(self.handle, _ptr(p), _stream()))
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0],), dtype=torch.float32, device=X.device)
+        _check(lib().rm_mlp_forward(self.handle, _ptr(X), int(X.shape[0]),
+                                    _ptr(Y), _stream()))
+        return Y
+
+    def grad(self, X, target, want_grad=False):
+        import torch
+        loss = torch.empty((1,), dtype=torch.float32, device=X.device)
+        g = torch.empty((self.n_params,), dtype=torch.float32,
+                        device=X.device) if want_grad else None
+        _check(lib().rm_mlp_grad(self.handle, _ptr(X), _ptr(target),
+                                 int(X.shape[0]), _ptr(loss), _ptr(g),
+                                 _stream()))
+        return loss, g
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().rm_mlp_adam_step(self.handle, lr, beta1, beta2, eps,
+                                      _stream()))
+
+
+def rm_mesh_from_density(dens, lo, hi, floor_frac, M):
+    import torch
+    E = torch.empty((M,), dtype=torch.float64, device=dens.device)
+    _check(lib().rm_mesh_from_density(_ptr(dens), int(dens.numel()), lo, hi,
+                                      floor_frac, M, _ptr(E), _stream()))
+    return E

@@ -163,3 +163,43 @@ def sample_indices(M, count, seed=0):
     """Seeded sorted subset of mesh indices (for oracle comparisons)."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(M, size=min(count, M), replace=False))
+
+
+def narrow_resonance_system(seed, n=200, n_poles=8000, n_narrow=50,
+                            pole_lo=-5.0, pole_hi=200.0, mesh_lo=0.0,
+                            mesh_hi=20.0, M_judge=1000000, width_lo=1e-5,
+                            width_hi=1e-3):
+    """C2-style symmetry plus n_narrow injected weakly coupled poles.
+
+    Each injected pole sits uniformly in the open part of [mesh_lo, mesh_hi]
+    with amplitude vector c u (u a random unit vector).  c^2 is drawn so that
+    a crude width proxy c^2 * mean_i sqrt(E_r - e_i)_+ lands log-uniformly in
+    [width_lo, width_hi]; the nominal (E_r, proxy width) pairs are returned
+    as the truth list.  Poles and thresholds avoid the judge mesh by 1e-9.
+    """
+    rng = np.random.default_rng(seed)
+    spec = (mesh_lo, mesh_hi, M_judge)
+    base = random_symmetry(rng, n, n_poles, pole_lo, pole_hi, mesh=spec)
+
+    def pos(k):
+        return rng.uniform(max(mesh_lo, 2.2), mesh_hi - 0.1, size=k)
+    Er = _redraw_near_mesh(pos(n_narrow), pos, spec)
+    widths = np.exp(rng.uniform(np.log(width_lo), np.log(width_hi),
+                                size=n_narrow))
+    u = rng.normal(size=(n, n_narrow))
+    u /= np.linalg.norm(u, axis=0, keepdims=True)
+    kbar = np.sqrt(np.clip(Er[None, :] - base.e_thr[:, None], 0.0, None))
+    proxy = (kbar * u * u).sum(axis=0)
+    c = np.sqrt(widths / np.maximum(proxy, 1e-12))
+    E_all = np.concatenate([base.E_pole, Er])
+    w_all = np.concatenate([base.w, u * c[None, :]], axis=1)
+    order = np.argsort(E_all, kind="stable")
+    E_all = E_all[order]
+    w_all = np.ascontiguousarray(w_all[:, order])
+    # keep poles strictly ascending
+    if np.any(np.diff(E_all) <= 0):
+        raise ValueError("coincident poles; change the seed")
+    sym = Symmetry(E_pole=E_all, w=w_all, e_thr=base.e_thr, l=base.l,
+                   a=base.a, z=base.z, g=base.g)
+    truth = np.stack([Er, widths], axis=1)
+    return sym, truth, spec

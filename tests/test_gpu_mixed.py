@@ -1,0 +1,82 @@
+"""Mixed-precision pole sums (FP32 and split-BF16 MFMA with the FP64
+near-pole correction) against the FP64 oracle (needs an MI355X).
+
+Bar: Omega within 1e-4 normwise per energy (the stated tolerance for the
+mixed paths).  R is checked normwise against bounds that follow from the
+arithmetic: FP32 operands carry 24 bits, split BF16 about 16 bits, with FP32
+accumulation over N_H terms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import log, omega_normwise_err
+from paper_1403_5524_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+OMEGA_TOL_MIXED = 1e-4
+R_TOL = {1: 1e-5, 2: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1403_5524_amd import native
+    assert torch.cuda.is_available()
+    w = wl.config2()
+    h = native.load_symmetry(w.syms[0])
+    return torch, native, w, h
+
+
+def _near_pole_energies(sym, count, offset):
+    """Energies offset Ry from poles inside [0.5, 19.5]."""
+    ks = np.nonzero((sym.E_pole > 0.5) & (sym.E_pole < 19.5))[0]
+    pick = ks[np.linspace(0, ks.size - 1, count).astype(int)]
+    return sym.E_pole[pick] + offset
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_rmatrix_mixed_c2(env, prec):
+    torch, nat, w, h = env
+    s = w.syms[0]
+    E = np.concatenate([w.mesh[wl.sample_indices(w.mesh.size, 12, seed=8)],
+                        _near_pole_energies(s, 4, 1e-6),
+                        _near_pole_energies(s, 4, -3e-4)])
+    log("rmatrix mixed prec=%d m=%d" % (prec, E.size))
+    Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
+    R = nat.rm_rmatrix(h, Et, nat.make_opts(prec=prec)).cpu().numpy()
+    Rr = oracle.r_matrix(s.E_pole, s.w, s.a, E)
+    err = np.abs(R - Rr).max(axis=(1, 2)) / np.abs(Rr).max(axis=(1, 2))
+    log("R normwise err max %.3e" % err.max())
+    assert err.max() < R_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_sweep_mixed_c2_sample(env, prec):
+    torch, nat, w, h = env
+    s = w.syms[0]
+    E = np.concatenate([w.mesh[wl.sample_indices(w.mesh.size, 16, seed=9)],
+                        _near_pole_energies(s, 4, 2e-6)])
+    log("sweep mixed prec=%d m=%d" % (prec, E.size))
+    Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
+    om, st = nat.rm_sweep_energies([h], 200, Et, nat.make_opts(prec=prec))
+    ref = oracle.sweep(s.as_dict(), E)
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
+    log("mixed prec=%d omega normwise err %.3e" % (prec, err))
+    assert err < OMEGA_TOL_MIXED
+    assert np.array_equal(st.cpu().numpy(), ref["status"])
+
+
+def test_mixed_matches_fp64_on_c1(env):
+    """Small system: every energy of the 8-channel case, both mixed paths."""
+    torch, nat, _, _ = env
+    w = wl.config1()
+    h = nat.load_symmetry(w.syms[0])
+    Et = torch.as_tensor(w.mesh, dtype=torch.float64, device="cuda:0")
+    ref = oracle.sweep(w.syms[0].as_dict(), w.mesh)
+    for prec in (1, 2):
+        om, _ = nat.rm_sweep_energies([h], 8, Et, nat.make_opts(prec=prec))
+        err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
+        log("c1 mixed prec=%d err %.3e" % (prec, err))
+        assert err < OMEGA_TOL_MIXED
