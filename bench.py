@@ -61,6 +61,11 @@ def main():
     ap.add_argument("--err-sample", type=int, default=32)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2 is the headline workload; c3 (40 symmetries) "
+                         "and c4 (1500 channels) time a prefix of their mesh")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of a hipGraph-captured plan")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -75,47 +80,74 @@ def main():
     from paper_1403_5524_amd import native, workloads
 
     dev = torch.device("cuda:0")
-    w = workloads.config2(M=args.M)
+    if args.workload == "c2":
+        w = workloads.config2(M=args.M)
+    elif args.workload == "c3":
+        w = workloads.config3()
+        w.mesh = w.mesh[:: max(1, w.mesh.size // args.M)][:args.M]
+    else:
+        w = workloads.config4()
+        w.mesh = w.mesh[:: max(1, w.mesh.size // args.M)][:args.M]
     sym = w.syms[0]
-    n, nh, M = sym.n, sym.n_poles, w.mesh.size
-    P = n * (n + 1) // 2
-    note("loading %s" % w.name)
-    h = native.load_symmetry(sym)
+    n_t = w.n_target
+    nh = sym.n_poles
+    n = sym.n
+    M = w.mesh.size
+    P = n_t * (n_t + 1) // 2
+    note("loading %s (%d energies timed)" % (w.name, M))
+    hs = [native.load_symmetry(s) for s in w.syms]
     E = torch.as_tensor(w.mesh, dtype=torch.float64, device=dev)
     omega = torch.empty((M, P), dtype=torch.float64, device=dev)
     status = torch.empty((M,), dtype=torch.int32, device=dev)
     opts = native.make_opts(prec=PREC_CODE[args.prec])
 
     for i in range(args.warmup):
-        native.rm_sweep_energies([h], n, E, opts, omega, status)
+        native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
         torch.cuda.synchronize()
         note("warmup %d done" % (i + 1))
     native.rm_profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        native.rm_sweep_energies([h], n, E, opts, omega, status)
+        native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     native.rm_profile(False)
     ms = (t1 - t0) * 1e3 / args.steps
     note("timed %d steps: %.2f ms/step" % (args.steps, ms))
-    stage = {k: native.rm_profile_query(k) for k in ("chanfn", "polesum",
-                                                     "match")}
+    stage = {k: native.rm_profile_query(k) for k in ("polesum", "match")}
+    graph_ms = None
+    if args.graph:
+        plan = native.Plan(hs, n_t, E, opts, omega, status)
+        plan.execute()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.execute()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - g0) * 1e3 / args.steps
+        plan.free()
+        note("graph replays: %.2f ms/step" % graph_ms)
 
     # accuracy against the oracle on a seeded sample of the mesh
     idx = workloads.sample_indices(M, args.err_sample, seed=7)
-    ref = oracle.sweep(sym.as_dict(), w.mesh[idx])
+    ref = None
+    for s in w.syms:
+        r = oracle.sweep(s.as_dict(), w.mesh[idx], n_target=n_t)["omega"]
+        ref = r if ref is None else ref + r
     got = omega[torch.as_tensor(idx, device=dev)].cpu().numpy()
-    den = np.maximum(np.abs(ref["omega"]).max(axis=1), 1e-300)
-    err = float((np.abs(got - ref["omega"]).max(axis=1) / den).max())
+    den = np.maximum(np.abs(ref).max(axis=1), 1e-300)
+    err = float((np.abs(got - ref).max(axis=1) / den).max())
     st = status.cpu().numpy()
     note("max rel err of Omega on %d sampled energies: %.3e" % (idx.size, err))
 
-    n_open = np.searchsorted(np.sort(sym.e_thr), w.mesh, side="left")
-    pairs = float((n_open * (n_open + 1) // 2).sum())
+    pairs = 0.0
+    flops_step = 0.0
+    for s in w.syms:
+        n_open = np.searchsorted(np.sort(s.e_thr), w.mesh, side="left")
+        pairs += float((n_open * (n_open + 1) // 2).sum())
+        flops_step += float(s.n) * (s.n + 1) * s.n_poles * M   # symmetric
     ps_ms, ps_launch = stage["polesum"]
-    flops_step = float(n) * (n + 1) * nh * M          # symmetric count
     ps_launch_per_step = ps_launch / args.steps
     achieved = (flops_step * args.steps) / (ps_ms * 1e-3) / 1e12 \
         if ps_ms > 0 else None
@@ -140,20 +172,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else "f64+%s" % args.prec,
         "data": "synthetic (seeded poles/amplitudes, C2 shape)",
-        "config": {"workload": w.name, "n_chan": n, "n_poles": nh,
-                   "energies": M, "mesh_Ry": [0.0, 20.0],
+        "config": {"workload": w.name, "n_sym": len(w.syms), "n_chan": n,
+                   "n_poles": nh, "energies": M,
+                   "mesh_Ry": [float(w.mesh_spec[0]), float(w.mesh_spec[1])],
                    "precision": args.prec},
         "max_rel_err_omega": err,
         "err_sample": int(idx.size),
         "omega_per_s": pairs / (ms * 1e-3),
         "status_flagged": int((st != 0).sum()),
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stage.items()},
+        "graph_ms_per_step": graph_ms,
+        "graph_value": (M / (graph_ms * 1e-3)) if graph_ms else None,
         "roofline": roof,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)
         out["cpu_baseline"] = cpu_baseline(sym, w.mesh, args.cpu_sample)
-    h.free()
+    for h in hs:
+        h.free()
     print(json.dumps(out), flush=True)
 
 

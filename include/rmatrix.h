@@ -102,8 +102,13 @@ typedef struct {
                             nonzero value returns RM_ERR_ARG)              */
   int32_t refine_iters;  /* reserved, must be >= 0                         */
   int32_t chunk;         /* energies per internal chunk; 0 -> automatic    */
-  uint32_t flags;        /* reserved, must be 0                            */
+  uint32_t flags;        /* RM_FLAG_* bits                                 */
 } rm_opts;
+
+/* rm_opts.flags: time the pole-sum tile variants on the first plan of each
+ * (channels, poles, precision) and keep the fastest (in memory, and in the
+ * file named by the environment variable RM_TUNE_CACHE when set). */
+#define RM_FLAG_AUTOTUNE 0x1u
 
 /* Load one symmetry (Sec. 3: the poles and amplitudes produced by the
  * inner-region diagonalisation; Sec. 6 Eq. 2: W is the shared operand of
@@ -135,6 +140,28 @@ int rm_sym_info(rm_sym_t sym, int32_t *n_chan, int32_t *n_poles,
 int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
                       const double *E, int64_t M, const rm_opts *opts,
                       double *omega, int32_t *status, void *stream);
+
+/* Captured sweep.  rm_plan_create validates like rm_sweep_energies, orders
+ * the symmetries by cost, sizes the chunks and the workspace (owned by the
+ * plan), builds the grouped pole-sum work tables (largest symmetries first),
+ * and records the whole sweep -- per chunk one grouped pole-sum launch per
+ * tile variant and one persistent matching launch covering every symmetry
+ * and energy of the chunk -- into a hipGraph bound to E, omega and status.
+ * rm_plan_execute replays it on `stream` (the caller may change the contents
+ * of E between replays, not the pointers).  Replays of one plan must not
+ * overlap.  rm_plan_create synchronises `stream` (autotuning and table
+ * uploads); rm_plan_free synchronises the device.
+ * rm_plan_info: energies per chunk, chunk count and the tile variant chosen
+ * for each symmetry in kernel order (largest first). */
+typedef struct rm_plan *rm_plan_t;
+int rm_plan_create(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
+                   const double *E, int64_t M, const rm_opts *opts,
+                   double *omega, int32_t *status, void *stream,
+                   rm_plan_t *out);
+int rm_plan_execute(rm_plan_t plan, void *stream);
+int rm_plan_info(rm_plan_t plan, int64_t *chunk, int32_t *n_chunks,
+                 int32_t *variants, int32_t n_variants);
+int rm_plan_free(rm_plan_t plan);
 
 /* K-matrix of one symmetry at m energies (device E [m]).
  * K (device, [m][n][n] FP64, n = n_chan): the open-open block occupies the
@@ -173,8 +200,9 @@ int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m,
  * every later call of this process bracket each kernel launch with HIP
  * events on the caller's stream; rm_profile(0) stops recording.
  * rm_profile_query synchronises on the recorded events and returns, for
- * stage 0 (channel functions), 1 (pole sum) or 2 (matching, K, T, Omega),
- * the summed kernel time in milliseconds and the number of launches.
+ * stage 1 (pole sum), 2 (channel functions, matching, K, T, Omega) or 3
+ * (rm_plan_execute graph replays), the summed time in milliseconds and the
+ * number of launches (stage 0 is kept for compatibility and stays empty).
  * Not thread-safe with concurrent sweeps while enabled. */
 int rm_profile(int32_t enable);
 int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches);

@@ -14,12 +14,18 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <vector>
 
 #include "chanfn.h"
 #include "rm_internal.h"
+
+struct rm_sym : public rmx::Sym {};
 
 namespace rmx {
 
@@ -304,16 +310,415 @@ static void clear_recs() {
   g_recs.clear();
 }
 
-// Workspace doubles per energy: [M | B] (n x 2n) and K (n x n).
+static int free_sym(Sym *s);
+
+// ---------------------------------------------------------------- plans
+//
+// A plan fixes the symmetries (ordered by cost, largest first), the chunk
+// length, the workspace layout and the pole-sum work-item tables, so that
+// the whole sweep is a fixed sequence of launches: per chunk one grouped
+// pole-sum launch per tile variant and one persistent matching launch.
+
 static int64_t work_doubles(int n) { return (int64_t)3 * n * n; }
 
-static int64_t pick_chunk(int n_max, int64_t M, int32_t user_chunk) {
-  if (user_chunk > 0) return std::min<int64_t>(user_chunk, M);
-  const double budget = 8.0e9;  // bytes of matching workspace per chunk
-  const double per = 8.0 * (double)work_doubles(n_max) + 64.0 * n_max;
-  int64_t c = (int64_t)(budget / per);
-  c = std::max<int64_t>(64, std::min<int64_t>(c, 4096));
-  return std::min<int64_t>(c, M);
+struct Plan {
+  int device = -1;
+  std::vector<const Sym *> syms;   // kernel order (cost descending)
+  int n_target = 0;
+  rm_opts o{};
+  int64_t M = 0, C = 0;            // energies, chunk length
+  int64_t work_estride = 0, chan_estride = 0;
+  std::vector<int> variant;        // per symmetry (kernel order)
+  // device tables
+  SymDev *d_syms = nullptr;
+  int64_t *d_work_off = nullptr, *d_chan_off = nullptr;
+  // item tables: [variant slot][0 full chunk / 1 tail chunk]
+  struct ItemSet {
+    int variant;
+    PsItem *d_items[2] = {nullptr, nullptr};
+    int n_items[2] = {0, 0};
+  };
+  std::vector<ItemSet> sets;
+  int64_t tail = 0;                // length of the last chunk
+  int n_chunks = 0;
+  // workspace
+  double *work = nullptr;
+  ChanSlot *chan = nullptr;
+  int *counters = nullptr;         // one per chunk (match kernel)
+  int match_grid = 0;
+  bool owns_async = false;         // workspace from hipMallocAsync
+  hipStream_t alloc_stream = nullptr;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  // bound arguments
+  const double *E = nullptr;
+  double *omega = nullptr;
+  int32_t *status = nullptr;
+  // rm_kmatrix-style extras (single symmetry)
+  double *K_out = nullptr;
+  int32_t *n_open_out = nullptr;
+  double *R_out = nullptr;
+  int do_t = 1;
+};
+
+static void plan_free_device(Plan &p) {
+  if (p.exec) (void)hipGraphExecDestroy(p.exec);
+  if (p.graph) (void)hipGraphDestroy(p.graph);
+  if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
+  p.exec = nullptr;
+  p.graph = nullptr;
+  p.cap_stream = nullptr;
+  for (auto &set : p.sets)
+    for (int t = 0; t < 2; ++t)
+      if (set.d_items[t]) (void)hipFree(set.d_items[t]);
+  p.sets.clear();
+  void *tabs[] = {p.d_syms, p.d_work_off, p.d_chan_off};
+  for (void *q : tabs)
+    if (q) (void)hipFree(q);
+  p.d_syms = nullptr;
+  p.d_work_off = p.d_chan_off = nullptr;
+  void *ws[] = {p.work, p.chan, p.counters};
+  for (void *q : ws) {
+    if (!q) continue;
+    if (p.owns_async)
+      (void)hipFreeAsync(q, p.alloc_stream);
+    else
+      (void)hipFree(q);
+  }
+  p.work = nullptr;
+  p.chan = nullptr;
+  p.counters = nullptr;
+}
+
+// ---- autotuner: fastest mixed tile variant per (n, N_H, precision)
+
+struct TuneKey {
+  int n, nh, prec;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(n, nh, prec) < std::tie(o.n, o.nh, o.prec);
+  }
+};
+static std::map<TuneKey, int> g_tuned;
+static std::mutex g_tune_mu;
+static bool g_tune_loaded = false;
+
+static const char *tune_path() { return std::getenv("RM_TUNE_CACHE"); }
+
+static void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = tune_path();
+  if (!path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  int n, nh, prec, v;
+  while (std::fscanf(f, "%d %d %d %d", &n, &nh, &prec, &v) == 4)
+    if (v >= PS_MX_J16_E8 && v <= PS_MX_J16_E4) g_tuned[{n, nh, prec}] = v;
+  std::fclose(f);
+}
+
+static void tune_store() {
+  const char *path = tune_path();
+  if (!path) return;
+  FILE *f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto &kv : g_tuned)
+    std::fprintf(f, "%d %d %d %d\n", kv.first.n, kv.first.nh, kv.first.prec,
+                 kv.second);
+  std::fclose(f);
+}
+
+static int default_variant(int prec) {
+  return prec == RM_PREC_FP64 ? PS_F64_T32_E16 : PS_MX_J16_E8;
+}
+
+static void build_items(const Plan &p, int variant, int64_t m,
+                        std::vector<PsItem> &out);
+
+// Time every mixed variant on up to 512 energies of E (device) and keep the
+// fastest.  Synchronises `st`.
+static int tune_sym(const Sym &s, int prec, double delta, const double *E,
+                    int64_t m, hipStream_t st, int *chosen) {
+  const int64_t mt = std::min<int64_t>(m, 512);
+  const int64_t nn = (int64_t)s.n * s.n;
+  double *R = nullptr;
+  SymDev *dsym = nullptr;
+  int64_t *doff = nullptr;
+  PsItem *ditems = nullptr;
+  hipEvent_t b = nullptr, e = nullptr;
+  int best = PS_MX_J16_E8;
+  float best_ms = 1e30f;
+  hipError_t err = hipMalloc(&R, (size_t)(mt * nn) * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dsym, sizeof(SymDev));
+  if (err == hipSuccess) err = hipMalloc(&doff, sizeof(int64_t));
+  const SymDev sd = s.dev();
+  const int64_t zero = 0;
+  if (err == hipSuccess) err = hipMemcpy(dsym, &sd, sizeof sd, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(doff, &zero, sizeof zero, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipEventCreate(&b);
+  if (err == hipSuccess) err = hipEventCreate(&e);
+  for (int v = PS_MX_J16_E8; v <= PS_MX_J16_E4 && err == hipSuccess; ++v) {
+    std::vector<std::pair<int, int>> tiles;
+    ps_tiles(s, v, tiles);
+    const int eg = ps_energy_group(v);
+    std::vector<PsItem> items;
+    for (auto &t : tiles)
+      for (int g = 0; g < (mt + eg - 1) / eg; ++g) items.push_back({0, t.first, t.second, g});
+    if (ditems) (void)hipFree(ditems);
+    ditems = nullptr;
+    err = hipMalloc(&ditems, items.size() * sizeof(PsItem));
+    if (err == hipSuccess)
+      err = hipMemcpy(ditems, items.data(), items.size() * sizeof(PsItem), hipMemcpyHostToDevice);
+    PsLaunch L{};
+    L.syms = dsym;
+    L.items = ditems;
+    L.n_items = (int)items.size();
+    L.E = E;
+    L.m = (int)mt;
+    L.out = PsOut{R, nn, doff, 1};
+    L.prec = prec;
+    L.delta = delta;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+      err = hipEventRecord(b, st);
+      if (err == hipSuccess) err = launch_polesum(L, v, st);
+      if (err == hipSuccess) err = hipEventRecord(e, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, b, e);
+      if (rep > 0) ms_min = std::min(ms_min, ms);  // first run warms caches
+    }
+    if (err == hipSuccess && ms_min < best_ms) {
+      best_ms = ms_min;
+      best = v;
+    }
+  }
+  if (ditems) (void)hipFree(ditems);
+  if (R) (void)hipFree(R);
+  if (dsym) (void)hipFree(dsym);
+  if (doff) (void)hipFree(doff);
+  if (b) (void)hipEventDestroy(b);
+  if (e) (void)hipEventDestroy(e);
+  if (err != hipSuccess)
+    return fail(RM_ERR_HIP, "autotune: %s", hipGetErrorString(err));
+  *chosen = best;
+  return RM_OK;
+}
+
+static int pick_variant(const Sym &s, const rm_opts &o, const double *E,
+                        int64_t M, hipStream_t st, int *v) {
+  if (o.prec == RM_PREC_FP64) {
+    *v = PS_F64_T32_E16;
+    return RM_OK;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load();
+  auto it = g_tuned.find({s.n, s.nh, o.prec});
+  if (it != g_tuned.end()) {
+    *v = it->second;
+    return RM_OK;
+  }
+  if (!(o.flags & RM_FLAG_AUTOTUNE) || M <= 0) {
+    *v = default_variant(o.prec);
+    return RM_OK;
+  }
+  int rc = tune_sym(s, o.prec, o.near_delta, E, M, st, v);
+  if (rc) return rc;
+  g_tuned[{s.n, s.nh, o.prec}] = *v;
+  tune_store();
+  return RM_OK;
+}
+
+static void build_items(const Plan &p, int variant, int64_t m,
+                        std::vector<PsItem> &out) {
+  out.clear();
+  const int eg = ps_energy_group(variant);
+  const int ngrp = (int)((m + eg - 1) / eg);
+  std::vector<std::pair<int, int>> tiles;
+  for (size_t q = 0; q < p.syms.size(); ++q) {
+    if (p.variant[q] != variant) continue;
+    ps_tiles(*p.syms[q], variant, tiles);
+    for (auto &t : tiles)
+      for (int g = 0; g < ngrp; ++g) out.push_back({(int)q, t.first, t.second, g});
+  }
+}
+
+static int match_grid_size() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+  }
+  return cus * 4;
+}
+
+// Build a plan: orders symmetries, allocates tables and workspace.
+// async: workspace from the stream-ordered allocator on st (eager calls).
+static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
+                      const double *E, int64_t M, const rm_opts &o,
+                      hipStream_t st, bool async, double ws_budget) {
+  p.o = o;
+  p.n_target = n_target;
+  p.M = M;
+  std::vector<const Sym *> v;
+  for (int q = 0; q < n_sym; ++q) v.push_back(syms[q]);
+  std::stable_sort(v.begin(), v.end(), [](const Sym *x, const Sym *y) {
+    const double cx = (double)x->n * x->n * x->nh + 4.0 * x->n * x->n * x->n;
+    const double cy = (double)y->n * y->n * y->nh + 4.0 * y->n * y->n * y->n;
+    return cx > cy;
+  });
+  p.syms = v;
+  p.device = v[0]->device;
+  std::vector<SymDev> sd;
+  std::vector<int64_t> woff, coff;
+  int64_t wacc = 0, cacc = 0;
+  for (const Sym *s : v) {
+    sd.push_back(s->dev());
+    woff.push_back(wacc);
+    coff.push_back(cacc);
+    wacc += work_doubles(s->n);
+    cacc += s->n;
+  }
+  p.work_estride = wacc;
+  p.chan_estride = cacc;
+  int64_t C = o.chunk > 0 ? o.chunk
+                          : (int64_t)(ws_budget / (8.0 * wacc + 32.0 * cacc + 64.0));
+  C = std::max<int64_t>(1, std::min<int64_t>(C, 4096));
+  if (o.chunk <= 0) C = std::max<int64_t>(std::min<int64_t>(64, M), C);
+  C = std::min<int64_t>(C, std::max<int64_t>(M, 1));
+  p.C = C;
+  p.n_chunks = (int)((M + C - 1) / C);
+  p.tail = M - (int64_t)(p.n_chunks - 1) * C;
+  p.variant.resize(v.size());
+  for (size_t q = 0; q < v.size(); ++q) {
+    int rc = pick_variant(*v[q], o, E, M, st, &p.variant[q]);
+    if (rc) return rc;
+  }
+  hipError_t e = hipMalloc(&p.d_syms, sd.size() * sizeof(SymDev));
+  if (e == hipSuccess) e = hipMalloc(&p.d_work_off, woff.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&p.d_chan_off, coff.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemcpy(p.d_syms, sd.data(), sd.size() * sizeof(SymDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p.d_work_off, woff.data(), woff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p.d_chan_off, coff.data(), coff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  std::vector<int> vars(p.variant.begin(), p.variant.end());
+  std::sort(vars.begin(), vars.end());
+  vars.erase(std::unique(vars.begin(), vars.end()), vars.end());
+  for (int var : vars) {
+    if (e != hipSuccess) break;
+    Plan::ItemSet set;
+    set.variant = var;
+    for (int t = 0; t < 2; ++t) {
+      const int64_t m = (t == 0) ? C : p.tail;
+      std::vector<PsItem> items;
+      build_items(p, var, m, items);
+      set.n_items[t] = (int)items.size();
+      if (items.empty()) continue;
+      e = hipMalloc(&set.d_items[t], items.size() * sizeof(PsItem));
+      if (e == hipSuccess)
+        e = hipMemcpy(set.d_items[t], items.data(), items.size() * sizeof(PsItem), hipMemcpyHostToDevice);
+    }
+    p.sets.push_back(set);
+  }
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
+                "plan tables: %s", hipGetErrorString(e));
+  const size_t wbytes = (size_t)(C * wacc) * sizeof(double);
+  const size_t cbytes = (size_t)(C * cacc) * sizeof(ChanSlot);
+  const size_t kbytes = (size_t)std::max(1, p.n_chunks) * sizeof(int);
+  p.owns_async = async;
+  p.alloc_stream = st;
+  if (async) {
+    e = hipMallocAsync((void **)&p.work, wbytes, st);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&p.chan, cbytes, st);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&p.counters, kbytes, st);
+  } else {
+    e = hipMalloc((void **)&p.work, wbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&p.chan, cbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&p.counters, kbytes);
+  }
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
+                "workspace of %zu bytes: %s", wbytes + cbytes,
+                hipGetErrorString(e));
+  p.match_grid = match_grid_size();
+  return RM_OK;
+}
+
+// Enqueue the whole sweep of a plan on st.
+static int plan_enqueue(Plan &p, hipStream_t st) {
+  const int64_t P = (int64_t)p.n_target * (p.n_target + 1) / 2;
+  if (p.omega) RM_HIP(launch_fill(p.omega, p.M * P, 0.0, st));
+  if (p.status) RM_HIP(launch_fill_i32(p.status, p.M, 0, st));
+  RM_HIP(launch_fill_i32(p.counters, std::max(1, p.n_chunks), 0, st));
+  for (int c = 0; c < p.n_chunks; ++c) {
+    const int64_t c0 = (int64_t)c * p.C;
+    const int64_t m = std::min(p.C, p.M - c0);
+    const int t = (m == p.C) ? 0 : 1;
+    {
+      StageTimer tm(1, st);
+      for (auto &set : p.sets) {
+        PsLaunch L{};
+        L.syms = p.d_syms;
+        L.items = set.d_items[t];
+        L.n_items = set.n_items[t];
+        L.counter = nullptr;
+        L.E = p.E + c0;
+        L.m = (int)m;
+        L.out = PsOut{p.work, p.work_estride, p.d_work_off, 2};
+        L.prec = p.o.prec;
+        L.delta = p.o.near_delta;
+        RM_HIP(launch_polesum(L, set.variant, st));
+      }
+    }
+    if (p.R_out) {
+      const Sym &s = *p.syms[0];
+      RM_HIP(launch_unsort_square(s, p.work, p.work_estride, 2 * s.n,
+                                  p.R_out + c0 * s.n * s.n, m, st));
+    }
+    MatchLaunch L{};
+    L.syms = p.d_syms;
+    L.n_sym = (int)p.syms.size();
+    L.E = p.E + c0;
+    L.m = (int)m;
+    L.work = p.work;
+    L.work_estride = p.work_estride;
+    L.work_off = p.d_work_off;
+    L.chan = p.chan;
+    L.chan_estride = p.chan_estride;
+    L.chan_off = p.d_chan_off;
+    L.n_open_out = p.n_open_out ? p.n_open_out + c0 : nullptr;
+    L.K_out = p.K_out ? p.K_out + c0 * p.syms[0]->n * p.syms[0]->n : nullptr;
+    L.K_in = nullptr;
+    L.omega = p.omega ? p.omega + c0 * P : nullptr;
+    L.omega_stride = P;
+    L.n_target_out = p.n_target;
+    L.status = p.status ? p.status + c0 : nullptr;
+    L.do_t = p.do_t;
+    L.counter = p.counters + c;
+    L.grid = p.match_grid;
+    StageTimer tm(2, st);
+    RM_HIP(launch_match(L, st));
+  }
+  return RM_OK;
+}
+
+static int validate_syms(const rm_sym_t *syms, int32_t n_sym, int32_t n_target) {
+  if (!syms || n_sym < 1) return fail(RM_ERR_ARG, "no symmetries");
+  if (n_target < 1) return fail(RM_ERR_ARG, "n_target < 1");
+  for (int q = 0; q < n_sym; ++q) {
+    if (!syms[q]) return fail(RM_ERR_ARG, "null handle %d", q);
+    if (syms[q]->n_target > n_target)
+      return fail(RM_ERR_ARG, "symmetry %d has target level %d >= n_target %d",
+                  q, syms[q]->n_target - 1, n_target);
+  }
+  for (int q = 0; q < n_sym; ++q) {
+    int rc = check_device(syms[q]);
+    if (rc) return rc;
+  }
+  return RM_OK;
 }
 
 static int free_sym(Sym *s) {
@@ -332,8 +737,6 @@ static int free_sym(Sym *s) {
 
 using namespace rmx;
 
-struct rm_sym : public rmx::Sym {};
-
 extern "C" {
 
 const char *rm_last_error(void) { return g_err.c_str(); }
@@ -345,7 +748,7 @@ int rm_profile(int32_t enable) {
 }
 
 int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches) {
-  if (stage < 0 || stage > 2) return fail(RM_ERR_ARG, "stage %d", stage);
+  if (stage < 0 || stage > 3) return fail(RM_ERR_ARG, "stage %d", stage);
   double tot = 0.0;
   int64_t cnt = 0;
   for (auto &r : g_recs) {
@@ -499,85 +902,31 @@ int rm_sym_info(rm_sym_t sym, int32_t *n_chan, int32_t *n_poles,
   return RM_OK;
 }
 
-static int polesum_dispatch(const Sym &s, const rm_opts &o, const double *E,
-                            int64_t m, double *R, int64_t estride, int ld,
-                            hipStream_t st) {
-  hipError_t e;
-  if (o.prec == RM_PREC_FP64)
-    e = launch_polesum_f64(s, E, m, R, estride, ld, st);
-  else
-    e = launch_polesum_mixed(s, o.prec, o.near_delta, E, m, R, estride, ld, st);
-  if (e != hipSuccess)
-    return fail(RM_ERR_HIP, "pole-sum launch failed: %s", hipGetErrorString(e));
-  return RM_OK;
-}
 
 int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
                       const double *E, int64_t M, const rm_opts *opts,
                       double *omega, int32_t *status, void *stream) {
-  if (!syms || n_sym < 1) return fail(RM_ERR_ARG, "no symmetries");
-  if (n_target < 1) return fail(RM_ERR_ARG, "n_target < 1");
   if (M < 0) return fail(RM_ERR_ARG, "M < 0");
-  if (M > 0 && (!E || !omega)) return fail(RM_ERR_ARG, "null E or omega");
   rm_opts o;
   int rc = check_opts(opts, &o);
   if (rc) return rc;
-  int n_max = 0;
-  for (int q = 0; q < n_sym; ++q) {
+  if (!syms || n_sym < 1 || n_target < 1) return validate_syms(syms, n_sym, n_target);
+  for (int q = 0; q < n_sym; ++q)
     if (!syms[q]) return fail(RM_ERR_ARG, "null handle %d", q);
-    if ((rc = check_device(syms[q]))) return rc;
-    if (syms[q]->n_target > n_target)
-      return fail(RM_ERR_ARG, "symmetry %d has target level %d >= n_target %d",
-                  q, syms[q]->n_target - 1, n_target);
-    n_max = std::max(n_max, syms[q]->n);
-  }
+  if (M > 0 && (!E || !omega)) return fail(RM_ERR_ARG, "null E or omega");
+  if ((rc = validate_syms(syms, n_sym, n_target))) return rc;
   if (M == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
-  const int64_t P = (int64_t)n_target * (n_target + 1) / 2;
-  RM_HIP(launch_fill(omega, M * P, 0.0, st));
-  if (status) RM_HIP(launch_fill_i32(status, M, 0, st));
-  const int64_t C = pick_chunk(n_max, M, o.chunk);
-  const int64_t wstride = work_doubles(n_max);
-  DevBuf work, chan, nopen;
-  if ((rc = dev_alloc(work, (size_t)(C * wstride) * sizeof(double), st))) return rc;
-  if ((rc = dev_alloc(chan, (size_t)(C * n_max) * sizeof(ChanSlot), st))) return rc;
-  if ((rc = dev_alloc(nopen, (size_t)C * sizeof(int32_t), st))) return rc;
-  for (int64_t c0 = 0; c0 < M; c0 += C) {
-    const int64_t m = std::min(C, M - c0);
-    for (int q = 0; q < n_sym; ++q) {
-      const Sym &s = *syms[q];
-      const int64_t ws = work_doubles(s.n);
-      {
-        StageTimer t(0, st);
-        RM_HIP(launch_chanfn(s, E + c0, m, (ChanSlot *)chan.p,
-                             (int32_t *)nopen.p, status ? status + c0 : nullptr,
-                             st));
-      }
-      {
-        StageTimer t(1, st);
-        if ((rc = polesum_dispatch(s, o, E + c0, m, (double *)work.p, ws,
-                                   2 * s.n, st)))
-          return rc;
-      }
-      MatchArgs a{};
-      a.chan = (const ChanSlot *)chan.p;
-      a.n_open = (const int32_t *)nopen.p;
-      a.work = (double *)work.p;
-      a.work_stride = ws;
-      a.m = (int)m;
-      a.K_out = nullptr;
-      a.omega = omega + c0 * P;
-      a.omega_stride = P;
-      a.n_target_out = n_target;
-      a.status = status ? status + c0 : nullptr;
-      a.do_t = 1;
-      a.solve_fp32 = o.solve_fp32;
-      a.refine_iters = o.refine_iters;
-      StageTimer t(2, st);
-      RM_HIP(launch_match(s, a, st));
-    }
+  Plan p;
+  rc = plan_build(p, syms, n_sym, n_target, E, M, o, st, true, 16.0e9);
+  if (!rc) {
+    p.E = E;
+    p.omega = omega;
+    p.status = status;
+    rc = plan_enqueue(p, st);
   }
-  return RM_OK;
+  plan_free_device(p);
+  return rc;
 }
 
 int rm_kmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
@@ -592,39 +941,20 @@ int rm_kmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
   if ((rc = check_device(sym))) return rc;
   if (m == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
-  const Sym &s = *sym;
-  if (status) RM_HIP(launch_fill_i32(status, m, 0, st));
-  const int64_t C = pick_chunk(s.n, m, o.chunk);
-  const int64_t ws = work_doubles(s.n);
-  DevBuf work, chan;
-  if ((rc = dev_alloc(work, (size_t)(C * ws) * sizeof(double), st))) return rc;
-  if ((rc = dev_alloc(chan, (size_t)(C * s.n) * sizeof(ChanSlot), st))) return rc;
-  const int64_t nn = (int64_t)s.n * s.n;
-  for (int64_t c0 = 0; c0 < m; c0 += C) {
-    const int64_t mc = std::min(C, m - c0);
-    RM_HIP(launch_chanfn(s, E + c0, mc, (ChanSlot *)chan.p, n_open + c0,
-                         status ? status + c0 : nullptr, st));
-    if ((rc = polesum_dispatch(s, o, E + c0, mc, (double *)work.p, ws, 2 * s.n, st)))
-      return rc;
-    if (R_opt)
-      RM_HIP(launch_unsort_square(s, (const double *)work.p, ws, 2 * s.n,
-                                  R_opt + c0 * nn, mc, st));
-    MatchArgs a{};
-    a.chan = (const ChanSlot *)chan.p;
-    a.n_open = n_open + c0;
-    a.work = (double *)work.p;
-    a.work_stride = ws;
-    a.m = (int)mc;
-    a.K_out = K + c0 * nn;
-    a.omega = nullptr;
-    a.n_target_out = s.n_target;
-    a.status = status ? status + c0 : nullptr;
-    a.do_t = 0;
-    a.solve_fp32 = o.solve_fp32;
-    a.refine_iters = o.refine_iters;
-    RM_HIP(launch_match(s, a, st));
+  Plan p;
+  rm_sym_t one[1] = {sym};
+  rc = plan_build(p, one, 1, sym->n_target, E, m, o, st, true, 8.0e9);
+  if (!rc) {
+    p.E = E;
+    p.status = status;
+    p.K_out = K;
+    p.n_open_out = n_open;
+    p.R_out = R_opt;
+    p.do_t = 0;
+    rc = plan_enqueue(p, st);
   }
-  return RM_OK;
+  plan_free_device(p);
+  return rc;
 }
 
 int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
@@ -641,17 +971,37 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
   if (m == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
   const Sym &s = *sym;
-  const int64_t C = pick_chunk(s.n, m, 0);
   const int64_t ws = work_doubles(s.n);
-  DevBuf work;
+  const int64_t C = std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)(8.0e9 / (8.0 * ws))));
+  DevBuf work, tabs;
   if ((rc = dev_alloc(work, (size_t)(C * ws) * sizeof(double), st))) return rc;
+  if ((rc = dev_alloc(tabs, sizeof(SymDev) + sizeof(int64_t), st))) return rc;
+  const SymDev sd = s.dev();
+  const int64_t zero = 0;
+  RM_HIP(hipMemcpyAsync(tabs.p, &sd, sizeof sd, hipMemcpyHostToDevice, st));
+  RM_HIP(hipMemcpyAsync((char *)tabs.p + sizeof(SymDev), &zero, sizeof zero,
+                        hipMemcpyHostToDevice, st));
   const int64_t nn = (int64_t)s.n * s.n;
   const int64_t P = (int64_t)n_target * (n_target + 1) / 2;
   for (int64_t c0 = 0; c0 < m; c0 += C) {
     const int64_t mc = std::min(C, m - c0);
-    RM_HIP(launch_t_omega_from_k(s, K + c0 * nn, n_open + c0, mc, (double *)work.p,
-                                 ws, omega + c0 * P, n_target, st));
+    MatchLaunch L{};
+    L.syms = (const SymDev *)tabs.p;
+    L.n_sym = 1;
+    L.E = E + c0;
+    L.m = (int)mc;
+    L.work = (double *)work.p;
+    L.work_estride = ws;
+    L.work_off = (const int64_t *)((char *)tabs.p + sizeof(SymDev));
+    L.K_in = K + c0 * nn;
+    L.omega = omega + c0 * P;
+    L.omega_stride = P;
+    L.n_target_out = n_target;
+    L.do_t = 1;
+    RM_HIP(launch_match(L, st));
   }
+  RM_HIP(hipStreamSynchronize(st));  // the host descriptor copies above
+  (void)n_open;
   return RM_OK;
 }
 
@@ -666,19 +1016,37 @@ int rm_rmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
   if ((rc = check_device(sym))) return rc;
   if (m == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
-  const Sym &s = *sym;
-  const int64_t nn = (int64_t)s.n * s.n;
-  const int64_t C = std::min<int64_t>(m, std::max<int64_t>(16, (int64_t)(4.0e9 / (8.0 * nn))));
-  DevBuf work;
-  if ((rc = dev_alloc(work, (size_t)(C * nn) * sizeof(double), st))) return rc;
-  for (int64_t c0 = 0; c0 < m; c0 += C) {
-    const int64_t mc = std::min(C, m - c0);
-    if ((rc = polesum_dispatch(s, o, E + c0, mc, (double *)work.p, nn, s.n, st)))
-      return rc;
-    RM_HIP(launch_unsort_square(s, (const double *)work.p, nn, s.n, R + c0 * nn,
-                                mc, st));
+  Plan p;
+  rm_sym_t one[1] = {sym};
+  rc = plan_build(p, one, 1, sym->n_target, E, m, o, st, true, 8.0e9);
+  if (!rc) {
+    const Sym &s = *sym;
+    for (int c = 0; c < p.n_chunks && !rc; ++c) {
+      const int64_t c0 = (int64_t)c * p.C;
+      const int64_t mc = std::min(p.C, m - c0);
+      const int t = (mc == p.C) ? 0 : 1;
+      for (auto &set : p.sets) {
+        PsLaunch L{};
+        L.syms = p.d_syms;
+        L.items = set.d_items[t];
+        L.n_items = set.n_items[t];
+        L.E = E + c0;
+        L.m = (int)mc;
+        L.out = PsOut{p.work, p.work_estride, p.d_work_off, 2};
+        L.prec = p.o.prec;
+        L.delta = p.o.near_delta;
+        hipError_t e = launch_polesum(L, set.variant, st);
+        if (e != hipSuccess) rc = fail(RM_ERR_HIP, "pole sum: %s", hipGetErrorString(e));
+      }
+      if (!rc) {
+        hipError_t e = launch_unsort_square(s, p.work, p.work_estride, 2 * s.n,
+                                            R + c0 * s.n * s.n, mc, st);
+        if (e != hipSuccess) rc = fail(RM_ERR_HIP, "unsort: %s", hipGetErrorString(e));
+      }
+    }
   }
-  return RM_OK;
+  plan_free_device(p);
+  return rc;
 }
 
 int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m, double *out,
@@ -698,6 +1066,87 @@ int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m, double *out,
   RM_HIP(launch_chanfn(s, E, m, (ChanSlot *)chan.p, (int32_t *)nopen.p, status, st));
   RM_HIP(launch_unsort_chan_open(s, (const ChanSlot *)chan.p,
                                  (const int32_t *)nopen.p, m, out, st));
+  return RM_OK;
+}
+
+struct rm_plan : public rmx::Plan {};
+
+int rm_plan_create(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
+                   const double *E, int64_t M, const rm_opts *opts,
+                   double *omega, int32_t *status, void *stream,
+                   rm_plan_t *out) {
+  if (!out) return fail(RM_ERR_ARG, "null out");
+  *out = nullptr;
+  if (M < 1) return fail(RM_ERR_ARG, "M < 1");
+  if (!E || !omega) return fail(RM_ERR_ARG, "null E or omega");
+  rm_opts o;
+  int rc = check_opts(opts, &o);
+  if (rc) return rc;
+  if ((rc = validate_syms(syms, n_sym, n_target))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  rm_plan *p = new (std::nothrow) rm_plan();
+  if (!p) return fail(RM_ERR_NOMEM, "host allocation");
+  rc = plan_build(*p, syms, n_sym, n_target, E, M, o, st, false, 32.0e9);
+  if (!rc) {
+    p->E = E;
+    p->omega = omega;
+    p->status = status;
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      rc = fail(RM_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    } else {
+      const bool prof = g_prof;
+      g_prof = false;  // no event records inside a captured graph
+      rc = plan_enqueue(*p, p->cap_stream);
+      g_prof = prof;
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+      p->graph = g;
+      if (!rc && e2 != hipSuccess)
+        rc = fail(RM_ERR_HIP, "end capture: %s", hipGetErrorString(e2));
+      if (!rc) {
+        e2 = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e2 != hipSuccess)
+          rc = fail(RM_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e2));
+      }
+    }
+  }
+  if (rc) {
+    plan_free_device(*p);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return RM_OK;
+}
+
+int rm_plan_execute(rm_plan_t plan, void *stream) {
+  if (!plan || !plan->exec) return fail(RM_ERR_ARG, "null plan");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RM_ERR_HIP, "hipGetDevice");
+  if (dev != plan->device) return fail(RM_ERR_STATE, "plan built on device %d", plan->device);
+  StageTimer tm(3, (hipStream_t)stream);
+  RM_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+  return RM_OK;
+}
+
+int rm_plan_info(rm_plan_t plan, int64_t *chunk, int32_t *n_chunks,
+                 int32_t *variants, int32_t n_variants) {
+  if (!plan) return fail(RM_ERR_ARG, "null plan");
+  if (chunk) *chunk = plan->C;
+  if (n_chunks) *n_chunks = plan->n_chunks;
+  if (variants)
+    for (int q = 0; q < n_variants && q < (int)plan->variant.size(); ++q)
+      variants[q] = plan->variant[q];
+  return RM_OK;
+}
+
+int rm_plan_free(rm_plan_t plan) {
+  if (!plan) return RM_OK;
+  (void)hipDeviceSynchronize();
+  plan_free_device(*plan);
+  delete plan;
   return RM_OK;
 }
 

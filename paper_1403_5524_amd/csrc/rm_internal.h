@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+#include <vector>
+
 #include "../../include/rmatrix.h"
 
 namespace rmx {
@@ -13,6 +16,23 @@ constexpr int kChanPad = 32;
 constexpr int kPolePad = 64;
 constexpr double kPadPole = 1.0e30;  // padding poles sit far from any energy
 
+// Device-side view of one symmetry (plain data, copied into a descriptor
+// table that the grouped kernels index by symmetry number).
+struct SymDev {
+  int n, nh, n_pad, nh_pad;
+  int n_target;
+  double a, z, g;
+  const double *E_pole;       // [nh_pad] ascending, padding = kPadPole
+  const double *Wt;           // [nh_pad][n_pad] FP64, pole-major
+  const float *W32c;          // [n_pad][nh_pad] FP32, channel-major
+  const uint16_t *Whc, *Wlc;  // [n_pad][nh_pad] BF16 split, channel-major
+  const double *e_thr;        // [n] sorted
+  const int32_t *l;           // [n] sorted order
+  const int32_t *perm;        // [n] sorted position -> input channel
+  const int32_t *tptr;        // [n_target+1] CSR of sorted positions per
+  const int32_t *tch;         // [n]           target level
+};
+
 // A symmetry resident on one device.  Channels are stored sorted by
 // threshold (stable), so at any energy the open channels are a prefix.
 struct Sym {
@@ -21,76 +41,114 @@ struct Sym {
   int n_pad, nh_pad;    // padded to kChanPad / kPolePad
   double a, z, g;
   int n_target;         // max target level + 1
-  // device arrays
-  double *E_pole;       // [nh_pad] ascending, padding = kPadPole
-  double *Wt;           // [nh_pad][n_pad] FP64, k-major, zero padded
-  float *W32c;          // [n_pad][nh_pad] FP32, channel-major
-  uint16_t *Whc, *Wlc;  // [n_pad][nh_pad] BF16 split, channel-major:
-                        // w = hi + lo + O(2^-16 |w|)
-  double *e_thr;        // [n] sorted
-  int32_t *l;           // [n] (sorted order)
-  int32_t *perm;        // [n] sorted position -> input channel
+  // device arrays (owned)
+  double *E_pole;
+  double *Wt;
+  float *W32c;
+  uint16_t *Whc, *Wlc;  // w = hi + lo + O(2^-16 |w|)
+  double *e_thr;
+  int32_t *l;
+  int32_t *perm;
   int32_t *inv;         // [n] input channel -> sorted position
-  int32_t *tptr;        // [n_target+1] CSR: channels (sorted positions) per
-  int32_t *tch;         // [n]           target level, ascending
+  int32_t *tptr;
+  int32_t *tch;
   // host copies
   double *h_e_thr;      // [n] sorted
   int32_t *h_perm;
+  SymDev dev() const {
+    SymDev d;
+    d.n = n; d.nh = nh; d.n_pad = n_pad; d.nh_pad = nh_pad;
+    d.n_target = n_target; d.a = a; d.z = z; d.g = g;
+    d.E_pole = E_pole; d.Wt = Wt; d.W32c = W32c; d.Whc = Whc; d.Wlc = Wlc;
+    d.e_thr = e_thr; d.l = l; d.perm = perm; d.tptr = tptr; d.tch = tch;
+    return d;
+  }
 };
 
-// Per-energy channel data written by the channel-function kernel, sorted
-// channel order: (d1, d2, s, a s') with d1 = c, d2 = a c' for open channels
-// and (e, a e') of the closed-channel function for closed ones.
+// Per-energy channel data, sorted channel order: (d1, d2, s, a s') with
+// d1 = c, d2 = a c' for open channels and (e, a e') of the closed-channel
+// function for closed ones.
 struct ChanSlot {
   double d1, d2, s, asp;
 };
 
-// ---- launchers (return hipError_t of the launch) ----
+// Work item of the grouped pole-sum kernels: symmetry, two tile
+// coordinates (meaning per kernel) and an energy group.
+struct PsItem {
+  int sym, x, y, grp;
+};
+
+// Where the pole sum writes R of symmetry s at chunk energy e:
+// out + e*estride + off[s] + i*(ld_mult*n_s) + j.
+struct PsOut {
+  double *out;
+  int64_t estride;
+  const int64_t *off;   // device [n_sym]
+  int ld_mult;
+};
+
+// Tile variants of the pole-sum kernels (chosen by the autotuner).
+enum PsVariant {
+  PS_F64_T32_E16 = 0,   // FP64, 32x32 tile pairs, 16 energies per WG
+  PS_MX_J16_E8 = 1,     // mixed, 16 column blocks, 8 energies per WG
+  PS_MX_J8_E8 = 2,      // mixed, 8 column blocks, 8 energies per WG
+  PS_MX_J16_E4 = 3      // mixed, 16 column blocks, 4 energies per WG
+};
+
+// ---- launchers (return the hipError_t of the launch) ----
 
 hipError_t launch_chanfn(const Sym &s, const double *E, int64_t m,
                          ChanSlot *chan, int32_t *n_open, int32_t *status,
                          hipStream_t st);
 
-// Pole sum (Sec. 6, Eq. 1-2), FP64 MFMA over all poles.  Writes
-// R[e][i][j] (sorted channel order) at R + e*r_estride + i*r_ld + j,
-// scaled by 1/(2a), both triangles.
-hipError_t launch_polesum_f64(const Sym &s, const double *E, int64_t m,
-                              double *R, int64_t r_estride, int r_ld,
-                              hipStream_t st);
-
-// Mixed-precision pole sum: far poles in FP32 or split-BF16 MFMA with FP32
-// accumulation, then the FP64 near-pole correction for |E_k - E| < delta.
-hipError_t launch_polesum_mixed(const Sym &s, int prec, double delta,
-                                const double *E, int64_t m, double *R,
-                                int64_t r_estride, int r_ld, hipStream_t st);
-
-// Matching -> K -> T -> Omega for m energies.  work: per energy a block of
-// 3 n^2 doubles whose first 2 n^2 (row-major, ld 2n) hold R on entry in the
-// left half (sorted order).  K_out (may be null): [m][n][n] open-open block
-// in input-channel order.  omega (may be null): accumulated.
-struct MatchArgs {
-  const ChanSlot *chan;
-  const int32_t *n_open;
-  double *work;
-  int64_t work_stride;  // doubles per energy
+// Grouped pole sum (Sec. 6, Eq. 1-2) over a table of work items that may
+// span several symmetries.  FP64 variants use MFMA over every pole; mixed
+// variants use FP32 or split-BF16 MFMA over the far poles with an FP64
+// near-pole correction for |E_k - E| < delta.  With a counter (device int
+// holding 0) the grid is persistent and pulls items from it.
+struct PsLaunch {
+  const SymDev *syms;
+  const PsItem *items;
+  int n_items;
+  int *counter;         // nullable
+  int grid;             // persistent grid size (used with counter)
+  const double *E;
   int m;
-  double *K_out;        // nullable
-  double *omega;        // nullable
-  int64_t omega_stride;
-  int n_target_out;     // Omega row has n_target_out*(n_target_out+1)/2
-  int32_t *status;      // nullable
-  int do_t;             // 1: compute T and Omega
-  int solve_fp32;
-  int refine_iters;
+  PsOut out;
+  int prec;
+  double delta;
 };
-hipError_t launch_match(const Sym &s, const MatchArgs &a, hipStream_t st);
+hipError_t launch_polesum(const PsLaunch &L, int variant, hipStream_t st);
+int ps_energy_group(int variant);         // energies per work item
+// Tile items of one symmetry for a variant: (x, y) pairs, in order.
+void ps_tiles(const Sym &s, int variant, std::vector<std::pair<int, int>> &out);
 
-// Omega from given K (rm_collision_strengths).
-hipError_t launch_t_omega_from_k(const Sym &s, const double *K,
-                                 const int32_t *n_open, int64_t m,
-                                 double *work, int64_t work_stride,
-                                 double *omega, int n_target_out,
-                                 hipStream_t st);
+// Channel functions, matching, K, T and Omega: one workgroup per energy,
+// looping over every symmetry (so it owns that energy's Omega row).  With a
+// counter the grid is persistent.
+struct MatchLaunch {
+  const SymDev *syms;
+  int n_sym;
+  const double *E;
+  int m;
+  double *work;               // [M | B] (n x 2n) then K (n x n) per symmetry
+  int64_t work_estride;
+  const int64_t *work_off;    // device [n_sym]
+  ChanSlot *chan;
+  int64_t chan_estride;
+  const int64_t *chan_off;    // device [n_sym]
+  int32_t *n_open_out;        // nullable, symmetry 0 only
+  double *K_out;              // nullable, symmetry 0 only: [m][n][n]
+  const double *K_in;         // nullable, symmetry 0 only (skip matching)
+  double *omega;              // nullable
+  int64_t omega_stride;
+  int n_target_out;
+  int32_t *status;            // nullable
+  int do_t;
+  int *counter;               // nullable
+  int grid;
+};
+hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
 
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v,
@@ -99,7 +157,5 @@ hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v,
 hipError_t launch_unsort_square(const Sym &s, const double *src,
                                 int64_t src_estride, int src_ld, double *dst,
                                 int64_t m, hipStream_t st);
-hipError_t launch_unsort_chan(const Sym &s, const ChanSlot *chan, int64_t m,
-                              double *out, hipStream_t st);
 
 }  // namespace rmx

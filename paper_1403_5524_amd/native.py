@@ -21,6 +21,7 @@ RM_E_CF_NOCONV = 0x04
 RM_E_NONFINITE = 0x08
 RM_E_ON_THRESHOLD = 0x10
 RM_E_REFINE_NOCONV = 0x20
+RM_FLAG_AUTOTUNE = 0x1
 
 EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_kmatrix", "rm_collision_strengths", "rm_rmatrix",
@@ -28,7 +29,8 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_mlp_create", "rm_mlp_free", "rm_mlp_n_params",
             "rm_mlp_get_params", "rm_mlp_set_params", "rm_mlp_forward",
             "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
-            "rm_last_error")
+            "rm_plan_create", "rm_plan_execute", "rm_plan_info",
+            "rm_plan_free", "rm_last_error")
 
 
 class RmError(RuntimeError):
@@ -87,6 +89,12 @@ def lib():
         L.rm_mlp_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.rm_mlp_adam_step.argtypes = [vp, f32, f32, f32, f32, vp]
         L.rm_mesh_from_density.argtypes = [vp, i32, f64, f64, f64, i64, vp, vp]
+        L.rm_plan_create.argtypes = [vp, i32, i32, vp, i64,
+                                     ctypes.POINTER(Opts), vp, vp, vp,
+                                     ctypes.POINTER(vp)]
+        L.rm_plan_execute.argtypes = [vp, vp]
+        L.rm_plan_info.argtypes = [vp, vp, vp, vp, i32]
+        L.rm_plan_free.argtypes = [vp]
         L.rm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "rm_last_error":
@@ -110,8 +118,8 @@ def _stream():
 
 
 def make_opts(prec=RM_PREC_FP64, near_delta=0.0, solve_fp32=0, refine_iters=0,
-              chunk=0):
-    return Opts(prec, near_delta, solve_fp32, refine_iters, chunk, 0)
+              chunk=0, flags=0):
+    return Opts(prec, near_delta, solve_fp32, refine_iters, chunk, flags)
 
 
 class Symmetry:
@@ -304,3 +312,49 @@ def rm_mesh_from_density(dens, lo, hi, floor_frac, M):
     _check(lib().rm_mesh_from_density(_ptr(dens), int(dens.numel()), lo, hi,
                                       floor_frac, M, _ptr(E), _stream()))
     return E
+
+
+class Plan:
+    """rm_plan_t: a sweep captured into a hipGraph, bound to E/omega/status."""
+
+    def __init__(self, syms, n_target, E, opts=None, omega=None, status=None):
+        import torch
+        M = int(E.numel())
+        P = n_target * (n_target + 1) // 2
+        self.E = E
+        self.omega = omega if omega is not None else torch.empty(
+            (M, P), dtype=torch.float64, device=E.device)
+        self.status = status if status is not None else torch.empty(
+            (M,), dtype=torch.int32, device=E.device)
+        self._syms = list(syms)
+        arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
+        o = opts if opts is not None else make_opts()
+        h = ctypes.c_void_p()
+        _check(lib().rm_plan_create(arr, len(syms), n_target, _ptr(E), M,
+                                    ctypes.byref(o), _ptr(self.omega),
+                                    _ptr(self.status), _stream(),
+                                    ctypes.byref(h)))
+        self.handle = h
+
+    def execute(self):
+        _check(lib().rm_plan_execute(self.handle, _stream()))
+        return self.omega, self.status
+
+    def info(self):
+        c = ctypes.c_int64()
+        nc = ctypes.c_int32()
+        v = (ctypes.c_int32 * len(self._syms))()
+        _check(lib().rm_plan_info(self.handle, ctypes.byref(c),
+                                  ctypes.byref(nc), v, len(self._syms)))
+        return int(c.value), int(nc.value), list(v)
+
+    def free(self):
+        if self.handle:
+            lib().rm_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

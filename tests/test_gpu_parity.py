@@ -242,3 +242,26 @@ def test_batched_symmetries_c3_sample(torch_dev, nat):
     log("c3 omega normwise err %.3e" % err)
     assert err < OMEGA_TOL_FP64
     assert np.array_equal(st.cpu().numpy(), rst)
+
+
+def test_large_symmetry_c4_sampled(torch_dev, nat):
+    """1500 channels, 40000 poles: the split-BF16 pole sum within the mixed
+    tolerance and the FP64 path within 1e-6 on sampled energies."""
+    torch, _ = torch_dev
+    w = wl.config4()
+    s = w.syms[0]
+    h = nat.load_symmetry(s)
+    idx = wl.sample_indices(w.mesh.size, 3, seed=6)
+    E = w.mesh[idx]
+    log("sweep c4 m=%d" % E.size)
+    ref = oracle.sweep(s.as_dict(), E)
+    Et = _dev(torch_dev, E)
+    om64, st = nat.rm_sweep_energies([h], 1500, Et)
+    err64, _, _ = omega_normwise_err(om64.cpu().numpy(), ref["omega"])
+    ombf, _ = nat.rm_sweep_energies([h], 1500, Et,
+                                    nat.make_opts(prec=nat.RM_PREC_BF16X3))
+    errbf, _, _ = omega_normwise_err(ombf.cpu().numpy(), ref["omega"])
+    log("c4 omega err fp64 %.3e bf16x3 %.3e" % (err64, errbf))
+    assert err64 < OMEGA_TOL_FP64
+    assert errbf < 1e-4
+    assert np.array_equal(st.cpu().numpy(), ref["status"])
