@@ -141,10 +141,12 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
         for (int r = 0; r < 4; ++r) {
           const int gi = I * PS_T + a * 16 + kq + 4 * r;
           const int gj = J * PS_T + b * 16 + col;
-          if (gi < S.n && gj < S.n) {
+          // diagonal tiles: the upper triangle is mirrored so R is exactly
+          // symmetric
+          if (gi < S.n && gj < S.n && (!diag || gi <= gj)) {
             const double v = acc[e][a][b][r] * scale;
             Re[(int64_t)gi * ld + gj] = v;
-            if (!diag) Re[(int64_t)gj * ld + gi] = v;
+            Re[(int64_t)gj * ld + gi] = v;
           }
         }
   }

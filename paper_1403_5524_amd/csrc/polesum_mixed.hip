@@ -206,6 +206,7 @@ __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
         const int gi = IB * 16 + 4 * kq + r;
         const int gj = JB * 16 + col;
         if (gi >= S.n || gj >= S.n) continue;
+        if (JB == IB && gi > gj) continue;  // diagonal block: mirror the upper
         double v = (double)acc[e][b][r];
         for (int k = klo; k < khi; ++k) {
           const double diff = S.E_pole[k] - Ee;
@@ -214,7 +215,7 @@ __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
         }
         v *= scale;
         Re[(int64_t)gi * ld + gj] = v;
-        if (JB != IB) Re[(int64_t)gj * ld + gi] = v;
+        Re[(int64_t)gj * ld + gi] = v;
       }
     }
   }

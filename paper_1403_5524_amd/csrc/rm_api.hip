@@ -243,7 +243,7 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
   if (d.refine_iters < 0) return fail(RM_ERR_ARG, "refine_iters < 0");
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");
-  if (d.flags != 0) return fail(RM_ERR_ARG, "flags must be 0");
+  if (d.flags & ~RM_FLAG_AUTOTUNE) return fail(RM_ERR_ARG, "unknown flags 0x%x", d.flags);
   if (d.solve_fp32 != 0)
     return fail(RM_ERR_ARG, "solve_fp32 is not available: the matching "
                             "solve runs in FP64");
