@@ -1,4 +1,4 @@
-// Matching, K-matrix, T-matrix and collision strengths, one workgroup per
+// Matching, K-matrix, T-matrix and collision strengths: one wavefront per
 // energy.
 //
 // With channels sorted by threshold the open channels at energy E are the
@@ -12,15 +12,24 @@
 // so |T_ij|^2 = 4 (Y_ij^2 + Q_ij^2), and
 //     Omega(t, u) += (g/2) sum_{i in t, j in u, open} |T_ij|^2.
 //
-// Dense algebra runs out of a per-energy global workspace (row-major,
-// leading dimension 2n) with a blocked right-looking LU (panels of 16
-// columns, partial pivoting) whose trailing updates and products are 64 x 64
-// tiles staged through LDS and multiplied on the FP64 matrix cores.
+// Each wavefront owns one energy at a time and loops over every symmetry;
+// it owns that energy's Omega row, so symmetries add without atomics and in
+// a fixed order.  The dense algebra is wavefront-local, in a per-energy
+// global workspace (row-major, leading dimension 2n): blocked right-looking
+// LU with partial pivoting (panels of 16 columns), trailing updates and
+// products as 16 x 16 FP64 MFMA blocks (v_mfma_f64_16x16x4f64).
 //
-// One workgroup owns one energy and loops over every symmetry: it computes
-// that symmetry's channel functions, solves, and adds into the energy's
-// Omega row, which no other workgroup touches (deterministic, no atomics).
-// With a counter the grid is persistent and pulls energies from it.
+// The workspace of one energy is far larger than a CU's caches, so this
+// code is bound by memory latency, not arithmetic.  Every pass is therefore
+// written as "issue all loads of a batch, then compute, then store": the
+// compiler cannot move a load above a store it cannot prove disjoint, so a
+// read-modify-write loop written element by element would pay one full
+// round trip per element.  GEMM tiles load A, B and C together and
+// prefetch the next tile before storing the current one.
+//
+// Lanes of a wavefront run in lockstep, so ordering between lanes needs only
+// a memory fence and a scheduling barrier -- no workgroup barrier anywhere.
+// Wavefronts pull energies from an atomic counter (persistent grid).
 #include <algorithm>
 
 #include "chanfn.h"
@@ -28,382 +37,567 @@
 
 namespace rmx {
 
-constexpr int MT = 256;
-constexpr int NB = 16;
-constexpr int TB = 64;
-constexpr int kMaxChanLds = 2048;
+constexpr int WT = 64;   // lanes per wavefront
+constexpr int NB = 16;   // panel width
+constexpr int WPB = 4;   // wavefronts per workgroup
+constexpr int UNR = 4;   // independent elements per lane per batch
 
-struct WgScratch {
-  double sL[TB * (NB + 1)];
-  double sU[NB * TB];
-  double red_v[4];
-  int red_i[4];
-  int piv[NB];
-  int flag;
-  double rowbuf[2][NB];
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Per-wavefront LDS: the 16 x 16 diagonal block of the current panel and the
+// row moves of its interchanges.
+struct WaveLds {
+  double T[NB][NB + 1];
+  double Ti[NB][NB + 1];  // its inverse
+  int piv[NB];   // pivot row chosen at each panel column
+  int srcp[NB];  // after the interchanges, panel row q holds old row srcp[q]
+  int opos[NB];  // rows below the panel that receive another row ...
+  int osrc[NB];  // ... namely old row osrc[m]
+  int nout;
 };
 
-// Block-wide argmax of v (ties -> smaller index).
-__device__ inline int wg_argmax(double v, int idx, WgScratch &sh) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ inline int lane_id() { return threadIdx.x & (WT - 1); }
+
+// Make this lane's earlier global writes visible to the other lanes of the
+// wavefront and keep the compiler from moving memory operations across.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ inline double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wavefront argmax of a = |v| (ties -> smaller index), carrying v.
+__device__ inline void wave_argmax(double &a, double &v, int &idx) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
+    const double oa = __shfl_xor(a, off);
     const double ov = __shfl_xor(v, off);
     const int oi = __shfl_xor(idx, off);
-    if (ov > v || (ov == v && oi < idx)) {
+    if (oa > a || (oa == a && oi < idx)) {
+      a = oa;
       v = ov;
       idx = oi;
     }
   }
-  if (lane == 0) {
-    sh.red_v[wave] = v;
-    sh.red_i[wave] = idx;
-  }
-  __syncthreads();
-  double bv = sh.red_v[0];
-  int bi = sh.red_i[0];
-#pragma unroll
-  for (int w = 1; w < 4; ++w) {
-    const double ov = sh.red_v[w];
-    const int oi = sh.red_i[w];
-    if (ov > bv || (ov == bv && oi < bi)) {
-      bv = ov;
-      bi = oi;
-    }
-  }
-  __syncthreads();
-  return bi;
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ inline int wave_or(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+  return v;
+}
 
-// C (rows x cols) op= A (rows x kd) * B (kd x cols), all in global memory.
-// mode 0: C -= AB;  mode 1: C = AB + I;  mode 2: C = AB.
-// 64 x 64 output tiles; A and B are staged in LDS 16 columns/rows at a
-// time and multiplied on the FP64 matrix cores (16x16x4): each wave owns a
-// 32 x 32 quarter of the tile as 2 x 2 MFMA blocks.
-__device__ void wg_gemm(double *C, int ldc, const double *A, int lda,
-                        const double *B, int ldb, int rows, int cols, int kd,
-                        int mode, WgScratch &sh) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+// ---------------------------------------------------------------------------
+// GEMM, wavefront-local, operands in global memory.
+//   MODE 0: C -= A B  (kd <= 16: the rank-16 updates of the LU)
+//   MODE 1: C = A B + I
+//   MODE 2: C = A B
+// The wavefront walks 32 x 32 output tiles (2 x 2 MFMA blocks sharing their
+// A and B fragments) in k-steps of 16.
+struct Frag {
+  double a[4][2], b[4][2];
+};
+
+__device__ inline void frag_load(Frag &f, const double *A, int lda,
+                                 const double *B, int ldb, int rows, int cols,
+                                 int kd, int rb, int cb, int k0) {
+  const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
-  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-  for (int rb = 0; rb < rows; rb += TB) {
-    for (int cb = 0; cb < cols; cb += TB) {
+  const int ra0 = rb + col, ra1 = ra0 + 16, c0 = cb + col, c1 = c0 + 16;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = k0 + 4 * s + kq;
+    const bool kv = k < kd;
+    f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)ra0 * lda + k] : 0.0;
+    f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)ra1 * lda + k] : 0.0;
+    f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)k * ldb + c0] : 0.0;
+    f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)k * ldb + c1] : 0.0;
+  }
+}
+
+// FP64 16x16x4 result layout: D[i][j] at j = lane % 16, i = lane / 16 + 4 r.
+__device__ inline void ctile_load(double (&c)[2][2][4], const double *C,
+                                  int ldc, int rows, int cols, int rb, int cb) {
+  const int lane = lane_id();
+  const int col = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rb + 16 * x + kq + 4 * r, j = cb + 16 * y + col;
+        c[x][y][r] = (i < rows && j < cols) ? C[(int64_t)i * ldc + j] : 0.0;
+      }
+}
+
+template <int MODE>
+__device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
+                          const double *B, int ldb, int rows, int cols,
+                          int kd) {
+  const int lane = lane_id();
+  const int col = lane & 15, kq = lane >> 4;
+  const int nct = (cols + 31) >> 5;
+  const int ntile = ((rows + 31) >> 5) * nct;
+  const int nk = MODE == 0 ? 1 : max(1, (kd + 15) >> 4);
+  if (ntile > 0) {
+    Frag cur, nxt;
+    double cv[2][2][4], cn[2][2][4];
+    frag_load(cur, A, lda, B, ldb, rows, cols, kd, 0, 0, 0);
+    if (MODE == 0) ctile_load(cv, C, ldc, rows, cols, 0, 0);
+    for (int t = 0; t < ntile; ++t) {
+      const int rb = (t / nct) * 32, cb = (t % nct) * 32;
       d4 acc[2][2];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < kd; k0 += NB) {
-        for (int idx = tid; idx < TB * NB; idx += MT) {
-          const int r = idx / NB, k = idx % NB;
-          sh.sL[r * (NB + 1) + k] = (rb + r < rows && k0 + k < kd)
-                                        ? A[(int64_t)(rb + r) * lda + k0 + k]
-                                        : 0.0;
-          const int kk = idx / TB, c = idx % TB;
-          sh.sU[kk * TB + c] = (k0 + kk < kd && cb + c < cols)
-                                   ? B[(int64_t)(k0 + kk) * ldb + cb + c]
-                                   : 0.0;
+      for (int kc = 0; kc < nk; ++kc) {
+        // prefetch: the next k-step of this tile, else the next tile (whose
+        // A, B and C do not overlap this tile's C)
+        if (kc + 1 < nk) {
+          frag_load(nxt, A, lda, B, ldb, rows, cols, kd, rb, cb, (kc + 1) * 16);
+        } else if (t + 1 < ntile) {
+          const int rn = ((t + 1) / nct) * 32, cnb = ((t + 1) % nct) * 32;
+          frag_load(nxt, A, lda, B, ldb, rows, cols, kd, rn, cnb, 0);
+          if (MODE == 0) ctile_load(cn, C, ldc, rows, cols, rn, cnb);
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < NB; kk += 4) {
-          const int kr = kk + kq;
-          const double a0 = sh.sL[(wi + col) * (NB + 1) + kr];
-          const double a1 = sh.sL[(wi + 16 + col) * (NB + 1) + kr];
-          const double b0 = sh.sU[kr * TB + wj + col];
-          const double b1 = sh.sU[kr * TB + wj + 16 + col];
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        __syncthreads();
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  cur.a[s][x], cur.b[s][y], acc[x][y], 0, 0, 0);
+        cur = nxt;
       }
-      // FP64 16x16x4 result: D[i][j] at j = lane % 16, i = lane / 16 + 4 r
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = rb + wi + 16 * x + kq + 4 * r;
-            const int j = cb + wj + 16 * y + col;
+            const int i = rb + 16 * x + kq + 4 * r, j = cb + 16 * y + col;
             if (i >= rows || j >= cols) continue;
-            double *cp = C + (int64_t)i * ldc + j;
-            const double v = acc[x][y][r];
-            if (mode == 0)
-              *cp -= v;
-            else if (mode == 1)
-              *cp = v + (i == j ? 1.0 : 0.0);
-            else
-              *cp = v;
+            double v = acc[x][y][r];
+            if (MODE == 0) v = cv[x][y][r] - v;
+            if (MODE == 1 && i == j) v += 1.0;
+            C[(int64_t)i * ldc + j] = v;
           }
+      if (MODE == 0) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cv[x][y][r] = cn[x][y][r];
+      }
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
-// Panel factorisation with partial pivoting, rows [j0, na), columns
-// [j0, j0 + jb), straight in global memory (any height).  Records the
-// pivot rows in sh.piv and sets sh.flag on an exactly zero pivot.
-__device__ void panel_global(double *A, int na, int ld, int j0, int jb,
-                             WgScratch &sh) {
-  const int tid = threadIdx.x;
+// ---------------------------------------------------------------------------
+// LU with partial pivoting.
+
+// Factor columns [j0, j0 + jb) of rows [j0, na) in place; pivots -> W.piv.
+// Returns 1 if a pivot was zero or not a number.
+__device__ int wave_panel(double *A, int na, int ld, int j0, int jb,
+                          WaveLds &W) {
+  const int lane = lane_id();
+  int flag = 0;
+#pragma unroll 1
   for (int jj = 0; jj < jb; ++jj) {
     const int col = j0 + jj;
-    double best = -1.0;
+    double ba = -1.0, bv = 0.0;
     int bi = na;
-    for (int r = col + tid; r < na; r += MT) {
-      const double v = fabs(A[(int64_t)r * ld + col]);
-      if (v > best) {
-        best = v;
-        bi = r;
+    for (int r0 = col + lane; r0 < na; r0 += UNR * WT) {
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int r = r0 + u * WT;
+        v[u] = r < na ? A[(int64_t)r * ld + col] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int r = r0 + u * WT;
+        if (r < na && fabs(v[u]) > ba) {
+          ba = fabs(v[u]);
+          bv = v[u];
+          bi = r;
+        }
       }
     }
-    const int pr = wg_argmax(best, bi, sh);
-    if (tid == 0) sh.piv[jj] = pr;
-    if (pr != col && tid < jb) {
-      double *x = A + (int64_t)col * ld + j0 + tid;
-      double *y = A + (int64_t)pr * ld + j0 + tid;
-      const double t = *x;
-      *x = *y;
-      *y = t;
+    wave_argmax(ba, bv, bi);
+    int pr = bi;
+    double pv = bv;
+    if (pr >= na) {  // every candidate is NaN
+      pr = col;
+      pv = __builtin_nan("");
     }
-    __syncthreads();
-    const double piv = A[(int64_t)col * ld + col];
-    if (piv == 0.0 && tid == 0) sh.flag = 1;
-    const double inv = 1.0 / piv;
-    for (int r = col + 1 + tid; r < na; r += MT) {
-      double *row = A + (int64_t)r * ld;
-      const double lv = row[col] * inv;
-      row[col] = lv;
-      const double *prow = A + (int64_t)col * ld;
-      for (int c = col + 1; c < j0 + jb; ++c) row[c] = fma(-lv, prow[c], row[c]);
+    if (lane == 0) W.piv[jj] = pr;
+    // swap the panel parts of rows col and pr; lane q keeps the new pivot
+    // row's element of panel column j0 + q
+    double prow = 0.0;
+    if (lane < jb) {
+      double *x = A + (int64_t)col * ld + j0 + lane;
+      double *y = A + (int64_t)pr * ld + j0 + lane;
+      const double xv = *x, yv = *y;
+      prow = yv;
+      if (pr != col) {
+        *x = yv;
+        *y = xv;
+      }
     }
-    __syncthreads();
+    wave_sync();
+    if (!(fabs(pv) > 0.0)) flag = 1;
+    const double inv = 1.0 / pv;
+    double pc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) pc[q] = read_lane(prow, q);
+    // eliminate below the pivot, two rows per lane per batch
+    for (int r0 = col + 1 + lane; r0 < na; r0 += 2 * WT) {
+      const int r1 = r0 + WT;
+      double *p0 = A + (int64_t)r0 * ld + j0;
+      double *p1 = A + (int64_t)r1 * ld + j0;
+      const bool h1 = r1 < na;
+      double x0[NB], x1[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const bool in = q >= jj && q < jb;
+        x0[q] = in ? p0[q] : 0.0;
+        x1[q] = (in && h1) ? p1[q] : 0.0;
+      }
+      double l0 = 0.0, l1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q == jj) {
+          l0 = x0[q] * inv;
+          l1 = x1[q] * inv;
+        }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (q < jj || q >= jb) continue;
+        const double v0 = q == jj ? l0 : fma(-l0, pc[q], x0[q]);
+        const double v1 = q == jj ? l1 : fma(-l1, pc[q], x1[q]);
+        p0[q] = v0;
+        if (h1) p1[q] = v1;
+      }
+    }
+    wave_sync();
   }
+  return flag;
 }
 
-// Same factorisation for panels of at most 2*MT rows, held in registers:
-// thread t owns local rows t and t + MT; the pivot row is exchanged and
-// broadcast through LDS, so a column costs a few barriers and no global
-// memory round trip.
-__device__ void panel_regs(double *A, int na, int ld, int j0, int jb,
-                           WgScratch &sh) {
-  const int tid = threadIdx.x;
-  const int m = na - j0;
-  double v[2][NB];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int rl = tid + q * MT;
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-      v[q][c] = (rl < m && c < jb) ? A[(int64_t)(j0 + rl) * ld + j0 + c] : 0.0;
+// Invert the 16 x 16 diagonal block held in W.T into W.Ti (lanes 0..15
+// each form one column of the inverse, keeping it in W.Ti).  lower: unit
+// lower triangle (L11); otherwise upper triangle with its diagonal (U11).
+// Padded rows and columns must hold the identity.
+__device__ void wave_tile_invert(WaveLds &W, bool lower) {
+  const int lane = lane_id();
+  if (lane < NB) {
+    const int j = lane;
+    if (lower) {
+#pragma unroll 1
+      for (int q = 0; q < NB; ++q) {
+        double s = q == j ? 1.0 : 0.0;
+        for (int p = j; p < q; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
+        W.Ti[q][j] = s;
+      }
+    } else {
+#pragma unroll 1
+      for (int q = NB - 1; q >= 0; --q) {
+        double s = q == j ? 1.0 : 0.0;
+        for (int p = q + 1; p <= j; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
+        W.Ti[q][j] = q <= j ? s / W.T[q][q] : 0.0;
+      }
+    }
   }
+  wave_sync();
+}
+
+// Columns [c0, c1) of rows j0 .. j0+15:  X <- Ti X, where row q of X is
+// taken from row src[q] (moves) or row j0 + q (src == nullptr), and rows
+// opos[m] receive rows osrc[m] (m < nout) in the same pass.  16 x 16 FP64
+// MFMA blocks, four column blocks per batch; every load of a batch is
+// issued before any store, so sources and destinations may coincide.
+__device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
+                                int c1, const WaveLds &W, bool moves) {
+  const int lane = lane_id();
+  const int col = lane & 15, kq = lane >> 4;
+  double ainv[4];
 #pragma unroll
-  for (int jj = 0; jj < NB; ++jj) {
-    if (jj >= jb) break;
-    double best = -1.0;
-    int bi = na;
+  for (int s = 0; s < 4; ++s) ainv[s] = W.Ti[col][4 * s + kq];
+  int srow[4], orow[4], drow[4];
+  bool sv[4], ov[4];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int rl = tid + q * MT;
-      if (rl < m && rl >= jj) {
-        const double a = fabs(v[q][jj]);
-        if (a > best) {
-          best = a;
-          bi = j0 + rl;
+  for (int s = 0; s < 4; ++s) {
+    const int q = 4 * s + kq;
+    sv[s] = q < jb;
+    srow[s] = moves ? (sv[s] ? W.srcp[q] : 0) : j0 + q;
+    ov[s] = moves && q < W.nout;
+    orow[s] = ov[s] ? W.osrc[q] : 0;
+    drow[s] = ov[s] ? W.opos[q] : 0;
+  }
+  constexpr int CB = 4;
+  for (int cb = c0; cb < c1; cb += 16 * CB) {
+    double b[CB][4], y[CB][4];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const int c = cb + 16 * u + col;
+      const bool cv = c < c1;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        b[u][s] = (cv && sv[s]) ? A[(int64_t)srow[s] * ld + c] : 0.0;
+        y[u][s] = (cv && ov[s]) ? A[(int64_t)orow[s] * ld + c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ainv[s], b[u][s], acc, 0,
+                                                   0, 0);
+      const int c = cb + 16 * u + col;
+      if (c < c1) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if (ov[s]) A[(int64_t)drow[s] * ld + c] = y[u][s];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = kq + 4 * r;  // FP64 result row
+          if (q < jb) A[(int64_t)(j0 + q) * ld + c] = acc[r];
         }
       }
     }
-    const int pr = wg_argmax(best, bi, sh);
-    const int prl = pr - j0;
-    // owner of the pivot row publishes it; owner of row jj publishes its own
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (tid + q * MT == prl) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) sh.rowbuf[0][c] = v[q][c];
-      }
-    }
-    if (tid == jj) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) sh.rowbuf[1][c] = v[0][c];
-    }
-    if (tid == 0) sh.piv[jj] = pr;
-    __syncthreads();
-    if (prl != jj) {
-      if (tid == jj) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) v[0][c] = sh.rowbuf[0][c];
-      }
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (tid + q * MT == prl) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) v[q][c] = sh.rowbuf[1][c];
-        }
-      }
-    }
-    const double piv = sh.rowbuf[0][jj];
-    if (piv == 0.0 && tid == 0) sh.flag = 1;
-    const double inv = 1.0 / piv;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int rl = tid + q * MT;
-      if (rl < m && rl > jj) {
-        const double lv = v[q][jj] * inv;
-        v[q][jj] = lv;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c > jj) v[q][c] = fma(-lv, sh.rowbuf[0][c], v[q][c]);
-      }
-    }
-    __syncthreads();
   }
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int rl = tid + q * MT;
-    if (rl < m) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < jb) A[(int64_t)(j0 + rl) * ld + j0 + c] = v[q][c];
-    }
-  }
-  __syncthreads();
+  wave_sync();
 }
 
 // Solve A X = B in place for the na x na matrix in columns [0, na) of rows
-// [0, na) (leading dimension ld) with right-hand sides in columns
-// [na, na + nrhs).  On return the RHS columns hold X.  Returns nonzero if a
-// pivot was exactly zero.
-__device__ int wg_lu_solve(double *A, int na, int ld, int nrhs,
-                           WgScratch &sh) {
-  const int tid = threadIdx.x;
+// [0, na) (leading dimension ld), right-hand sides in columns
+// [na, na + nrhs); on return those columns hold X.  Wavefront-local.
+// Returns nonzero if a pivot was zero or not a number.
+__device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
+  const int lane = lane_id();
   const int ntot = na + nrhs;
-  if (tid == 0) sh.flag = 0;
-  __syncthreads();
+  int flag = 0;
   for (int j0 = 0; j0 < na; j0 += NB) {
     const int jb = min(NB, na - j0);
-    // --- panel factorisation, columns [j0, j0 + jb)
-    if (na - j0 <= 2 * MT)
-      panel_regs(A, na, ld, j0, jb, sh);
-    else
-      panel_global(A, na, ld, j0, jb, sh);
-    // --- row interchanges and L11^-1 on the columns right of the panel
-    for (int c = j0 + jb + tid; c < ntot; c += MT) {
-      double x[NB];
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        if (jj < jb) {
-          const int pr = sh.piv[jj];
-          const int rr = j0 + jj;
-          if (pr != rr) {
-            double *a = A + (int64_t)rr * ld + c;
-            double *b = A + (int64_t)pr * ld + c;
-            const double t = *a;
-            *a = *b;
-            *b = t;
+    flag |= wave_panel(A, na, ld, j0, jb, W);
+    // row moves of this panel's interchanges (they act in sequence; a panel
+    // row, once passed, is never moved again)
+    if (lane == 0) {
+      int nout = 0;
+      for (int q = 0; q < jb; ++q) W.srcp[q] = j0 + q;
+      for (int q = 0; q < jb; ++q) {
+        const int p = W.piv[q];
+        if (p == j0 + q) continue;
+        int *slot;
+        if (p < j0 + jb) {
+          slot = &W.srcp[p - j0];
+        } else {
+          int m = 0;
+          while (m < nout && W.opos[m] != p) ++m;
+          if (m == nout) {
+            W.opos[m] = p;
+            W.osrc[m] = p;
+            ++nout;
           }
+          slot = &W.osrc[m];
         }
+        const int t = W.srcp[q];
+        W.srcp[q] = *slot;
+        *slot = t;
       }
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
-        x[jj] = (jj < jb) ? A[(int64_t)(j0 + jj) * ld + c] : 0.0;
-#pragma unroll
-      for (int jj = 1; jj < NB; ++jj) {
-        if (jj < jb) {
-          double s = x[jj];
-          const double *lrow = A + (int64_t)(j0 + jj) * ld + j0;
-#pragma unroll
-          for (int ii = 0; ii < NB; ++ii)
-            if (ii < jj) s = fma(-lrow[ii], x[ii], s);
-          x[jj] = s;
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
-        if (jj < jb) A[(int64_t)(j0 + jj) * ld + c] = x[jj];
+      W.nout = nout;
     }
-    __syncthreads();
-    // --- trailing update
+    // L11 (unit lower; identity padding) -> its inverse in the LDS tile
+    for (int q = lane; q < NB * NB; q += WT) {
+      const int i = q / NB, j = q % NB;
+      double v = i == j ? 1.0 : 0.0;
+      if (i < jb && j < i) v = A[(int64_t)(j0 + i) * ld + j0 + j];
+      W.T[i][j] = v;
+    }
+    wave_sync();
+    wave_tile_invert(W, true);
+    // columns right of the panel: row moves, then L11^-1
+    wave_tile_apply(A, ld, j0, jb, j0 + jb, ntot, W, true);
     const int r0 = j0 + jb;
-    if (r0 < na) {
-      wg_gemm(A + (int64_t)r0 * ld + r0, ld, A + (int64_t)r0 * ld + j0, ld,
-              A + (int64_t)j0 * ld + r0, ld, na - r0, ntot - r0, jb, 0, sh);
-    }
+    if (r0 < na)
+      wave_gemm<0>(A + (int64_t)r0 * ld + r0, ld, A + (int64_t)r0 * ld + j0,
+                   ld, A + (int64_t)j0 * ld + r0, ld, na - r0, ntot - r0, jb);
   }
-  // --- back substitution U X = B' on the RHS columns
+  // back substitution U X = B' on the right-hand sides
   for (int j0 = ((na - 1) / NB) * NB; j0 >= 0; j0 -= NB) {
     const int jb = min(NB, na - j0);
-    for (int c = na + tid; c < ntot; c += MT) {
-      double x[NB];
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
-        x[jj] = (jj < jb) ? A[(int64_t)(j0 + jj) * ld + c] : 0.0;
-#pragma unroll
-      for (int jj = NB - 1; jj >= 0; --jj) {
-        if (jj < jb) {
-          const double *urow = A + (int64_t)(j0 + jj) * ld + j0;
-          double s = x[jj];
-#pragma unroll
-          for (int ii = 0; ii < NB; ++ii)
-            if (ii > jj && ii < jb) s = fma(-urow[ii], x[ii], s);
-          x[jj] = s / urow[jj];
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj)
-        if (jj < jb) A[(int64_t)(j0 + jj) * ld + c] = x[jj];
+    // U11 (identity padding) -> its inverse
+    for (int q = lane; q < NB * NB; q += WT) {
+      const int i = q / NB, j = q % NB;
+      double v = i == j ? 1.0 : 0.0;
+      if (i < jb && j < jb && j >= i) v = A[(int64_t)(j0 + i) * ld + j0 + j];
+      W.T[i][j] = v;
     }
-    __syncthreads();
-    if (j0 > 0) {
-      wg_gemm(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0, nrhs,
-              jb, 0, sh);
-    }
+    wave_sync();
+    wave_tile_invert(W, false);
+    wave_tile_apply(A, ld, j0, jb, na, ntot, W, false);
+    if (j0 > 0)
+      wave_gemm<0>(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0,
+                   nrhs, jb);
   }
-  __syncthreads();
-  return sh.flag;
+  return flag;
 }
 
-// Omega(t, u) += 2g sum_{i in t, j in u, i,j < no} (Y_ij^2 + Q_ij^2)
-__device__ void accumulate_omega(const SymDev &S, int n_out, const double *Y,
-                                 const double *Q, int ld, int no, double *om,
-                                 int &nonfinite) {
-  const int tid = threadIdx.x;
-  const int NT = S.n_target;
-  for (int t = 0; t < NT; ++t) {
-    const int ta = S.tptr[t], tb = S.tptr[t + 1];
-    if (ta == tb || S.tch[ta] >= no) continue;  // lists ascending
-    for (int u = t + tid; u < NT; u += MT) {
-      const int ua = S.tptr[u], ub = S.tptr[u + 1];
-      if (ua == ub || S.tch[ua] >= no) continue;
-      double sum = 0.0;
-      for (int x = ta; x < tb; ++x) {
-        const int i = S.tch[x];
-        if (i >= no) break;
-        for (int y = ua; y < ub; ++y) {
-          const int j = S.tch[y];
-          if (j >= no) break;
-          const double yv = Y[(int64_t)i * ld + j];
-          const double qv = Q[(int64_t)i * ld + j];
-          sum += yv * yv + qv * qv;
-        }
+// ---------------------------------------------------------------------------
+// Collision strengths.
+//
+// V_ij = Y_ij^2 + Q_ij^2 over the open block; Omega(t, u) += 2g sum_{i in t,
+// j in u} V_ij.  When every target level holds one channel the sum is a
+// relabelling of V's upper triangle; otherwise it is G^T V G with the 0/1
+// channel-to-level matrix G (two MFMA products).
+
+__device__ inline int64_t omega_index(int t, int u, int n_out) {
+  if (t > u) {
+    const int x = t;
+    t = u;
+    u = x;
+  }
+  return (int64_t)t * n_out - ((int64_t)t * (t - 1)) / 2 + (u - t);
+}
+
+// Start of row i of the row-major upper triangle of an m x m matrix.
+__device__ inline int64_t tri_row_start(int i, int m) {
+  return (int64_t)i * m - ((int64_t)i * (i - 1)) / 2;
+}
+
+// Row i and column j >= i of entry p of that triangle.
+__device__ inline void tri_decode(int64_t p, int m, int &i, int &j) {
+  const double b = 2.0 * m + 1.0;
+  int r = (int)((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
+  r = max(0, min(r, m - 1));
+  while (r > 0 && tri_row_start(r, m) > p) --r;
+  while (r + 1 < m && tri_row_start(r + 1, m) <= p) ++r;
+  i = r;
+  j = r + (int)(p - tri_row_start(r, m));
+}
+
+// Aug holds Q in columns [0, no) and Y in columns [no, 2 no); Kb (ld n) is
+// free scratch.  Returns 1 if a contribution was not finite.
+__device__ int wave_omega(const SymDev &S, int n_out, double *Aug, int ld,
+                          double *Kb, int no, double *om) {
+  const int lane = lane_id();
+  const double g2 = 2.0 * S.g;
+  int nonfinite = 0;
+  if (S.ntu == S.n) {
+    // one channel per level: walk the open block's upper triangle
+    const int64_t npair = (int64_t)no * (no + 1) / 2;
+    for (int64_t p0 = lane; p0 < npair; p0 += UNR * WT) {
+      int ii[UNR], jj[UNR], ti[UNR], tj[UNR];
+      double yv[UNR], qv[UNR], ov[UNR];
+      int64_t oi[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int64_t p = p0 + (int64_t)u * WT;
+        ii[u] = 0;
+        jj[u] = 0;
+        if (p < npair) tri_decode(p, no, ii[u], jj[u]);
       }
-      sum *= 2.0 * S.g;
-      if (!isfinite(sum)) nonfinite = 1;
-      om[t * n_out - (t * (t - 1)) / 2 + (u - t)] += sum;
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const bool in = p0 + (int64_t)u * WT < npair;
+        const double *row = Aug + (int64_t)ii[u] * ld;
+        ti[u] = in ? S.tgt[ii[u]] : 0;
+        tj[u] = in ? S.tgt[jj[u]] : 0;
+        qv[u] = in ? row[jj[u]] : 0.0;
+        yv[u] = in ? row[no + jj[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const bool in = p0 + (int64_t)u * WT < npair;
+        oi[u] = omega_index(ti[u], tj[u], n_out);
+        ov[u] = in ? om[oi[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (p0 + (int64_t)u * WT >= npair) continue;
+        const double v = g2 * (yv[u] * yv[u] + qv[u] * qv[u]);
+        if (!isfinite(v)) nonfinite = 1;
+        om[oi[u]] = ov[u] + v;
+      }
+    }
+    return nonfinite;
+  }
+  // V into columns [0, no), both triangles
+  const int nsq = no * no;
+  for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+    double yv[UNR], qv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      const double *row = Aug + (int64_t)(q / no) * ld;
+      qv[u] = q < nsq ? row[q % no] : 0.0;
+      yv[u] = q < nsq ? row[no + q % no] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q < nsq)
+        Aug[(int64_t)(q / no) * ld + q % no] = yv[u] * yv[u] + qv[u] * qv[u];
     }
   }
+  wave_sync();
+  const int nt = S.ntu;
+  // W1 = G^T V (nt x no) into Kb, then Omega_u = W1 G (nt x nt) into Aug
+  wave_gemm<2>(Kb, S.n, S.GT, S.n, Aug, ld, nt, no, no);
+  wave_gemm<2>(Aug, ld, Kb, S.n, S.G, nt, nt, nt, no);
+  const int64_t npair = (int64_t)nt * (nt + 1) / 2;
+  for (int64_t p0 = lane; p0 < npair; p0 += UNR * WT) {
+    int ta[UNR], tb[UNR];
+    double v[UNR], ov[UNR];
+    int64_t oi[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int64_t p = p0 + (int64_t)u * WT;
+      ta[u] = 0;
+      tb[u] = 0;
+      if (p < npair) tri_decode(p, nt, ta[u], tb[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const bool in = p0 + (int64_t)u * WT < npair;
+      v[u] = in ? Aug[(int64_t)ta[u] * ld + tb[u]] : 0.0;
+      const int t = in ? S.ut[ta[u]] : 0, w = in ? S.ut[tb[u]] : 0;
+      oi[u] = omega_index(t, w, n_out);
+      ov[u] = in ? om[oi[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      if (p0 + (int64_t)u * WT >= npair) continue;
+      const double c = g2 * v[u];
+      if (!isfinite(c)) nonfinite = 1;
+      om[oi[u]] = ov[u] + c;
+    }
+  }
+  return nonfinite;
 }
+
+// ---------------------------------------------------------------------------
 
 // Channel functions of symmetry S at energy Ee into ch[0..n), sorted order.
-__device__ int channel_functions(const SymDev &S, double Ee, ChanSlot *ch) {
+__device__ int wave_channel_functions(const SymDev &S, double Ee,
+                                      ChanSlot *ch) {
+  const int lane = lane_id();
   int bits = 0;
-  for (int i = threadIdx.x; i < S.n; i += MT) {
+  for (int i = lane; i < S.n; i += WT) {
     const double diff = Ee - S.e_thr[i];
     ChanSlot c;
     if (diff > 0.0) {
@@ -432,7 +626,7 @@ __device__ int channel_functions(const SymDev &S, double Ee, ChanSlot *ch) {
   return bits;
 }
 
-__device__ int count_open(const SymDev &S, double Ee) {
+__device__ inline int count_open(const SymDev &S, double Ee) {
   int lo = 0, hi = S.n;  // thresholds strictly below E
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -444,133 +638,195 @@ __device__ int count_open(const SymDev &S, double Ee) {
   return lo;
 }
 
-struct MatchSmem {
-  WgScratch sh;
-  int rank[kMaxChanLds];
-  int bits;
-};
+// Copy a rows x cols block (row-major source ld sl, destination ld dl) with
+// batched loads.
+__device__ inline void wave_copy(double *dst, int dl, const double *src,
+                                 int sl, int rows, int cols) {
+  const int lane = lane_id();
+  const int nq = rows * cols;
+  for (int q0 = lane; q0 < nq; q0 += UNR * WT) {
+    double v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      v[u] = q < nq ? src[(int64_t)(q / cols) * sl + q % cols] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q < nq) dst[(int64_t)(q / cols) * dl + q % cols] = v[u];
+    }
+  }
+}
 
-// One symmetry at one energy.  Returns RM_E_* bits.
-__device__ int match_one(const MatchLaunch &L, int s, int e, MatchSmem &sm) {
+// One symmetry at one energy, one wavefront.  Returns RM_E_* bits.
+__device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
   const SymDev &S = L.syms[s];
-  const int tid = threadIdx.x;
+  const int lane = lane_id();
   const int n = S.n;
   const int ld = 2 * n;
   const double Ee = L.E[e];
   double *Aug = L.work + (int64_t)e * L.work_estride + L.work_off[s];
   double *Kb = Aug + (int64_t)2 * n * n;
+  ChanSlot *ch = L.chan + (int64_t)e * L.chan_estride + L.chan_off[s];
+  int *rank = (int *)ch;  // reused once the channel slots are consumed
   const int no = count_open(S, Ee);
-  int stat = 0;
-  if (tid == 0) sm.bits = 0;
-  __syncthreads();
-  if (L.n_open_out && s == 0 && tid == 0) L.n_open_out[e] = no;
+  if (L.n_open_out && s == 0 && lane == 0) L.n_open_out[e] = no;
   if (no == 0) {
     if (L.K_out && s == 0) {
       double *Ko = L.K_out + (int64_t)e * n * n;
-      for (int idx = tid; idx < n * n; idx += MT) Ko[idx] = 0.0;
+      for (int idx = lane; idx < n * n; idx += WT) Ko[idx] = 0.0;
     }
-    __syncthreads();
     return RM_E_NO_OPEN;
   }
-  // rank of each open channel among the open channels' input indices
-  for (int i = tid; i < no; i += MT) {
-    const int pi = S.perm[i];
-    int r = 0;
-    for (int j = 0; j < no; ++j) r += (S.perm[j] < pi);
-    sm.rank[i] = r;
-  }
+  int bits = 0;
   const bool k_given = (L.K_in != nullptr) && s == 0;
   if (!k_given) {
-    ChanSlot *ch = L.chan + (int64_t)e * L.chan_estride + L.chan_off[s];
-    const int b = channel_functions(S, Ee, ch);
-    if (b) atomicOr(&sm.bits, b);
-    __syncthreads();
-    for (int idx = tid; idx < n * n; idx += MT) {
-      const int i = idx / n, j = idx % n;
-      double *a = Aug + (int64_t)i * ld + j;
-      const double rij = *a;
-      const ChanSlot cj = ch[j];
-      *a = (i == j ? ch[i].d1 : 0.0) - rij * cj.d2;
-      if (j < no) Aug[(int64_t)i * ld + n + j] = rij * cj.asp - (i == j ? ch[i].s : 0.0);
+    bits |= wave_channel_functions(S, Ee, ch);
+    wave_sync();
+    // [D1 - R D2 | R[:, P] diag(a s'_P) - diag(s_P)], R already in place
+    const int nsq = n * n;
+    for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+      double r[UNR], d2[UNR], asp[UNR], d1[UNR], sv[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        const bool in = q < nsq;
+        const int i = q / n, j = q % n;
+        r[u] = in ? Aug[(int64_t)i * ld + j] : 0.0;
+        d2[u] = in ? ch[j].d2 : 0.0;
+        asp[u] = (in && j < no) ? ch[j].asp : 0.0;
+        d1[u] = (in && i == j) ? ch[i].d1 : 0.0;
+        sv[u] = (in && i == j) ? ch[i].s : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        if (q >= nsq) continue;
+        const int i = q / n, j = q % n;
+        Aug[(int64_t)i * ld + j] = d1[u] - r[u] * d2[u];
+        if (j < no) Aug[(int64_t)i * ld + n + j] = r[u] * asp[u] - sv[u];
+      }
     }
-    __syncthreads();
-    if (wg_lu_solve(Aug, n, ld, no, sm.sh)) stat |= RM_E_SINGULAR;
+    wave_sync();
+    if (wave_lu_solve(Aug, n, ld, no, W)) bits |= RM_E_SINGULAR;
     // K = sym(Z[0:no, 0:no]) -> Kb (ld n)
-    for (int idx = tid; idx < no * no; idx += MT) {
-      const int i = idx / no, j = idx % no;
-      Kb[(int64_t)i * n + j] =
-          0.5 * (Aug[(int64_t)i * ld + n + j] + Aug[(int64_t)j * ld + n + i]);
-    }
-  } else {
-    __syncthreads();
-    const double *Ki = L.K_in + (int64_t)e * n * n;  // input order, ld n
-    for (int idx = tid; idx < no * no; idx += MT) {
-      const int i = idx / no, j = idx % no;
-      Kb[(int64_t)i * n + j] = Ki[(int64_t)sm.rank[i] * n + sm.rank[j]];
+    const int nk = no * no;
+    for (int q0 = lane; q0 < nk; q0 += UNR * WT) {
+      double a[UNR], b[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        const int i = q / no, j = q % no;
+        a[u] = q < nk ? Aug[(int64_t)i * ld + n + j] : 0.0;
+        b[u] = q < nk ? Aug[(int64_t)j * ld + n + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        if (q < nk) Kb[(int64_t)(q / no) * n + q % no] = 0.5 * (a[u] + b[u]);
+      }
     }
   }
-  __syncthreads();
+  // rank of each open channel among the open channels' input indices
+  if (L.K_out || k_given) {
+    wave_sync();
+    for (int i = lane; i < no; i += WT) {
+      const int pi = S.perm[i];
+      int r = 0;
+#pragma unroll 8
+      for (int j = 0; j < no; ++j) r += (S.perm[j] < pi);
+      rank[i] = r;
+    }
+  }
+  wave_sync();
+  if (k_given) {
+    const double *Ki = L.K_in + (int64_t)e * n * n;  // input order, ld n
+    const int nk = no * no;
+    for (int q0 = lane; q0 < nk; q0 += UNR * WT) {
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        v[u] = q < nk ? Ki[(int64_t)rank[q / no] * n + rank[q % no]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        if (q < nk) Kb[(int64_t)(q / no) * n + q % no] = v[u];
+      }
+    }
+    wave_sync();
+  }
   int nonfinite = 0;
   if (L.K_out && s == 0) {
     double *Ko = L.K_out + (int64_t)e * n * n;
-    for (int idx = tid; idx < n * n; idx += MT) {
+    for (int idx = lane; idx < n * n; idx += WT) {
       const int r = idx / n, c = idx % n;
       if (r >= no || c >= no) Ko[idx] = 0.0;
     }
-    for (int idx = tid; idx < no * no; idx += MT) {
-      const int i = idx / no, j = idx % no;
-      const double v = Kb[(int64_t)i * n + j];
-      if (!isfinite(v)) nonfinite = 1;
-      Ko[(int64_t)sm.rank[i] * n + sm.rank[j]] = v;
+    const int nk = no * no;
+    for (int q0 = lane; q0 < nk; q0 += UNR * WT) {
+      double v[UNR];
+      int ri[UNR], rj[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        const bool in = q < nk;
+        v[u] = in ? Kb[(int64_t)(q / no) * n + q % no] : 0.0;
+        ri[u] = in ? rank[q / no] : 0;
+        rj[u] = in ? rank[q % no] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (q0 + u * WT >= nk) continue;
+        if (!isfinite(v[u])) nonfinite = 1;
+        Ko[(int64_t)ri[u] * n + rj[u]] = v[u];
+      }
     }
   }
   if (L.do_t) {
-    // Pm = 1 + K K in columns [0, no), RHS K in columns [no, 2 no)
-    wg_gemm(Aug, ld, Kb, n, Kb, n, no, no, no, 1, sm.sh);
-    for (int idx = tid; idx < no * no; idx += MT) {
-      const int i = idx / no, j = idx % no;
-      Aug[(int64_t)i * ld + no + j] = Kb[(int64_t)i * n + j];
-    }
-    __syncthreads();
-    if (wg_lu_solve(Aug, no, ld, no, sm.sh)) stat |= RM_E_SINGULAR;
+    // Pm = 1 + K K in columns [0, no), right-hand side K in [no, 2 no)
+    wave_gemm<1>(Aug, ld, Kb, n, Kb, n, no, no, no);
+    wave_copy(Aug + no, ld, Kb, n, no, no);
+    wave_sync();
+    if (wave_lu_solve(Aug, no, ld, no, W)) bits |= RM_E_SINGULAR;
     // Q = K Y into columns [0, no)
-    wg_gemm(Aug, ld, Kb, n, Aug + no, ld, no, no, no, 2, sm.sh);
+    wave_gemm<2>(Aug, ld, Kb, n, Aug + no, ld, no, no, no);
     if (L.omega)
-      accumulate_omega(S, L.n_target_out, Aug + no, Aug, ld, no,
-                       L.omega + (int64_t)e * L.omega_stride, nonfinite);
+      nonfinite |= wave_omega(S, L.n_target_out, Aug, ld, Kb, no,
+                              L.omega + (int64_t)e * L.omega_stride);
   }
-  if (nonfinite) atomicOr(&sm.bits, RM_E_NONFINITE);
-  __syncthreads();
-  stat |= sm.bits;
-  __syncthreads();
-  return stat;
+  if (nonfinite) bits |= RM_E_NONFINITE;
+  wave_sync();
+  return wave_or(bits);
 }
 
-__global__ __launch_bounds__(MT) void match_kernel(MatchLaunch L) {
-  __shared__ MatchSmem sm;
-  __shared__ int s_item;
-  const int tid = threadIdx.x;
-  int e = blockIdx.x;
+__global__ __launch_bounds__(WT *WPB) void match_kernel(MatchLaunch L) {
+  __shared__ WaveLds lds[WPB];
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int gw = blockIdx.x * WPB + wv;  // global wave id
+  int e = gw;
   for (;;) {
     if (L.counter) {
-      if (tid == 0) s_item = atomicAdd(L.counter, 1);
-      __syncthreads();
-      e = s_item;
-      __syncthreads();
+      int v = 0;
+      if (lane == 0) v = atomicAdd(L.counter, 1);
+      e = __builtin_amdgcn_readfirstlane(v);  // wavefront-uniform
     }
     if (e >= L.m) break;
     int stat = 0;
-    for (int s = 0; s < L.n_sym; ++s) stat |= match_one(L, s, e, sm);
-    if (tid == 0 && L.status && stat) atomicOr(&L.status[e], stat);
+    for (int s = 0; s < L.n_sym; ++s) stat |= match_one(L, s, e, lds[wv]);
+    if (lane == 0 && L.status && stat) atomicOr(&L.status[e], stat);
     if (!L.counter) break;
   }
 }
 
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st) {
   if (L.m <= 0) return hipSuccess;
-  unsigned grid = L.counter ? (unsigned)std::max(1, std::min(L.grid, L.m))
-                            : (unsigned)L.m;
-  hipLaunchKernelGGL(match_kernel, dim3(grid), dim3(MT), 0, st, L);
+  const int waves = L.counter ? std::max(1, std::min(L.grid * WPB, L.m)) : L.m;
+  const unsigned blocks = (unsigned)((waves + WPB - 1) / WPB);
+  hipLaunchKernelGGL(match_kernel, dim3(blocks), dim3(WT * WPB), 0, st, L);
   return hipGetLastError();
 }
 

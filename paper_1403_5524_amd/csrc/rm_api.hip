@@ -239,7 +239,9 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
     return fail(RM_ERR_ARG, "unknown precision %d", d.prec);
   if (!(d.near_delta >= 0.0) || !std::isfinite(d.near_delta))
     return fail(RM_ERR_ARG, "near_delta must be finite and >= 0");
-  if (d.near_delta == 0.0) d.near_delta = 1e-3;
+  // default near-pole window: split BF16 carries ~17 bits per operand, so
+  // poles within a few 1e-3 Ry still dominate its error; it takes 1e-2
+  if (d.near_delta == 0.0) d.near_delta = d.prec == RM_PREC_BF16X3 ? 1e-2 : 1e-3;
   if (d.refine_iters < 0) return fail(RM_ERR_ARG, "refine_iters < 0");
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");
@@ -724,7 +726,7 @@ static int validate_syms(const rm_sym_t *syms, int32_t n_sym, int32_t n_target) 
 static int free_sym(Sym *s) {
   if (!s) return RM_OK;
   void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
-                  s->l,      s->perm, s->inv, s->tptr, s->tch};
+                  s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete[] s->h_e_thr;
@@ -825,17 +827,30 @@ int rm_load_poles(const rm_poles_desc *d, rm_sym_t *out, void *stream) {
     lsrt[i] = d->l[perm[i]];
     ethr[i] = d->e_thr[perm[i]];
   }
-  // CSR of sorted positions per target level (ascending within a level)
-  std::vector<int32_t> tptr(n_target + 1, 0), tch(n);
-  for (int i = 0; i < n; ++i) tptr[(d->target ? d->target[perm[i]] : perm[i]) + 1]++;
-  for (int t = 0; t < n_target; ++t) tptr[t + 1] += tptr[t];
+  // target level of each sorted position; the levels that hold a channel
+  // and the 0/1 channel-to-level matrix over them
+  std::vector<int32_t> tgt(n), ut;
+  for (int i = 0; i < n; ++i) tgt[i] = d->target ? d->target[perm[i]] : perm[i];
   {
-    std::vector<int32_t> fillp(tptr.begin(), tptr.end() - 1);
+    std::vector<char> used(n_target, 0);
+    for (int i = 0; i < n; ++i) used[tgt[i]] = 1;
+    for (int t = 0; t < n_target; ++t)
+      if (used[t]) ut.push_back(t);
+  }
+  const int ntu = (int)ut.size();
+  std::vector<double> G, GT;
+  if (ntu < n) {
+    std::vector<int32_t> col_of(n_target, -1);
+    for (int a = 0; a < ntu; ++a) col_of[ut[a]] = a;
+    G.assign((size_t)n * ntu, 0.0);
+    GT.assign((size_t)n * ntu, 0.0);
     for (int i = 0; i < n; ++i) {
-      const int t = d->target ? d->target[perm[i]] : perm[i];
-      tch[fillp[t]++] = i;
+      const int a = col_of[tgt[i]];
+      G[(size_t)i * ntu + a] = 1.0;
+      GT[(size_t)a * n + i] = 1.0;
     }
   }
+  s->ntu = ntu;
   // staged W, pole-major, zero padded
   const int64_t npad = s->n_pad, hpad = s->nh_pad;
   std::vector<double> Wt((size_t)(npad * hpad), 0.0);
@@ -870,8 +885,12 @@ int rm_load_poles(const rm_poles_desc *d, rm_sym_t *out, void *stream) {
   RM_ALLOC_COPY(s->l, lsrt.data(), n * sizeof(int32_t));
   RM_ALLOC_COPY(s->perm, perm.data(), n * sizeof(int32_t));
   RM_ALLOC_COPY(s->inv, inv.data(), n * sizeof(int32_t));
-  RM_ALLOC_COPY(s->tptr, tptr.data(), (n_target + 1) * sizeof(int32_t));
-  RM_ALLOC_COPY(s->tch, tch.data(), n * sizeof(int32_t));
+  RM_ALLOC_COPY(s->tgt, tgt.data(), n * sizeof(int32_t));
+  RM_ALLOC_COPY(s->ut, ut.data(), ntu * sizeof(int32_t));
+  if (ntu < n) {
+    RM_ALLOC_COPY(s->G, G.data(), (size_t)n * ntu * sizeof(double));
+    RM_ALLOC_COPY(s->GT, GT.data(), (size_t)n * ntu * sizeof(double));
+  }
 #undef RM_ALLOC_COPY
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -973,8 +992,9 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
   const Sym &s = *sym;
   const int64_t ws = work_doubles(s.n);
   const int64_t C = std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)(8.0e9 / (8.0 * ws))));
-  DevBuf work, tabs;
+  DevBuf work, tabs, chan;
   if ((rc = dev_alloc(work, (size_t)(C * ws) * sizeof(double), st))) return rc;
+  if ((rc = dev_alloc(chan, (size_t)(C * s.n) * sizeof(ChanSlot), st))) return rc;
   if ((rc = dev_alloc(tabs, sizeof(SymDev) + sizeof(int64_t), st))) return rc;
   const SymDev sd = s.dev();
   const int64_t zero = 0;
@@ -993,6 +1013,9 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
     L.work = (double *)work.p;
     L.work_estride = ws;
     L.work_off = (const int64_t *)((char *)tabs.p + sizeof(SymDev));
+    L.chan = (ChanSlot *)chan.p;           // rank table of the K input
+    L.chan_estride = s.n;
+    L.chan_off = L.work_off;               // both offsets are zero
     L.K_in = K + c0 * nn;
     L.omega = omega + c0 * P;
     L.omega_stride = P;

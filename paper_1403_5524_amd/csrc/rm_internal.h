@@ -29,8 +29,11 @@ struct SymDev {
   const double *e_thr;        // [n] sorted
   const int32_t *l;           // [n] sorted order
   const int32_t *perm;        // [n] sorted position -> input channel
-  const int32_t *tptr;        // [n_target+1] CSR of sorted positions per
-  const int32_t *tch;         // [n]           target level
+  const int32_t *tgt;         // [n] sorted position -> target level
+  int ntu;                    // target levels that hold a channel
+  const int32_t *ut;          // [ntu] those levels, ascending
+  const double *G;            // [n][ntu] 0/1, channel -> used level
+  const double *GT;           // [ntu][n] its transpose
 };
 
 // A symmetry resident on one device.  Channels are stored sorted by
@@ -50,8 +53,10 @@ struct Sym {
   int32_t *l;
   int32_t *perm;
   int32_t *inv;         // [n] input channel -> sorted position
-  int32_t *tptr;
-  int32_t *tch;
+  int32_t *tgt;
+  int ntu;
+  int32_t *ut;
+  double *G, *GT;
   // host copies
   double *h_e_thr;      // [n] sorted
   int32_t *h_perm;
@@ -60,7 +65,8 @@ struct Sym {
     d.n = n; d.nh = nh; d.n_pad = n_pad; d.nh_pad = nh_pad;
     d.n_target = n_target; d.a = a; d.z = z; d.g = g;
     d.E_pole = E_pole; d.Wt = Wt; d.W32c = W32c; d.Whc = Whc; d.Wlc = Wlc;
-    d.e_thr = e_thr; d.l = l; d.perm = perm; d.tptr = tptr; d.tch = tch;
+    d.e_thr = e_thr; d.l = l; d.perm = perm; d.tgt = tgt;
+    d.ntu = ntu; d.ut = ut; d.G = G; d.GT = GT;
     return d;
   }
 };
@@ -123,7 +129,7 @@ int ps_energy_group(int variant);         // energies per work item
 // Tile items of one symmetry for a variant: (x, y) pairs, in order.
 void ps_tiles(const Sym &s, int variant, std::vector<std::pair<int, int>> &out);
 
-// Channel functions, matching, K, T and Omega: one workgroup per energy,
+// Channel functions, matching, K, T and Omega: one wavefront per energy,
 // looping over every symmetry (so it owns that energy's Omega row).  With a
 // counter the grid is persistent.
 struct MatchLaunch {
