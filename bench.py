@@ -22,6 +22,41 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # TFLOP/s dense MFMA
 PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
+# HBM bytes per energy from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE) of the 200-channel workload, scaled by what the same counters
+# read for a plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
+# A figure applies only while its kernel source is the one measured.
+PMC_TRAFFIC = {
+    "match_kernel": {"src": "paper_1403_5524_amd/csrc/match.hip",
+                     "sha256_16": "4f908263f1947deb",
+                     "bytes_per_energy": 30.79e6 + 17.03e6},
+    "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
+                     "sha256_16": "dc26a00f811564ec",
+                     "bytes_per_energy": 195.5e3 + 320.0e3},
+}
+
+
+def measured_traffic(key, energies):
+    """HBM bytes for `energies` energies, or None if the kernel changed."""
+    import hashlib
+    t = PMC_TRAFFIC.get(key)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha256_16"]:
+            return None
+    return t["bytes_per_energy"] * energies
+
+
+def match_flops(n, n_open):
+    """Algorithmic FP64 flops of matching one symmetry at energies with
+    n_open open channels: LU of the n x n matrix (2n^3/3), forward and back
+    substitution of n_open right-hand sides (2 n^2 n_open), K^2 and K Y
+    (2 n_open^3 each), LU and solve of 1 + K^2 (2/3 + 2) n_open^3."""
+    no = n_open.astype(np.float64)
+    f = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * no + (20.0 / 3.0) * no ** 3
+    return float(np.where(no > 0, f, 0.0).sum())
+
 
 def note(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -143,21 +178,31 @@ def main():
 
     pairs = 0.0
     flops_step = 0.0
+    mflops_step = 0.0
     for s in w.syms:
         n_open = np.searchsorted(np.sort(s.e_thr), w.mesh, side="left")
         pairs += float((n_open * (n_open + 1) // 2).sum())
         flops_step += float(s.n) * (s.n + 1) * s.n_poles * M   # symmetric
-    ps_ms, ps_launch = stage["polesum"]
-    ps_launch_per_step = ps_launch / args.steps
-    achieved = (flops_step * args.steps) / (ps_ms * 1e-3) / 1e12 \
-        if ps_ms > 0 else None
-    roof = {"bound": "mfma", "kernel": "polesum_%s" % args.prec,
-            "achieved": achieved, "peak": PEAK[args.prec], "unit": "TFLOP/s",
-            "frac": (achieved / PEAK[args.prec]) if achieved else None,
-            "traffic": None,
-            "flops_per_launch": flops_step / ps_launch_per_step
-            if ps_launch_per_step else None,
-            "avg_launch_ms": ps_ms / ps_launch if ps_launch else None}
+        mflops_step += match_flops(s.n, n_open)
+    kernels = {}
+    for key, flops, peak, st, tkey in (
+            ("polesum_%s" % args.prec, flops_step, PEAK[args.prec], "polesum",
+             "polesum_fp64" if args.prec == "fp64" else None),
+            ("match_kernel", mflops_step, PEAK["fp64"], "match",
+             "match_kernel")):
+        ms_tot, launches = stage[st]
+        lp = launches / args.steps if launches else 0
+        ach = flops * args.steps / (ms_tot * 1e-3) / 1e12 if ms_tot > 0 else None
+        traffic = measured_traffic(tkey, M / lp) if (tkey and lp) else None
+        kernels[key] = {
+            "bound": "mfma", "kernel": key, "achieved": ach, "peak": peak,
+            "unit": "TFLOP/s", "frac": ach / peak if ach else None,
+            "traffic": traffic,
+            "flops_per_launch": flops / lp if lp else None,
+            "avg_launch_ms": ms_tot / launches if launches else None,
+            "ms_per_step": ms_tot / args.steps}
+    dom = max(kernels.values(), key=lambda k: k["ms_per_step"])
+    roof = dict(dom)
     out = {
         "metric": "energy points/sec (K->Omega) at n=200 ch, N_H=8000; "
                   "max rel err of Omega vs FP64 oracle",
@@ -181,6 +226,7 @@ def main():
         "omega_per_s": pairs / (ms * 1e-3),
         "status_flagged": int((st != 0).sum()),
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stage.items()},
+        "kernels": kernels,
         "graph_ms_per_step": graph_ms,
         "graph_value": (M / (graph_ms * 1e-3)) if graph_ms else None,
         "roofline": roof,

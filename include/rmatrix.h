@@ -97,8 +97,7 @@ typedef struct {
 /* Options; a zero-initialised struct selects the defaults. */
 typedef struct {
   int32_t prec;          /* rm_precision                                   */
-  double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-3 (FP32),
-                            1e-2 (BF16X3)                                  */
+  double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-2           */
   int32_t solve_fp32;    /* must be 0: the matching solve is FP64 (a
                             nonzero value returns RM_ERR_ARG)              */
   int32_t refine_iters;  /* reserved, must be >= 0                         */

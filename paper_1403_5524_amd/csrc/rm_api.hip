@@ -239,9 +239,10 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
     return fail(RM_ERR_ARG, "unknown precision %d", d.prec);
   if (!(d.near_delta >= 0.0) || !std::isfinite(d.near_delta))
     return fail(RM_ERR_ARG, "near_delta must be finite and >= 0");
-  // default near-pole window: split BF16 carries ~17 bits per operand, so
-  // poles within a few 1e-3 Ry still dominate its error; it takes 1e-2
-  if (d.near_delta == 0.0) d.near_delta = d.prec == RM_PREC_BF16X3 ? 1e-2 : 1e-3;
+  // default near-pole window 1e-2 Ry: with 1e-3 the FP32-accumulated far
+  // sum still carries poles a few 1e-3 Ry away, whose large terms put
+  // Omega's error above 1e-4 near them
+  if (d.near_delta == 0.0) d.near_delta = 1e-2;
   if (d.refine_iters < 0) return fail(RM_ERR_ARG, "refine_iters < 0");
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");

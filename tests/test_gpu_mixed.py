@@ -56,8 +56,12 @@ def test_rmatrix_mixed_c2(env, prec):
 def test_sweep_mixed_c2_sample(env, prec):
     torch, nat, w, h = env
     s = w.syms[0]
+    # mesh energies, energies inside the FP64 window and energies just
+    # outside it (the largest terms the low-precision far sum carries)
     E = np.concatenate([w.mesh[wl.sample_indices(w.mesh.size, 16, seed=9)],
-                        _near_pole_energies(s, 4, 2e-6)])
+                        _near_pole_energies(s, 4, 2e-6),
+                        _near_pole_energies(s, 4, 1.2e-2),
+                        _near_pole_energies(s, 4, -1.5e-2)])
     log("sweep mixed prec=%d m=%d" % (prec, E.size))
     Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
     om, st = nat.rm_sweep_energies([h], 200, Et, nat.make_opts(prec=prec))
