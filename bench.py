@@ -185,12 +185,12 @@ def main():
         flops_step += float(s.n) * (s.n + 1) * s.n_poles * M   # symmetric
         mflops_step += match_flops(s.n, n_open)
     kernels = {}
-    for key, flops, peak, st, tkey in (
+    for key, flops, peak, stg, tkey in (
             ("polesum_%s" % args.prec, flops_step, PEAK[args.prec], "polesum",
              "polesum_fp64" if args.prec == "fp64" else None),
             ("match_kernel", mflops_step, PEAK["fp64"], "match",
              "match_kernel")):
-        ms_tot, launches = stage[st]
+        ms_tot, launches = stage[stg]
         lp = launches / args.steps if launches else 0
         ach = flops * args.steps / (ms_tot * 1e-3) / 1e12 if ms_tot > 0 else None
         traffic = measured_traffic(tkey, M / lp) if (tkey and lp) else None

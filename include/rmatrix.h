@@ -109,6 +109,19 @@ typedef struct {
  * (channels, poles, precision) and keep the fastest (in memory, and in the
  * file named by the environment variable RM_TUNE_CACHE when set). */
 #define RM_FLAG_AUTOTUNE 0x1u
+/* rm_opts.flags: the pole sum has two forms.  The scaled-W kernels
+ * contract (W diag(d)) W^T per energy tile and need nothing beyond W.  The
+ * pair form precomputes the products w_ik w_jk (i <= j) once per symmetry
+ * and precision, in device memory (8 bytes per pair and pole in FP64, 4 in
+ * FP32 or split BF16: 1.3 / 0.66 GB at 200 channels and 8000 poles; not
+ * formed above 8 GB, a quarter of free memory, or 32 GB over all live
+ * symmetries), and runs one GEMM over them.  Mixed precisions use the pair
+ * form where it fits, FP64 uses the scaled-W kernels (with
+ * RM_FLAG_AUTOTUNE, whichever times faster).  NO_PAIR_PRODUCTS forces the
+ * scaled-W kernels; PAIR_PRODUCTS forces the pair form where it fits.  The
+ * two may not be combined (RM_ERR_ARG). */
+#define RM_FLAG_NO_PAIR_PRODUCTS 0x2u
+#define RM_FLAG_PAIR_PRODUCTS 0x4u
 
 /* Load one symmetry (Sec. 3: the poles and amplitudes produced by the
  * inner-region diagonalisation; Sec. 6 Eq. 2: W is the shared operand of

@@ -186,6 +186,8 @@ int ps_energy_group(int variant) {
     case PS_MX_J16_E8: return 8;
     case PS_MX_J8_E8: return 8;
     case PS_MX_J16_E4: return 4;
+    case PS_PD: return 128;
+    case PS_PD64: return 64;
   }
   return 1;
 }
@@ -198,6 +200,10 @@ void ps_tiles(const Sym &s, int variant, std::vector<std::pair<int, int>> &out) 
       for (int J = I; J < nt; ++J) out.push_back({I, J});
     return;
   }
+  if (variant == PS_PD || variant == PS_PD64) {
+    for (int pb = 0; pb < s.np_pad / kPairBlock; ++pb) out.push_back({pb, 0});
+    return;
+  }
   const int jmax = (variant == PS_MX_J8_E8) ? 8 : 16;
   const int nblk = s.n_pad / 16;
   for (int IB = 0; IB < nblk; ++IB)
@@ -206,6 +212,8 @@ void ps_tiles(const Sym &s, int variant, std::vector<std::pair<int, int>> &out) 
 
 hipError_t launch_polesum(const PsLaunch &L, int variant, hipStream_t st) {
   if (L.n_items <= 0 || L.m <= 0) return hipSuccess;
+  if (variant == PS_PD) return launch_polesum_pd(L, st);
+  if (variant == PS_PD64) return launch_polesum_pd64(L, st);
   if (variant != PS_F64_T32_E16) return launch_polesum_mixed(L, variant, st);
   unsigned grid;
   if (L.counter)

@@ -246,7 +246,10 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
   if (d.refine_iters < 0) return fail(RM_ERR_ARG, "refine_iters < 0");
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");
-  if (d.flags & ~RM_FLAG_AUTOTUNE) return fail(RM_ERR_ARG, "unknown flags 0x%x", d.flags);
+  if (d.flags & ~(RM_FLAG_AUTOTUNE | RM_FLAG_NO_PAIR_PRODUCTS | RM_FLAG_PAIR_PRODUCTS))
+    return fail(RM_ERR_ARG, "unknown flags 0x%x", d.flags);
+  if ((d.flags & RM_FLAG_NO_PAIR_PRODUCTS) && (d.flags & RM_FLAG_PAIR_PRODUCTS))
+    return fail(RM_ERR_ARG, "RM_FLAG_NO_PAIR_PRODUCTS and RM_FLAG_PAIR_PRODUCTS together");
   if (d.solve_fp32 != 0)
     return fail(RM_ERR_ARG, "solve_fp32 is not available: the matching "
                             "solve runs in FP64");
@@ -418,7 +421,7 @@ static void tune_load() {
   if (!f) return;
   int n, nh, prec, v;
   while (std::fscanf(f, "%d %d %d %d", &n, &nh, &prec, &v) == 4)
-    if (v >= PS_MX_J16_E8 && v <= PS_MX_J16_E4) g_tuned[{n, nh, prec}] = v;
+    if (v >= PS_F64_T32_E16 && v <= PS_PD64) g_tuned[{n, nh, prec}] = v;
   std::fclose(f);
 }
 
@@ -437,13 +440,89 @@ static int default_variant(int prec) {
   return prec == RM_PREC_FP64 ? PS_F64_T32_E16 : PS_MX_J16_E8;
 }
 
+// Pair products of s for a mixed precision, formed on first use.  Returns
+// true when they are (or now are) resident; false when they would not fit
+// the budget (the caller then keeps the scaled-W kernels).
+// Pair-product bytes held by all live symmetries of the process; the total is
+// capped at 32 GB (callers hold g_tune_mu).
+static double g_pd_bytes = 0.0;
+
+static double pd_bytes(const Sym &s) {
+  const double per = (s.Ph ? 4.0 : 0.0) + (s.P32 ? 4.0 : 0.0) + (s.P64 ? 8.0 : 0.0);
+  return per * s.np_pad * (double)s.nh_pad;
+}
+
+static void pd_release(const Sym &s) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_pd_bytes = std::max(0.0, g_pd_bytes - pd_bytes(s));
+}
+
+static bool ensure_pd(Sym &s, int prec, hipStream_t st) {
+  const bool bf = prec == RM_PREC_BF16X3, f64 = prec == RM_PREC_FP64;
+  if (bf ? (s.Ph != nullptr) : f64 ? (s.P64 != nullptr) : (s.P32 != nullptr))
+    return true;
+  const double bytes = (f64 ? 8.0 : 4.0) * s.np_pad * (double)s.nh_pad;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
+  if (bytes > 8.0e9 || bytes > 0.25 * (double)free_b ||
+      g_pd_bytes + bytes > 32.0e9)
+    return false;
+  const size_t half = (size_t)s.np_pad * s.nh_pad * sizeof(uint16_t);
+  hipError_t e;
+  if (bf) {
+    e = hipMalloc((void **)&s.Ph, half);
+    if (e == hipSuccess) e = hipMalloc((void **)&s.Pl, half);
+  } else if (f64) {
+    e = hipMalloc((void **)&s.P64, 4 * half);
+  } else {
+    e = hipMalloc((void **)&s.P32, 2 * half);
+  }
+  if (e == hipSuccess) e = f64 ? launch_pd64_build(s, st) : launch_pd_build(s, prec, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    if (bf) {
+      if (s.Ph) (void)hipFree(s.Ph);
+      if (s.Pl) (void)hipFree(s.Pl);
+      s.Ph = s.Pl = nullptr;
+    } else if (f64) {
+      if (s.P64) (void)hipFree(s.P64);
+      s.P64 = nullptr;
+    } else {
+      if (s.P32) (void)hipFree(s.P32);
+      s.P32 = nullptr;
+    }
+    (void)hipGetLastError();
+    return false;
+  }
+  g_pd_bytes += bytes;
+  return true;
+}
+
 static void build_items(const Plan &p, int variant, int64_t m,
                         std::vector<PsItem> &out);
 
 // Time every mixed variant on up to 512 energies of E (device) and keep the
 // fastest.  Synchronises `st`.
+static int tune_variants(const Sym &s, int prec, double delta, const double *E,
+                         int64_t m, hipStream_t st, const std::vector<int> &cands,
+                         int *chosen);
+
 static int tune_sym(const Sym &s, int prec, double delta, const double *E,
-                    int64_t m, hipStream_t st, int *chosen) {
+                    int64_t m, hipStream_t st, bool with_pd, int *chosen) {
+  std::vector<int> c = {PS_MX_J16_E8, PS_MX_J8_E8, PS_MX_J16_E4};
+  if (with_pd) c.push_back(PS_PD);
+  return tune_variants(s, prec, delta, E, m, st, c, chosen);
+}
+
+static int tune_f64(const Sym &s, const double *E, int64_t m, hipStream_t st,
+                    int *chosen) {
+  return tune_variants(s, RM_PREC_FP64, 0.0, E, m, st,
+                       {PS_F64_T32_E16, PS_PD64}, chosen);
+}
+
+static int tune_variants(const Sym &s, int prec, double delta, const double *E,
+                         int64_t m, hipStream_t st, const std::vector<int> &cands,
+                         int *chosen) {
   const int64_t mt = std::min<int64_t>(m, 512);
   const int64_t nn = (int64_t)s.n * s.n;
   double *R = nullptr;
@@ -451,7 +530,7 @@ static int tune_sym(const Sym &s, int prec, double delta, const double *E,
   int64_t *doff = nullptr;
   PsItem *ditems = nullptr;
   hipEvent_t b = nullptr, e = nullptr;
-  int best = PS_MX_J16_E8;
+  int best = cands[0];
   float best_ms = 1e30f;
   hipError_t err = hipMalloc(&R, (size_t)(mt * nn) * sizeof(double));
   if (err == hipSuccess) err = hipMalloc(&dsym, sizeof(SymDev));
@@ -462,7 +541,8 @@ static int tune_sym(const Sym &s, int prec, double delta, const double *E,
   if (err == hipSuccess) err = hipMemcpy(doff, &zero, sizeof zero, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipEventCreate(&b);
   if (err == hipSuccess) err = hipEventCreate(&e);
-  for (int v = PS_MX_J16_E8; v <= PS_MX_J16_E4 && err == hipSuccess; ++v) {
+  for (size_t ci = 0; ci < cands.size() && err == hipSuccess; ++ci) {
+    const int v = cands[ci];
     std::vector<std::pair<int, int>> tiles;
     ps_tiles(s, v, tiles);
     const int eg = ps_energy_group(v);
@@ -510,27 +590,51 @@ static int tune_sym(const Sym &s, int prec, double delta, const double *E,
   return RM_OK;
 }
 
-static int pick_variant(const Sym &s, const rm_opts &o, const double *E,
-                        int64_t M, hipStream_t st, int *v) {
+static int pick_variant(Sym &s, const rm_opts &o, const double *E, int64_t M,
+                        hipStream_t st, int *v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
   if (o.prec == RM_PREC_FP64) {
+    // the FP64 pair-major GEMM is no faster than the scaled-W tiles on the
+    // 200-channel case and costs 8 bytes per pair and pole; it is used only
+    // when the autotuner times it faster
     *v = PS_F64_T32_E16;
+    if (o.flags & RM_FLAG_NO_PAIR_PRODUCTS) return RM_OK;
+    if (o.flags & RM_FLAG_PAIR_PRODUCTS) {
+      if (ensure_pd(s, o.prec, st)) *v = PS_PD64;
+      return RM_OK;
+    }
+    if (!(o.flags & RM_FLAG_AUTOTUNE) || M <= 0) return RM_OK;
+    auto it = g_tuned.find({s.n, s.nh, o.prec});
+    if (it != g_tuned.end()) {
+      if (it->second == PS_F64_T32_E16 || ensure_pd(s, o.prec, st)) *v = it->second;
+      return RM_OK;
+    }
+    if (!ensure_pd(s, o.prec, st)) return RM_OK;
+    int rc = tune_f64(s, E, M, st, v);
+    if (rc) return rc;
+    g_tuned[{s.n, s.nh, o.prec}] = *v;
+    tune_store();
     return RM_OK;
   }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const bool pd = !(o.flags & RM_FLAG_NO_PAIR_PRODUCTS) && ensure_pd(s, o.prec, st);
+  if (pd && (o.flags & RM_FLAG_PAIR_PRODUCTS)) {
+    *v = PS_PD;
+    return RM_OK;
+  }
   tune_load();
   auto it = g_tuned.find({s.n, s.nh, o.prec});
-  if (it != g_tuned.end()) {
+  if (it != g_tuned.end() && (pd || it->second != PS_PD)) {
     *v = it->second;
     return RM_OK;
   }
   if (!(o.flags & RM_FLAG_AUTOTUNE) || M <= 0) {
-    *v = default_variant(o.prec);
+    *v = pd ? PS_PD : default_variant(o.prec);
     return RM_OK;
   }
-  int rc = tune_sym(s, o.prec, o.near_delta, E, M, st, v);
+  int rc = tune_sym(s, o.prec, o.near_delta, E, M, st, pd, v);
   if (rc) return rc;
-  g_tuned[{s.n, s.nh, o.prec}] = *v;
-  tune_store();
+  if (pd) g_tuned[{s.n, s.nh, o.prec}] = *v;  // a table without the pair
+  tune_store();                               // form is not cached
   return RM_OK;
 }
 
@@ -575,6 +679,11 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   });
   p.syms = v;
   p.device = v[0]->device;
+  p.variant.resize(v.size());
+  for (size_t q = 0; q < v.size(); ++q) {
+    int rc = pick_variant(*const_cast<Sym *>(v[q]), o, E, M, st, &p.variant[q]);
+    if (rc) return rc;
+  }
   std::vector<SymDev> sd;
   std::vector<int64_t> woff, coff;
   int64_t wacc = 0, cacc = 0;
@@ -595,11 +704,6 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   p.C = C;
   p.n_chunks = (int)((M + C - 1) / C);
   p.tail = M - (int64_t)(p.n_chunks - 1) * C;
-  p.variant.resize(v.size());
-  for (size_t q = 0; q < v.size(); ++q) {
-    int rc = pick_variant(*v[q], o, E, M, st, &p.variant[q]);
-    if (rc) return rc;
-  }
   hipError_t e = hipMalloc(&p.d_syms, sd.size() * sizeof(SymDev));
   if (e == hipSuccess) e = hipMalloc(&p.d_work_off, woff.size() * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc(&p.d_chan_off, coff.size() * sizeof(int64_t));
@@ -724,10 +828,15 @@ static int validate_syms(const rm_sym_t *syms, int32_t n_sym, int32_t n_target) 
   return RM_OK;
 }
 
+static double pd_bytes(const Sym &s);
+static void pd_release(const Sym &s);
+
 static int free_sym(Sym *s) {
   if (!s) return RM_OK;
+  pd_release(*s);
   void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
-                  s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT};
+                  s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT,
+                  s->pair_ij, s->Ph, s->Pl, s->P32, s->P64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete[] s->h_e_thr;
@@ -852,6 +961,15 @@ int rm_load_poles(const rm_poles_desc *d, rm_sym_t *out, void *stream) {
     }
   }
   s->ntu = ntu;
+  // upper-triangle channel pairs, row-major, padded to the pair block
+  s->np = n * (n + 1) / 2;
+  s->np_pad = (s->np + kPairBlock - 1) / kPairBlock * kPairBlock;
+  std::vector<int32_t> pair_ij((size_t)s->np_pad, 0);
+  {
+    int q = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i; j < n; ++j) pair_ij[q++] = (i << 16) | j;
+  }
   // staged W, pole-major, zero padded
   const int64_t npad = s->n_pad, hpad = s->nh_pad;
   std::vector<double> Wt((size_t)(npad * hpad), 0.0);
@@ -887,6 +1005,7 @@ int rm_load_poles(const rm_poles_desc *d, rm_sym_t *out, void *stream) {
   RM_ALLOC_COPY(s->perm, perm.data(), n * sizeof(int32_t));
   RM_ALLOC_COPY(s->inv, inv.data(), n * sizeof(int32_t));
   RM_ALLOC_COPY(s->tgt, tgt.data(), n * sizeof(int32_t));
+  RM_ALLOC_COPY(s->pair_ij, pair_ij.data(), (size_t)s->np_pad * sizeof(int32_t));
   RM_ALLOC_COPY(s->ut, ut.data(), ntu * sizeof(int32_t));
   if (ntu < n) {
     RM_ALLOC_COPY(s->G, G.data(), (size_t)n * ntu * sizeof(double));

@@ -34,6 +34,11 @@ struct SymDev {
   const int32_t *ut;          // [ntu] those levels, ascending
   const double *G;            // [n][ntu] 0/1, channel -> used level
   const double *GT;           // [ntu][n] its transpose
+  int np, np_pad;             // pairs i <= j (row-major upper triangle)
+  const int32_t *pair_ij;     // [np_pad] (i << 16) | j
+  const uint16_t *Ph, *Pl;    // [np_pad][nh_pad] BF16 hi/lo of w_ik w_jk
+  const float *P32;           // [np_pad][nh_pad] FP32 w_ik w_jk
+  const double *P64;          // [np_pad][nh_pad] FP64 w_ik w_jk
 };
 
 // A symmetry resident on one device.  Channels are stored sorted by
@@ -57,6 +62,11 @@ struct Sym {
   int ntu;
   int32_t *ut;
   double *G, *GT;
+  int np, np_pad;       // channel pairs, padded to the pair-block size
+  int32_t *pair_ij;
+  uint16_t *Ph, *Pl;    // pair products, formed on first use (owned)
+  float *P32;
+  double *P64;
   // host copies
   double *h_e_thr;      // [n] sorted
   int32_t *h_perm;
@@ -67,6 +77,8 @@ struct Sym {
     d.E_pole = E_pole; d.Wt = Wt; d.W32c = W32c; d.Whc = Whc; d.Wlc = Wlc;
     d.e_thr = e_thr; d.l = l; d.perm = perm; d.tgt = tgt;
     d.ntu = ntu; d.ut = ut; d.G = G; d.GT = GT;
+    d.np = np; d.np_pad = np_pad; d.pair_ij = pair_ij;
+    d.Ph = Ph; d.Pl = Pl; d.P32 = P32; d.P64 = P64;
     return d;
   }
 };
@@ -98,8 +110,11 @@ enum PsVariant {
   PS_F64_T32_E16 = 0,   // FP64, 32x32 tile pairs, 16 energies per WG
   PS_MX_J16_E8 = 1,     // mixed, 16 column blocks, 8 energies per WG
   PS_MX_J8_E8 = 2,      // mixed, 8 column blocks, 8 energies per WG
-  PS_MX_J16_E4 = 3      // mixed, 16 column blocks, 4 energies per WG
+  PS_MX_J16_E4 = 3,     // mixed, 16 column blocks, 4 energies per WG
+  PS_PD = 4,            // mixed, pair-major GEMM over precomputed w_ik w_jk
+  PS_PD64 = 5           // FP64, pair-major GEMM
 };
+constexpr int kPairBlock = 256;   // pairs per pair-major workgroup tile
 
 // ---- launchers (return the hipError_t of the launch) ----
 
@@ -125,6 +140,11 @@ struct PsLaunch {
   double delta;
 };
 hipError_t launch_polesum(const PsLaunch &L, int variant, hipStream_t st);
+hipError_t launch_polesum_pd(const PsLaunch &L, hipStream_t st);
+hipError_t launch_polesum_pd64(const PsLaunch &L, hipStream_t st);
+hipError_t launch_pd64_build(const Sym &s, hipStream_t st);
+// Form the pair products of s for prec (FP32 or BF16X3) into its planes.
+hipError_t launch_pd_build(const Sym &s, int prec, hipStream_t st);
 int ps_energy_group(int variant);         // energies per work item
 // Tile items of one symmetry for a variant: (x, y) pairs, in order.
 void ps_tiles(const Sym &s, int variant, std::vector<std::pair<int, int>> &out);

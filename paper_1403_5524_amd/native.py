@@ -22,6 +22,8 @@ RM_E_NONFINITE = 0x08
 RM_E_ON_THRESHOLD = 0x10
 RM_E_REFINE_NOCONV = 0x20
 RM_FLAG_AUTOTUNE = 0x1
+RM_FLAG_NO_PAIR_PRODUCTS = 0x2
+RM_FLAG_PAIR_PRODUCTS = 0x4
 
 EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_kmatrix", "rm_collision_strengths", "rm_rmatrix",

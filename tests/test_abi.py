@@ -76,6 +76,14 @@ def test_sweep_rejects_invalid(L):
     neg = native.make_opts(near_delta=-1.0)
     assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(neg), None,
                                None, None) == native.RM_ERR_ARG
+    both = native.make_opts(flags=native.RM_FLAG_NO_PAIR_PRODUCTS
+                            | native.RM_FLAG_PAIR_PRODUCTS)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(both), None,
+                               None, None) == native.RM_ERR_ARG
+    unknown = native.make_opts(flags=0x8)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(unknown), None,
+                               None, None) == native.RM_ERR_ARG
+    assert b"flags" in L.rm_last_error()
 
 
 def test_null_handles_rejected(L):

@@ -1,5 +1,7 @@
 """Mixed-precision pole sums (FP32 and split-BF16 MFMA with the FP64
-near-pole correction) against the FP64 oracle (needs an MI355X).
+near-pole correction) against the FP64 oracle (needs an MI355X), for both
+forms of the pole sum: the pair-major GEMM over precomputed w_ik w_jk (the
+default) and the scaled-W kernels (RM_FLAG_NO_PAIR_PRODUCTS).
 
 Bar: Omega within 1e-4 normwise per energy (the stated tolerance for the
 mixed paths).  R is checked normwise against bounds that follow from the
@@ -17,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 OMEGA_TOL_MIXED = 1e-4
 R_TOL = {1: 1e-5, 2: 1e-4}
+FORMS = [0, 0x2]   # pair-major GEMM, scaled-W kernels
 
 
 @pytest.fixture(scope="module")
@@ -36,24 +39,26 @@ def _near_pole_energies(sym, count, offset):
     return sym.E_pole[pick] + offset
 
 
+@pytest.mark.parametrize("flags", FORMS)
 @pytest.mark.parametrize("prec", [1, 2])
-def test_rmatrix_mixed_c2(env, prec):
+def test_rmatrix_mixed_c2(env, prec, flags):
     torch, nat, w, h = env
     s = w.syms[0]
     E = np.concatenate([w.mesh[wl.sample_indices(w.mesh.size, 12, seed=8)],
                         _near_pole_energies(s, 4, 1e-6),
                         _near_pole_energies(s, 4, -3e-4)])
-    log("rmatrix mixed prec=%d m=%d" % (prec, E.size))
+    log("rmatrix mixed prec=%d flags=%d m=%d" % (prec, flags, E.size))
     Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
-    R = nat.rm_rmatrix(h, Et, nat.make_opts(prec=prec)).cpu().numpy()
+    R = nat.rm_rmatrix(h, Et, nat.make_opts(prec=prec, flags=flags)).cpu().numpy()
     Rr = oracle.r_matrix(s.E_pole, s.w, s.a, E)
     err = np.abs(R - Rr).max(axis=(1, 2)) / np.abs(Rr).max(axis=(1, 2))
     log("R normwise err max %.3e" % err.max())
     assert err.max() < R_TOL[prec]
 
 
+@pytest.mark.parametrize("flags", FORMS)
 @pytest.mark.parametrize("prec", [1, 2])
-def test_sweep_mixed_c2_sample(env, prec):
+def test_sweep_mixed_c2_sample(env, prec, flags):
     torch, nat, w, h = env
     s = w.syms[0]
     # mesh energies, energies inside the FP64 window and energies just
@@ -62,25 +67,45 @@ def test_sweep_mixed_c2_sample(env, prec):
                         _near_pole_energies(s, 4, 2e-6),
                         _near_pole_energies(s, 4, 1.2e-2),
                         _near_pole_energies(s, 4, -1.5e-2)])
-    log("sweep mixed prec=%d m=%d" % (prec, E.size))
+    log("sweep mixed prec=%d flags=%d m=%d" % (prec, flags, E.size))
     Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
-    om, st = nat.rm_sweep_energies([h], 200, Et, nat.make_opts(prec=prec))
+    om, st = nat.rm_sweep_energies([h], 200, Et,
+                                   nat.make_opts(prec=prec, flags=flags))
     ref = oracle.sweep(s.as_dict(), E)
     err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
-    log("mixed prec=%d omega normwise err %.3e" % (prec, err))
+    log("mixed prec=%d flags=%d omega normwise err %.3e" % (prec, flags, err))
     assert err < OMEGA_TOL_MIXED
     assert np.array_equal(st.cpu().numpy(), ref["status"])
 
 
 def test_mixed_matches_fp64_on_c1(env):
-    """Small system: every energy of the 8-channel case, both mixed paths."""
+    """Small system: every energy of the 8-channel case (one padded pair
+    block, 16 energy blocks with a ragged last one), both mixed paths and
+    both forms."""
     torch, nat, _, _ = env
     w = wl.config1()
     h = nat.load_symmetry(w.syms[0])
     Et = torch.as_tensor(w.mesh, dtype=torch.float64, device="cuda:0")
     ref = oracle.sweep(w.syms[0].as_dict(), w.mesh)
     for prec in (1, 2):
-        om, _ = nat.rm_sweep_energies([h], 8, Et, nat.make_opts(prec=prec))
-        err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
-        log("c1 mixed prec=%d err %.3e" % (prec, err))
-        assert err < OMEGA_TOL_MIXED
+        for flags in FORMS:
+            om, _ = nat.rm_sweep_energies([h], 8, Et,
+                                          nat.make_opts(prec=prec, flags=flags))
+            err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
+            log("c1 mixed prec=%d flags=%d err %.3e" % (prec, flags, err))
+            assert err < OMEGA_TOL_MIXED
+
+
+def test_pair_form_matches_scaled_w_form(env):
+    """The two forms of the mixed pole sum agree on R to the precision of
+    their operands (both round the same FP64 products and reciprocals)."""
+    torch, nat, w, h = env
+    E = w.mesh[wl.sample_indices(w.mesh.size, 300, seed=11)]
+    Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
+    for prec in (1, 2):
+        Ra = nat.rm_rmatrix(h, Et, nat.make_opts(prec=prec)).cpu().numpy()
+        Rb = nat.rm_rmatrix(h, Et, nat.make_opts(prec=prec, flags=0x2)).cpu().numpy()
+        d = np.abs(Ra - Rb).max(axis=(1, 2)) / np.abs(Rb).max(axis=(1, 2))
+        log("pair vs scaled-W prec=%d max normwise diff %.3e" % (prec, d.max()))
+        assert d.max() < 2 * R_TOL[prec]
+        assert np.array_equal(Ra, Ra.transpose(0, 2, 1))

@@ -100,13 +100,16 @@ def test_rmatrix_fp64_c1(torch_dev, nat, c1):
     assert err.max() < 1e-12, err.max()
 
 
-def test_rmatrix_fp64_c2_sample(torch_dev, nat, c2):
+@pytest.mark.parametrize("flags", [0x4, 0x2])
+def test_rmatrix_fp64_c2_sample(torch_dev, nat, c2, flags):
+    """FP64 pole sum, pair-major GEMM (flags 0x4) and scaled-W tiles (0x2):
+    129 energies (two 64-energy blocks and a ragged one)."""
     w, h = c2
     s = w.syms[0]
-    idx = wl.sample_indices(w.mesh.size, 24, seed=2)
+    idx = wl.sample_indices(w.mesh.size, 129, seed=2)
     E = w.mesh[idx]
-    log("rmatrix c2 m=%d" % E.size)
-    R = nat.rm_rmatrix(h, _dev(torch_dev, E)).cpu().numpy()
+    log("rmatrix c2 m=%d flags=%d" % (E.size, flags))
+    R = nat.rm_rmatrix(h, _dev(torch_dev, E), nat.make_opts(flags=flags)).cpu().numpy()
     Rr = oracle.r_matrix(s.E_pole, s.w, s.a, E)
     err = np.abs(R - Rr).max(axis=(1, 2)) / np.abs(Rr).max(axis=(1, 2))
     assert err.max() < 1e-12, err.max()

@@ -61,8 +61,8 @@ def test_plan_batched_symmetries_vs_oracle(env):
 
 
 def test_autotuned_mixed_plan(env):
-    """Autotuning picks one of the mixed tile variants; the result still
-    meets the mixed tolerance."""
+    """Autotuning picks one of the mixed variants (scaled-W tiles 1-3 or the
+    pair-major GEMM 4); the result still meets the mixed tolerance."""
     torch, nat = env
     w = wl.config2(M=4096)
     h = nat.load_symmetry(w.syms[0])
@@ -71,7 +71,7 @@ def test_autotuned_mixed_plan(env):
                                                flags=nat.RM_FLAG_AUTOTUNE))
     _, _, variants = plan.info()
     log("autotuned variant %s" % variants)
-    assert variants[0] in (1, 2, 3)
+    assert variants[0] in (1, 2, 3, 4)
     om, st = plan.execute()
     torch.cuda.synchronize()
     idx = wl.sample_indices(E.numel(), 8, seed=12)
