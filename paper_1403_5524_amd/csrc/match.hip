@@ -38,21 +38,22 @@
 namespace rmx {
 
 constexpr int WT = 64;   // lanes per wavefront
-constexpr int NB = 16;   // panel width
+constexpr int NB = 16;   // panel (factorisation) width
+constexpr int NB2 = 32;  // update width: two panels per trailing update
 constexpr int WPB = 4;   // wavefronts per workgroup
 constexpr int UNR = 4;   // independent elements per lane per batch
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Per-wavefront LDS: the 16 x 16 diagonal block of the current panel and the
-// row moves of its interchanges.
+// Per-wavefront LDS: the diagonal block of the current two panels, its
+// inverse, and the row moves of their interchanges.
 struct WaveLds {
-  double T[NB][NB + 1];
-  double Ti[NB][NB + 1];  // its inverse
-  int piv[NB];   // pivot row chosen at each panel column
-  int srcp[NB];  // after the interchanges, panel row q holds old row srcp[q]
-  int opos[NB];  // rows below the panel that receive another row ...
-  int osrc[NB];  // ... namely old row osrc[m]
+  double T[NB2][NB2 + 1];
+  double Ti[NB2][NB2 + 1];  // its inverse
+  int piv[NB2];   // pivot row chosen at each column of the block
+  int srcp[NB2];  // after the interchanges, block row q holds old row srcp[q]
+  int opos[NB2];  // rows below the block that receive another row ...
+  int osrc[NB2];  // ... namely old row osrc[m]
   int nout;
 };
 
@@ -96,7 +97,7 @@ __device__ inline int wave_or(int v) {
 
 // ---------------------------------------------------------------------------
 // GEMM, wavefront-local, operands in global memory.
-//   MODE 0: C -= A B  (kd <= 16: the rank-16 updates of the LU)
+//   MODE 0: C -= A B  (the rank-16 and rank-32 updates of the LU)
 //   MODE 1: C = A B + I
 //   MODE 2: C = A B
 // The wavefront walks 32 x 32 output tiles (2 x 2 MFMA blocks sharing their
@@ -146,7 +147,7 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
   const int col = lane & 15, kq = lane >> 4;
   const int nct = (cols + 31) >> 5;
   const int ntile = ((rows + 31) >> 5) * nct;
-  const int nk = MODE == 0 ? 1 : max(1, (kd + 15) >> 4);
+  const int nk = max(1, (kd + 15) >> 4);
   if (ntile > 0) {
     Frag cur, nxt;
     double cv[2][2][4], cn[2][2][4];
@@ -208,10 +209,12 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
 // ---------------------------------------------------------------------------
 // LU with partial pivoting.
 
-// Factor columns [j0, j0 + jb) of rows [j0, na) in place; pivots -> W.piv.
+// Factor columns [j0, j0 + jb) (jb <= 16) of rows [j0, na) in place;
+// interchanges swap the row segments [sw0, j0 + jb) (the panel and the L
+// columns of an earlier panel of the same block); pivots -> W.piv[po + .].
 // Returns 1 if a pivot was zero or not a number.
-__device__ int wave_panel(double *A, int na, int ld, int j0, int jb,
-                          WaveLds &W) {
+__device__ int wave_panel(double *A, int na, int ld, int j0, int jb, int sw0,
+                          int po, WaveLds &W) {
   const int lane = lane_id();
   int flag = 0;
 #pragma unroll 1
@@ -243,20 +246,23 @@ __device__ int wave_panel(double *A, int na, int ld, int j0, int jb,
       pr = col;
       pv = __builtin_nan("");
     }
-    if (lane == 0) W.piv[jj] = pr;
-    // swap the panel parts of rows col and pr; lane q keeps the new pivot
-    // row's element of panel column j0 + q
-    double prow = 0.0;
-    if (lane < jb) {
-      double *x = A + (int64_t)col * ld + j0 + lane;
-      double *y = A + (int64_t)pr * ld + j0 + lane;
-      const double xv = *x, yv = *y;
-      prow = yv;
+    if (lane == 0) W.piv[po + jj] = pr;
+    // swap the segments [sw0, j0 + jb) of rows col and pr; lane q keeps the
+    // new pivot row's element of panel column j0 + q
+    const int sw = lane + sw0 - j0;  // this lane's column, relative to j0
+    double yv = 0.0;
+    if (sw < jb) {
+      double *x = A + (int64_t)col * ld + j0 + sw;
+      double *y = A + (int64_t)pr * ld + j0 + sw;
+      const double xv = *x;
+      yv = *y;
       if (pr != col) {
         *x = yv;
         *y = xv;
       }
     }
+    // the lane that swapped panel column j0 + q holds its pivot-row value
+    const double prow = __shfl(yv, min(lane + j0 - sw0, WT - 1));
     wave_sync();
     if (!(fabs(pv) > 0.0)) flag = 1;
     const double inv = 1.0 / pv;
@@ -297,24 +303,144 @@ __device__ int wave_panel(double *A, int na, int ld, int j0, int jb,
   return flag;
 }
 
-// Invert the 16 x 16 diagonal block held in W.T into W.Ti (lanes 0..15
-// each form one column of the inverse, keeping it in W.Ti).  lower: unit
-// lower triangle (L11); otherwise upper triangle with its diagonal (U11).
-// Padded rows and columns must hold the identity.
+// The same factorisation with the panel held in registers, for panels of
+// at most 256 rows (row j0 + lane + 64 t of the panel in slot t): one load and
+// one store of the panel, and per column only cross-lane operations --
+// pivot search, the interchange, and the eliminations need no memory round
+// trip.  Interchanges swap rows of the panel only.
+constexpr int PR_T = 4;  // panel rows per lane
+typedef double d16 __attribute__((ext_vector_type(16)));
+
+// x0..x3 are four 16-wide row vectors (not an array, which would be placed
+// in scratch memory); PR_EACH applies M to each with its slot index.
+#define PR_EACH(M) M(0, x0) M(1, x1) M(2, x2) M(3, x3)
+
+__device__ int wave_panel_regs(double *A, int na, int ld, int j0, int jb,
+                               int po, WaveLds &W) {
+  static_assert(NB == 16, "row vectors hold one 16-column panel");
+  const int lane = lane_id();
+  d16 x0, x1, x2, x3;
+#define PR_LOAD(t, xv)                                                    \
+  {                                                                       \
+    const int r = j0 + lane + WT * t;                                     \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) xv[q] =                \
+        (r < na && q < jb) ? A[(int64_t)r * ld + j0 + q] : 0.0;           \
+  }
+  PR_EACH(PR_LOAD)
+#undef PR_LOAD
+  int flag = 0;
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) {
+    if (jj < jb) {  // uniform; the loop is unrolled so jj is a constant
+      const int col = j0 + jj;
+      double ba = -1.0, bv = 0.0;
+      int bi = na;
+#define PR_ARGMAX(t, xv)                                                  \
+  {                                                                       \
+    const int r = j0 + lane + WT * t;                                     \
+    const double v = xv[jj];                                              \
+    if (r >= col && r < na && fabs(v) > ba) {                             \
+      ba = fabs(v);                                                       \
+      bv = v;                                                             \
+      bi = r;                                                             \
+    }                                                                     \
+  }
+      PR_EACH(PR_ARGMAX)
+#undef PR_ARGMAX
+      wave_argmax(ba, bv, bi);
+      int pr = __builtin_amdgcn_readfirstlane(bi);
+      const bool bad = pr >= na;  // every candidate is NaN
+      if (bad) pr = col;
+      if (lane == 0) W.piv[po + jj] = pr;
+      const int d = pr - j0;
+      const int lp = __builtin_amdgcn_readfirstlane(d & (WT - 1)), tp = d >> 6;
+      const bool swap = pr != col, on_p = lane == lp, on_c = lane == jj;
+      d16 pc;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double s = tp == 0 ? x0[q] : tp == 1 ? x1[q] : tp == 2 ? x2[q] : x3[q];
+        const double vp = read_lane(s, lp);      // pivot row
+        const double vc = read_lane(x0[q], jj);  // row col (lane jj, slot 0)
+        pc[q] = vp;
+        // branch-free: the pivot row's slot takes row col, lane jj's slot 0
+        // takes the pivot row
+        const bool wp = swap && on_p;
+        x0[q] = (swap && on_c) ? vp : (wp && tp == 0) ? vc : x0[q];
+        x1[q] = (wp && tp == 1) ? vc : x1[q];
+        x2[q] = (wp && tp == 2) ? vc : x2[q];
+        x3[q] = (wp && tp == 3) ? vc : x3[q];
+      }
+      const double pv = bad ? __builtin_nan("") : pc[jj];
+      if (!(fabs(pv) > 0.0)) flag = 1;
+      const double inv = 1.0 / pv;
+#define PR_ELIM(t, xv)                                                    \
+  {                                                                       \
+    const int r = j0 + lane + WT * t;                                     \
+    if (r > col && r < na) {                                              \
+      const double l = xv[jj] * inv;                                      \
+      xv[jj] = l;                                                         \
+      _Pragma("unroll") for (int q = jj + 1; q < NB; ++q) xv[q] =         \
+          fma(-l, pc[q], xv[q]);                                          \
+    }                                                                     \
+  }
+      PR_EACH(PR_ELIM)
+#undef PR_ELIM
+    }
+  }
+#define PR_STORE(t, xv)                                                   \
+  {                                                                       \
+    const int r = j0 + lane + WT * t;                                     \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) if (r < na && q < jb)  \
+        A[(int64_t)r * ld + j0 + q] = xv[q];                              \
+  }
+  PR_EACH(PR_STORE)
+#undef PR_STORE
+  wave_sync();
+  return flag;
+}
+#undef PR_EACH
+
+// Apply the row moves in W (block positions j0 .. j0+cnt-1) to columns
+// [c0, c1) only, with batched loads before stores.
+__device__ void wave_apply_moves(double *A, int ld, int j0, int cnt, int c0,
+                                 int c1, const WaveLds &W) {
+  const int lane = lane_id();
+  const int nout = W.nout;
+  for (int c = c0 + lane; c < c1; c += WT) {
+    double xv[NB], yv[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      xv[q] = q < cnt ? A[(int64_t)W.srcp[q] * ld + c] : 0.0;
+      yv[q] = q < nout ? A[(int64_t)W.osrc[q] * ld + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (q < cnt) A[(int64_t)(j0 + q) * ld + c] = xv[q];
+      if (q < nout) A[(int64_t)W.opos[q] * ld + c] = yv[q];
+    }
+  }
+  wave_sync();
+}
+
+// Invert the NT x NT diagonal block held in W.T into W.Ti (lanes 0..NT-1
+// each form one column of the inverse).  lower: unit lower triangle (L11);
+// otherwise upper triangle with its diagonal (U11).  Padded rows and columns
+// must hold the identity.
+template <int NT>
 __device__ void wave_tile_invert(WaveLds &W, bool lower) {
   const int lane = lane_id();
-  if (lane < NB) {
+  if (lane < NT) {
     const int j = lane;
     if (lower) {
 #pragma unroll 1
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < NT; ++q) {
         double s = q == j ? 1.0 : 0.0;
         for (int p = j; p < q; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
         W.Ti[q][j] = s;
       }
     } else {
 #pragma unroll 1
-      for (int q = NB - 1; q >= 0; --q) {
+      for (int q = NT - 1; q >= 0; --q) {
         double s = q == j ? 1.0 : 0.0;
         for (int p = q + 1; p <= j; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
         W.Ti[q][j] = q <= j ? s / W.T[q][q] : 0.0;
@@ -324,59 +450,118 @@ __device__ void wave_tile_invert(WaveLds &W, bool lower) {
   wave_sync();
 }
 
-// Columns [c0, c1) of rows j0 .. j0+15:  X <- Ti X, where row q of X is
-// taken from row src[q] (moves) or row j0 + q (src == nullptr), and rows
-// opos[m] receive rows osrc[m] (m < nout) in the same pass.  16 x 16 FP64
-// MFMA blocks, four column blocks per batch; every load of a batch is
+// Stage the block's diagonal part of A (rows and columns [j0, j0 + jb)) into
+// W.T with identity padding to NT: its unit lower triangle (lower) or its
+// upper triangle with the diagonal.
+template <int NT>
+__device__ void wave_tile_stage(const double *A, int ld, int j0, int jb,
+                                WaveLds &W, bool lower) {
+  const int lane = lane_id();
+  for (int q = lane; q < NT * NT; q += WT) {
+    const int i = q / NT, j = q % NT;
+    double v = i == j ? 1.0 : 0.0;
+    if (i < jb && j < jb && (lower ? j < i : j >= i))
+      v = A[(int64_t)(j0 + i) * ld + j0 + j];
+    W.T[i][j] = v;
+  }
+  wave_sync();
+}
+
+// Row moves of the cnt interchanges W.piv[po + q] at positions j0 + q
+// (they act in sequence; a position, once passed, is never moved again):
+// W.srcp, W.opos, W.osrc, W.nout.  Lane 0 only.
+__device__ void wave_build_moves(WaveLds &W, int j0, int cnt, int po = 0) {
+  if (lane_id() == 0) {
+    int nout = 0;
+    for (int q = 0; q < cnt; ++q) W.srcp[q] = j0 + q;
+    for (int q = 0; q < cnt; ++q) {
+      const int p = W.piv[po + q];
+      if (p == j0 + q) continue;
+      int *slot;
+      if (p < j0 + cnt) {
+        slot = &W.srcp[p - j0];
+      } else {
+        int m = 0;
+        while (m < nout && W.opos[m] != p) ++m;
+        if (m == nout) {
+          W.opos[m] = p;
+          W.osrc[m] = p;
+          ++nout;
+        }
+        slot = &W.osrc[m];
+      }
+      const int t = W.srcp[q];
+      W.srcp[q] = *slot;
+      *slot = t;
+    }
+    W.nout = nout;
+  }
+  wave_sync();
+}
+
+// Columns [c0, c1) of rows j0 .. j0+NT-1:  X <- Ti X, where row q of X is
+// taken from row srcp[q] (moves) or row j0 + q, and rows opos[m] receive
+// rows osrc[m] (m < nout) in the same pass; only rows q < jb are written.
+// 16 x 16 FP64 MFMA blocks over NT/4 k-steps; every load of a batch is
 // issued before any store, so sources and destinations may coincide.
+template <int NT>
 __device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
                                 int c1, const WaveLds &W, bool moves) {
+  constexpr int NS = NT / 4, NRB = NT / 16, CB = NT == 16 ? 4 : 2;
   const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
-  double ainv[4];
+  double ainv[NRB][NS];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) ainv[s] = W.Ti[col][4 * s + kq];
-  int srow[4], orow[4], drow[4];
-  bool sv[4], ov[4];
+  for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < NS; ++s) ainv[rb][s] = W.Ti[rb * 16 + col][4 * s + kq];
+  int srow[NS], orow[NS], drow[NS];
+  bool sv[NS], ov[NS];
+  const int nout = moves ? W.nout : 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
     const int q = 4 * s + kq;
     sv[s] = q < jb;
     srow[s] = moves ? (sv[s] ? W.srcp[q] : 0) : j0 + q;
-    ov[s] = moves && q < W.nout;
+    ov[s] = q < nout;
     orow[s] = ov[s] ? W.osrc[q] : 0;
     drow[s] = ov[s] ? W.opos[q] : 0;
   }
-  constexpr int CB = 4;
   for (int cb = c0; cb < c1; cb += 16 * CB) {
-    double b[CB][4], y[CB][4];
+    double b[CB][NS], y[CB][NS];
 #pragma unroll
     for (int u = 0; u < CB; ++u) {
       const int c = cb + 16 * u + col;
       const bool cv = c < c1;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NS; ++s) {
         b[u][s] = (cv && sv[s]) ? A[(int64_t)srow[s] * ld + c] : 0.0;
         y[u][s] = (cv && ov[s]) ? A[(int64_t)orow[s] * ld + c] : 0.0;
       }
     }
 #pragma unroll
     for (int u = 0; u < CB; ++u) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      d4 acc[NRB];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ainv[s], b[u][s], acc, 0,
-                                                   0, 0);
+      for (int rb = 0; rb < NRB; ++rb) acc[rb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ainv[rb][s], b[u][s],
+                                                         acc[rb], 0, 0, 0);
       const int c = cb + 16 * u + col;
       if (c < c1) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < NS; ++s)
           if (ov[s]) A[(int64_t)drow[s] * ld + c] = y[u][s];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int q = kq + 4 * r;  // FP64 result row
-          if (q < jb) A[(int64_t)(j0 + q) * ld + c] = acc[r];
-        }
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = rb * 16 + kq + 4 * r;  // FP64 result row
+            if (q < jb) A[(int64_t)(j0 + q) * ld + c] = acc[rb][r];
+          }
       }
     }
   }
@@ -386,70 +571,56 @@ __device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
 // Solve A X = B in place for the na x na matrix in columns [0, na) of rows
 // [0, na) (leading dimension ld), right-hand sides in columns
 // [na, na + nrhs); on return those columns hold X.  Wavefront-local.
-// Returns nonzero if a pivot was zero or not a number.
+// Blocks of 32 columns: two 16-column panels (the second updated by the
+// first before it is factored), then the block's interchanges and L11^-1
+// applied to the columns on its right and one rank-32 trailing update, so
+// the trailing matrix crosses HBM once per 32 columns.  Returns nonzero if
+// a pivot was zero or not a number.
 __device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
-  const int lane = lane_id();
   const int ntot = na + nrhs;
   int flag = 0;
-  for (int j0 = 0; j0 < na; j0 += NB) {
-    const int jb = min(NB, na - j0);
-    flag |= wave_panel(A, na, ld, j0, jb, W);
-    // row moves of this panel's interchanges (they act in sequence; a panel
-    // row, once passed, is never moved again)
-    if (lane == 0) {
-      int nout = 0;
-      for (int q = 0; q < jb; ++q) W.srcp[q] = j0 + q;
-      for (int q = 0; q < jb; ++q) {
-        const int p = W.piv[q];
-        if (p == j0 + q) continue;
-        int *slot;
-        if (p < j0 + jb) {
-          slot = &W.srcp[p - j0];
-        } else {
-          int m = 0;
-          while (m < nout && W.opos[m] != p) ++m;
-          if (m == nout) {
-            W.opos[m] = p;
-            W.osrc[m] = p;
-            ++nout;
-          }
-          slot = &W.osrc[m];
-        }
-        const int t = W.srcp[q];
-        W.srcp[q] = *slot;
-        *slot = t;
+  for (int j0 = 0; j0 < na; j0 += NB2) {
+    const int jb = min(NB2, na - j0);
+    const int ja = min(NB, jb);
+    const bool regs = na - j0 <= PR_T * WT;
+    flag |= regs ? wave_panel_regs(A, na, ld, j0, ja, 0, W)
+                 : wave_panel(A, na, ld, j0, ja, j0, 0, W);
+    if (jb > ja) {
+      // first panel's interchanges and L^-1 on the second panel's columns,
+      // then its update of the second panel's rows below
+      wave_build_moves(W, j0, ja);
+      wave_tile_stage<NB>(A, ld, j0, ja, W, true);
+      wave_tile_invert<NB>(W, true);
+      wave_tile_apply<NB>(A, ld, j0, ja, j0 + ja, j0 + jb, W, true);
+      wave_gemm<0>(A + (int64_t)(j0 + ja) * ld + j0 + ja, ld,
+                   A + (int64_t)(j0 + ja) * ld + j0, ld,
+                   A + (int64_t)j0 * ld + j0 + ja, ld, na - j0 - ja, jb - ja,
+                   ja);
+      if (regs) {
+        // the second panel's interchanges also move the first panel's L
+        flag |= wave_panel_regs(A, na, ld, j0 + ja, jb - ja, ja, W);
+        wave_build_moves(W, j0 + ja, jb - ja, ja);
+        wave_apply_moves(A, ld, j0 + ja, jb - ja, j0, j0 + ja, W);
+      } else {
+        flag |= wave_panel(A, na, ld, j0 + ja, jb - ja, j0, ja, W);
       }
-      W.nout = nout;
     }
-    // L11 (unit lower; identity padding) -> its inverse in the LDS tile
-    for (int q = lane; q < NB * NB; q += WT) {
-      const int i = q / NB, j = q % NB;
-      double v = i == j ? 1.0 : 0.0;
-      if (i < jb && j < i) v = A[(int64_t)(j0 + i) * ld + j0 + j];
-      W.T[i][j] = v;
-    }
-    wave_sync();
-    wave_tile_invert(W, true);
-    // columns right of the panel: row moves, then L11^-1
-    wave_tile_apply(A, ld, j0, jb, j0 + jb, ntot, W, true);
+    // the block's interchanges and L11^-1 on every column to its right
+    wave_build_moves(W, j0, jb);
+    wave_tile_stage<NB2>(A, ld, j0, jb, W, true);
+    wave_tile_invert<NB2>(W, true);
+    wave_tile_apply<NB2>(A, ld, j0, jb, j0 + jb, ntot, W, true);
     const int r0 = j0 + jb;
     if (r0 < na)
       wave_gemm<0>(A + (int64_t)r0 * ld + r0, ld, A + (int64_t)r0 * ld + j0,
                    ld, A + (int64_t)j0 * ld + r0, ld, na - r0, ntot - r0, jb);
   }
-  // back substitution U X = B' on the right-hand sides
-  for (int j0 = ((na - 1) / NB) * NB; j0 >= 0; j0 -= NB) {
-    const int jb = min(NB, na - j0);
-    // U11 (identity padding) -> its inverse
-    for (int q = lane; q < NB * NB; q += WT) {
-      const int i = q / NB, j = q % NB;
-      double v = i == j ? 1.0 : 0.0;
-      if (i < jb && j < jb && j >= i) v = A[(int64_t)(j0 + i) * ld + j0 + j];
-      W.T[i][j] = v;
-    }
-    wave_sync();
-    wave_tile_invert(W, false);
-    wave_tile_apply(A, ld, j0, jb, na, ntot, W, false);
+  // back substitution U X = B' on the right-hand sides, 32 rows at a time
+  for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
+    const int jb = min(NB2, na - j0);
+    wave_tile_stage<NB2>(A, ld, j0, jb, W, false);
+    wave_tile_invert<NB2>(W, false);
+    wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
     if (j0 > 0)
       wave_gemm<0>(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0,
                    nrhs, jb);
