@@ -662,6 +662,15 @@ static int match_grid_size() {
   return cus * 4;
 }
 
+// Workspace budget of a sweep: at least `base` bytes, else up to 40 % of
+// the device memory free now (at most 96 GB), so that large symmetries
+// still get enough energies per chunk to fill the GPU with wavefronts.
+static double workspace_budget(double base) {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return base;
+  return std::max(base, std::min(0.4 * (double)free_b, 96.0e9));
+}
+
 // Build a plan: orders symmetries, allocates tables and workspace.
 // async: workspace from the stream-ordered allocator on st (eager calls).
 static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
@@ -1057,7 +1066,8 @@ int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
   if (M == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
   Plan p;
-  rc = plan_build(p, syms, n_sym, n_target, E, M, o, st, true, 16.0e9);
+  rc = plan_build(p, syms, n_sym, n_target, E, M, o, st, true,
+                  workspace_budget(16.0e9));
   if (!rc) {
     p.E = E;
     p.omega = omega;
@@ -1229,7 +1239,8 @@ int rm_plan_create(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
   hipStream_t st = (hipStream_t)stream;
   rm_plan *p = new (std::nothrow) rm_plan();
   if (!p) return fail(RM_ERR_NOMEM, "host allocation");
-  rc = plan_build(*p, syms, n_sym, n_target, E, M, o, st, false, 32.0e9);
+  rc = plan_build(*p, syms, n_sym, n_target, E, M, o, st, false,
+                  workspace_budget(32.0e9));
   if (!rc) {
     p->E = E;
     p->omega = omega;
