@@ -50,11 +50,12 @@ def measured_traffic(key, energies):
 
 def match_flops(n, n_open):
     """Algorithmic FP64 flops of matching one symmetry at energies with
-    n_open open channels: LU of the n x n matrix (2n^3/3), forward and back
-    substitution of n_open right-hand sides (2 n^2 n_open), K^2 and K Y
-    (2 n_open^3 each), LU and solve of 1 + K^2 (2/3 + 2) n_open^3."""
+    n_open = m open channels: LU of the n x n matrix (2n^3/3), forward and
+    back substitution of m right-hand sides (2 n^2 m); the T step: 1 + K^2
+    (its lower triangle, m^3), Cholesky (m^3/3), Z = L^-1 K and Y = L^-T Z
+    (m^3 each), Q = Z^T Z (2 m^3)."""
     no = n_open.astype(np.float64)
-    f = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * no + (20.0 / 3.0) * no ** 3
+    f = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * no + (16.0 / 3.0) * no ** 3
     return float(np.where(no > 0, f, 0.0).sum())
 
 

@@ -106,6 +106,12 @@ struct Frag {
   double a[4][2], b[4][2];
 };
 
+// Operand storage flags of wave_gemm.
+constexpr int G_TA = 1;     // A[i][k] stored at A[k * lda + i]
+constexpr int G_TB = 2;     // B[k][j] stored at B[j * ldb + k]
+constexpr int G_LOWER = 4;  // only the tiles of C that meet its lower triangle
+
+template <int FL>
 __device__ inline void frag_load(Frag &f, const double *A, int lda,
                                  const double *B, int ldb, int rows, int cols,
                                  int kd, int rb, int cb, int k0) {
@@ -116,10 +122,20 @@ __device__ inline void frag_load(Frag &f, const double *A, int lda,
   for (int s = 0; s < 4; ++s) {
     const int k = k0 + 4 * s + kq;
     const bool kv = k < kd;
-    f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)ra0 * lda + k] : 0.0;
-    f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)ra1 * lda + k] : 0.0;
-    f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)k * ldb + c0] : 0.0;
-    f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)k * ldb + c1] : 0.0;
+    if (FL & G_TA) {
+      f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)k * lda + ra0] : 0.0;
+      f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)k * lda + ra1] : 0.0;
+    } else {
+      f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)ra0 * lda + k] : 0.0;
+      f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)ra1 * lda + k] : 0.0;
+    }
+    if (FL & G_TB) {
+      f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)c0 * ldb + k] : 0.0;
+      f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)c1 * ldb + k] : 0.0;
+    } else {
+      f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)k * ldb + c0] : 0.0;
+      f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)k * ldb + c1] : 0.0;
+    }
   }
 }
 
@@ -139,7 +155,17 @@ __device__ inline void ctile_load(double (&c)[2][2][4], const double *C,
       }
 }
 
-template <int MODE>
+// Next tile index after t (row-major over 32 x 32 tiles), skipping the
+// tiles strictly above the diagonal when only the lower triangle is wanted.
+template <int FL>
+__device__ inline int gemm_next_tile(int t, int nct, int ntile) {
+  ++t;
+  if (FL & G_LOWER)
+    while (t < ntile && (t % nct) > (t / nct)) ++t;
+  return t;
+}
+
+template <int MODE, int FL = 0>
 __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
                           const double *B, int ldb, int rows, int cols,
                           int kd) {
@@ -151,9 +177,10 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
   if (ntile > 0) {
     Frag cur, nxt;
     double cv[2][2][4], cn[2][2][4];
-    frag_load(cur, A, lda, B, ldb, rows, cols, kd, 0, 0, 0);
+    frag_load<FL>(cur, A, lda, B, ldb, rows, cols, kd, 0, 0, 0);
     if (MODE == 0) ctile_load(cv, C, ldc, rows, cols, 0, 0);
-    for (int t = 0; t < ntile; ++t) {
+    for (int t = 0; t < ntile;) {
+      const int tn = gemm_next_tile<FL>(t, nct, ntile);
       const int rb = (t / nct) * 32, cb = (t % nct) * 32;
       d4 acc[2][2];
 #pragma unroll
@@ -164,10 +191,10 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
         // prefetch: the next k-step of this tile, else the next tile (whose
         // A, B and C do not overlap this tile's C)
         if (kc + 1 < nk) {
-          frag_load(nxt, A, lda, B, ldb, rows, cols, kd, rb, cb, (kc + 1) * 16);
-        } else if (t + 1 < ntile) {
-          const int rn = ((t + 1) / nct) * 32, cnb = ((t + 1) % nct) * 32;
-          frag_load(nxt, A, lda, B, ldb, rows, cols, kd, rn, cnb, 0);
+          frag_load<FL>(nxt, A, lda, B, ldb, rows, cols, kd, rb, cb, (kc + 1) * 16);
+        } else if (tn < ntile) {
+          const int rn = (tn / nct) * 32, cnb = (tn % nct) * 32;
+          frag_load<FL>(nxt, A, lda, B, ldb, rows, cols, kd, rn, cnb, 0);
           if (MODE == 0) ctile_load(cn, C, ldc, rows, cols, rn, cnb);
         }
 #pragma unroll
@@ -201,6 +228,7 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
 #pragma unroll
             for (int r = 0; r < 4; ++r) cv[x][y][r] = cn[x][y][r];
       }
+      t = tn;
     }
   }
   wave_sync();
@@ -423,20 +451,22 @@ __device__ void wave_apply_moves(double *A, int ld, int j0, int cnt, int c0,
 }
 
 // Invert the NT x NT diagonal block held in W.T into W.Ti (lanes 0..NT-1
-// each form one column of the inverse).  lower: unit lower triangle (L11);
-// otherwise upper triangle with its diagonal (U11).  Padded rows and columns
-// must hold the identity.
+// each form one column of the inverse).  Kinds: unit lower triangle (L11 of
+// the LU), upper triangle with its diagonal (U11), lower triangle with its
+// diagonal (a Cholesky factor).  Padded rows and columns must hold the
+// identity.
+enum TileKind { TILE_UNIT_LOWER = 0, TILE_UPPER = 1, TILE_LOWER = 2 };
 template <int NT>
-__device__ void wave_tile_invert(WaveLds &W, bool lower) {
+__device__ void wave_tile_invert(WaveLds &W, int kind) {
   const int lane = lane_id();
   if (lane < NT) {
     const int j = lane;
-    if (lower) {
+    if (kind != TILE_UPPER) {
 #pragma unroll 1
       for (int q = 0; q < NT; ++q) {
         double s = q == j ? 1.0 : 0.0;
         for (int p = j; p < q; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
-        W.Ti[q][j] = s;
+        W.Ti[q][j] = kind == TILE_LOWER ? (q >= j ? s / W.T[q][q] : 0.0) : s;
       }
     } else {
 #pragma unroll 1
@@ -455,13 +485,15 @@ __device__ void wave_tile_invert(WaveLds &W, bool lower) {
 // upper triangle with the diagonal.
 template <int NT>
 __device__ void wave_tile_stage(const double *A, int ld, int j0, int jb,
-                                WaveLds &W, bool lower) {
+                                WaveLds &W, int kind) {
   const int lane = lane_id();
   for (int q = lane; q < NT * NT; q += WT) {
     const int i = q / NT, j = q % NT;
     double v = i == j ? 1.0 : 0.0;
-    if (i < jb && j < jb && (lower ? j < i : j >= i))
-      v = A[(int64_t)(j0 + i) * ld + j0 + j];
+    const bool in = kind == TILE_UNIT_LOWER ? j < i
+                    : kind == TILE_UPPER    ? j >= i
+                                            : j <= i;
+    if (i < jb && j < jb && in) v = A[(int64_t)(j0 + i) * ld + j0 + j];
     W.T[i][j] = v;
   }
   wave_sync();
@@ -499,22 +531,24 @@ __device__ void wave_build_moves(WaveLds &W, int j0, int cnt, int po = 0) {
   wave_sync();
 }
 
-// Columns [c0, c1) of rows j0 .. j0+NT-1:  X <- Ti X, where row q of X is
+// Columns [c0, c1) of rows j0 .. j0+NT-1:  X <- Ti X (or Ti^T X), where row q of X is
 // taken from row srcp[q] (moves) or row j0 + q, and rows opos[m] receive
 // rows osrc[m] (m < nout) in the same pass; only rows q < jb are written.
 // 16 x 16 FP64 MFMA blocks over NT/4 k-steps; every load of a batch is
 // issued before any store, so sources and destinations may coincide.
-template <int NT>
+template <int NT, bool TRANS = false>
 __device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
                                 int c1, const WaveLds &W, bool moves) {
   constexpr int NS = NT / 4, NRB = NT / 16, CB = NT == 16 ? 4 : 2;
   const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
-  double ainv[NRB][NS];
+  double ainv[NRB][NS];  // Ti, or its transpose
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) ainv[rb][s] = W.Ti[rb * 16 + col][4 * s + kq];
+    for (int s = 0; s < NS; ++s)
+      ainv[rb][s] = TRANS ? W.Ti[4 * s + kq][rb * 16 + col]
+                          : W.Ti[rb * 16 + col][4 * s + kq];
   int srow[NS], orow[NS], drow[NS];
   bool sv[NS], ov[NS];
   const int nout = moves ? W.nout : 0;
@@ -589,8 +623,8 @@ __device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
       // first panel's interchanges and L^-1 on the second panel's columns,
       // then its update of the second panel's rows below
       wave_build_moves(W, j0, ja);
-      wave_tile_stage<NB>(A, ld, j0, ja, W, true);
-      wave_tile_invert<NB>(W, true);
+      wave_tile_stage<NB>(A, ld, j0, ja, W, TILE_UNIT_LOWER);
+      wave_tile_invert<NB>(W, TILE_UNIT_LOWER);
       wave_tile_apply<NB>(A, ld, j0, ja, j0 + ja, j0 + jb, W, true);
       wave_gemm<0>(A + (int64_t)(j0 + ja) * ld + j0 + ja, ld,
                    A + (int64_t)(j0 + ja) * ld + j0, ld,
@@ -607,8 +641,8 @@ __device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
     }
     // the block's interchanges and L11^-1 on every column to its right
     wave_build_moves(W, j0, jb);
-    wave_tile_stage<NB2>(A, ld, j0, jb, W, true);
-    wave_tile_invert<NB2>(W, true);
+    wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UNIT_LOWER);
+    wave_tile_invert<NB2>(W, TILE_UNIT_LOWER);
     wave_tile_apply<NB2>(A, ld, j0, jb, j0 + jb, ntot, W, true);
     const int r0 = j0 + jb;
     if (r0 < na)
@@ -618,12 +652,191 @@ __device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
   // back substitution U X = B' on the right-hand sides, 32 rows at a time
   for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, na - j0);
-    wave_tile_stage<NB2>(A, ld, j0, jb, W, false);
-    wave_tile_invert<NB2>(W, false);
+    wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UPPER);
+    wave_tile_invert<NB2>(W, TILE_UPPER);
     wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
     if (j0 > 0)
       wave_gemm<0>(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0,
                    nrhs, jb);
+  }
+  return flag;
+}
+
+// Copy a rows x cols block (row-major source ld sl, destination ld dl) with
+// batched loads.
+__device__ inline void wave_copy(double *dst, int dl, const double *src,
+                                 int sl, int rows, int cols) {
+  const int lane = lane_id();
+  const int nq = rows * cols;
+  for (int q0 = lane; q0 < nq; q0 += UNR * WT) {
+    double v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      v[u] = q < nq ? src[(int64_t)(q / cols) * sl + q % cols] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q < nq) dst[(int64_t)(q / cols) * dl + q % cols] = v[u];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// T step by Cholesky: 1 + K^2 is symmetric positive definite (eigenvalues
+// 1 + k^2 >= 1), so with 1 + K^2 = L L^T and Z = L^-1 K,
+//     Y = (1 + K^2)^-1 K = L^-T Z,   Q = K Y = K L^-T L^-1 K = Z^T Z
+// (K symmetric): no pivoting, only the lower triangle is factored, and
+// Q needs no product with K.
+
+// Factor the jb x jb (jb <= 32) diagonal block at (j0, j0) of A = L L^T in
+// registers: lane i holds row i in two 16-wide vectors; per column, one
+// broadcast of the diagonal and of the column, no memory round trip.
+// Writes L11 back (lower triangle with its diagonal) and stages it in W.T
+// for inversion.  Returns 1 if a diagonal was not positive.
+__device__ int wave_chol_diag(double *A, int ld, int j0, int jb, WaveLds &W) {
+  const int lane = lane_id();
+  d16 xa, xb;  // row `lane`, columns 0..15 and 16..31 of the block
+  const bool row_ok = lane < jb;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    xa[k] = (row_ok && k <= lane) ? A[(int64_t)(j0 + lane) * ld + j0 + k] : 0.0;
+    xb[k] = (row_ok && 16 + k <= lane && 16 + k < jb)
+                ? A[(int64_t)(j0 + lane) * ld + j0 + 16 + k]
+                : 0.0;
+  }
+  int flag = 0;
+#define CH_GET(j) ((j) < 16 ? xa[(j) & 15] : xb[(j) & 15])
+#define CH_SET(j, v)          \
+  if ((j) < 16)               \
+    xa[(j) & 15] = (v);       \
+  else                        \
+    xb[(j) & 15] = (v);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    if (j < jb) {  // uniform; the loop is unrolled so j is a constant
+      const double djj = read_lane(CH_GET(j), j);
+      if (!(djj > 0.0)) flag = 1;
+      const double d = sqrt(djj), rd = 1.0 / d;
+      const double lij = lane > j ? CH_GET(j) * rd : lane == j ? d : CH_GET(j);
+      CH_SET(j, lij);
+#pragma unroll
+      for (int k = j + 1; k < 32; ++k) {
+        if (k < jb) {
+          const double lkj = read_lane(lij, k);  // L[k][j]
+          const double v = CH_GET(k);
+          CH_SET(k, lane >= k ? fma(-lij, lkj, v) : v);
+        }
+      }
+    }
+  }
+#undef CH_GET
+#undef CH_SET
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (row_ok && k <= lane) A[(int64_t)(j0 + lane) * ld + j0 + k] = xa[k];
+    if (row_ok && 16 + k <= lane && 16 + k < jb)
+      A[(int64_t)(j0 + lane) * ld + j0 + 16 + k] = xb[k];
+  }
+  // W.T: the factor with identity padding
+  if (lane < NB2) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      W.T[lane][k] = row_ok ? (k <= lane ? xa[k] : 0.0) : (k == lane ? 1.0 : 0.0);
+      W.T[lane][16 + k] = row_ok ? (16 + k <= lane ? xb[k] : 0.0)
+                                 : (16 + k == lane ? 1.0 : 0.0);
+    }
+  }
+  wave_sync();
+  return flag;
+}
+
+// Rows [r0, r1) of columns [j0, j0 + jb): X <- X Ti^T (the panel of a
+// Cholesky factor, L21 = A21 L11^-T), 16 rows at a time as FP64 MFMA
+// blocks; each row block is loaded whole before it is stored.
+__device__ void wave_rows_times_tit(double *A, int ld, int r0, int r1, int j0,
+                                    int jb, const WaveLds &W) {
+  const int lane = lane_id();
+  const int col = lane & 15, kq = lane >> 4;
+  double b[2][8];  // B[k][j] = Ti[j][k], j = 16 cb + col, k = 4 s + kq
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b[cb][s] = W.Ti[16 * cb + col][4 * s + kq];
+  for (int rb = r0; rb < r1; rb += 32) {
+    double a[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = rb + 16 * h + col;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = 4 * s + kq;
+        a[h][s] = (r < r1 && k < jb) ? A[(int64_t)r * ld + j0 + k] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      d4 acc[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h][s], b[cb][s],
+                                                         acc[cb], 0, 0, 0);
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb + 16 * h + kq + 4 * r, j = 16 * cb + col;
+          if (row < r1 && j < jb) A[(int64_t)row * ld + j0 + j] = acc[cb][r];
+        }
+    }
+  }
+  wave_sync();
+}
+
+// The T step in the workspace of one energy: K (no x no, leading dimension
+// lk) in; Y in columns [no, 2 no) of Aug (leading dimension ld) and Q in K's
+// place out; Aug's columns [0, no) hold L.  Returns nonzero if 1 + K^2 was
+// not positive definite in floating point.
+__device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
+                          WaveLds &W) {
+  int flag = 0;
+  // lower triangle of 1 + K^2, and K as the right-hand side
+  wave_gemm<1, G_LOWER>(Aug, ld, Kb, lk, Kb, lk, no, no, no);
+  wave_copy(Aug + no, ld, Kb, lk, no, no);
+  wave_sync();
+  // right-looking blocked Cholesky with the forward substitution Z = L^-1 K
+  for (int j0 = 0; j0 < no; j0 += NB2) {
+    const int jb = min(NB2, no - j0);
+    flag |= wave_chol_diag(Aug, ld, j0, jb, W);
+    wave_tile_invert<NB2>(W, TILE_LOWER);
+    const int r0 = j0 + jb;
+    if (r0 < no) wave_rows_times_tit(Aug, ld, r0, no, j0, jb, W);
+    wave_tile_apply<NB2>(Aug, ld, j0, jb, no, 2 * no, W, false);
+    if (r0 < no) {
+      wave_gemm<0, G_TB | G_LOWER>(Aug + (int64_t)r0 * ld + r0, ld,
+                                    Aug + (int64_t)r0 * ld + j0, ld,
+                                    Aug + (int64_t)r0 * ld + j0, ld, no - r0,
+                                    no - r0, jb);
+      wave_gemm<0>(Aug + (int64_t)r0 * ld + no, ld, Aug + (int64_t)r0 * ld + j0,
+                   ld, Aug + (int64_t)j0 * ld + no, ld, no - r0, no, jb);
+    }
+  }
+  // Q = Z^T Z in K's place
+  wave_gemm<2, G_TA>(Kb, lk, Aug + no, ld, Aug + no, ld, no, no, no);
+  // Y = L^-T Z, blocks from the bottom
+  for (int j0 = ((no - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
+    const int jb = min(NB2, no - j0);
+    wave_tile_stage<NB2>(Aug, ld, j0, jb, W, TILE_LOWER);
+    wave_tile_invert<NB2>(W, TILE_LOWER);
+    wave_tile_apply<NB2, true>(Aug, ld, j0, jb, no, 2 * no, W, false);
+    if (j0 > 0)
+      wave_gemm<0, G_TA>(Aug + no, ld, Aug + (int64_t)j0 * ld, ld,
+                         Aug + (int64_t)j0 * ld + no, ld, j0, no, jb);
   }
   return flag;
 }
@@ -661,10 +874,12 @@ __device__ inline void tri_decode(int64_t p, int m, int &i, int &j) {
   j = r + (int)(p - tri_row_start(r, m));
 }
 
-// Aug holds Q in columns [0, no) and Y in columns [no, 2 no); Kb (ld n) is
-// free scratch.  Returns 1 if a contribution was not finite.
-__device__ int wave_omega(const SymDev &S, int n_out, double *Aug, int ld,
-                          double *Kb, int no, double *om) {
+// Y (leading dimension ldy) and Q (ldq) over the open block in; V (ldv,
+// disjoint from Y) is scratch, and so is Q once V is formed.  Returns 1 if a
+// contribution was not finite.
+__device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
+                          double *Q, int ldq, double *V, int ldv, int no,
+                          double *om) {
   const int lane = lane_id();
   const double g2 = 2.0 * S.g;
   int nonfinite = 0;
@@ -685,11 +900,10 @@ __device__ int wave_omega(const SymDev &S, int n_out, double *Aug, int ld,
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const bool in = p0 + (int64_t)u * WT < npair;
-        const double *row = Aug + (int64_t)ii[u] * ld;
         ti[u] = in ? S.tgt[ii[u]] : 0;
         tj[u] = in ? S.tgt[jj[u]] : 0;
-        qv[u] = in ? row[jj[u]] : 0.0;
-        yv[u] = in ? row[no + jj[u]] : 0.0;
+        qv[u] = in ? Q[(int64_t)ii[u] * ldq + jj[u]] : 0.0;
+        yv[u] = in ? Y[(int64_t)ii[u] * ldy + jj[u]] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
@@ -707,29 +921,28 @@ __device__ int wave_omega(const SymDev &S, int n_out, double *Aug, int ld,
     }
     return nonfinite;
   }
-  // V into columns [0, no), both triangles
+  // V, both triangles
   const int nsq = no * no;
   for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
     double yv[UNR], qv[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int q = q0 + u * WT;
-      const double *row = Aug + (int64_t)(q / no) * ld;
-      qv[u] = q < nsq ? row[q % no] : 0.0;
-      yv[u] = q < nsq ? row[no + q % no] : 0.0;
+      qv[u] = q < nsq ? Q[(int64_t)(q / no) * ldq + q % no] : 0.0;
+      yv[u] = q < nsq ? Y[(int64_t)(q / no) * ldy + q % no] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int q = q0 + u * WT;
       if (q < nsq)
-        Aug[(int64_t)(q / no) * ld + q % no] = yv[u] * yv[u] + qv[u] * qv[u];
+        V[(int64_t)(q / no) * ldv + q % no] = yv[u] * yv[u] + qv[u] * qv[u];
     }
   }
   wave_sync();
   const int nt = S.ntu;
-  // W1 = G^T V (nt x no) into Kb, then Omega_u = W1 G (nt x nt) into Aug
-  wave_gemm<2>(Kb, S.n, S.GT, S.n, Aug, ld, nt, no, no);
-  wave_gemm<2>(Aug, ld, Kb, S.n, S.G, nt, nt, nt, no);
+  // W1 = G^T V (nt x no) into Q's place, then Omega_u = W1 G (nt x nt) into V
+  wave_gemm<2>(Q, ldq, S.GT, S.n, V, ldv, nt, no, no);
+  wave_gemm<2>(V, ldv, Q, ldq, S.G, nt, nt, nt, no);
   const int64_t npair = (int64_t)nt * (nt + 1) / 2;
   for (int64_t p0 = lane; p0 < npair; p0 += UNR * WT) {
     int ta[UNR], tb[UNR];
@@ -745,7 +958,7 @@ __device__ int wave_omega(const SymDev &S, int n_out, double *Aug, int ld,
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const bool in = p0 + (int64_t)u * WT < npair;
-      v[u] = in ? Aug[(int64_t)ta[u] * ld + tb[u]] : 0.0;
+      v[u] = in ? V[(int64_t)ta[u] * ldv + tb[u]] : 0.0;
       const int t = in ? S.ut[ta[u]] : 0, w = in ? S.ut[tb[u]] : 0;
       oi[u] = omega_index(t, w, n_out);
       ov[u] = in ? om[oi[u]] : 0.0;
@@ -807,27 +1020,6 @@ __device__ inline int count_open(const SymDev &S, double Ee) {
       hi = mid;
   }
   return lo;
-}
-
-// Copy a rows x cols block (row-major source ld sl, destination ld dl) with
-// batched loads.
-__device__ inline void wave_copy(double *dst, int dl, const double *src,
-                                 int sl, int rows, int cols) {
-  const int lane = lane_id();
-  const int nq = rows * cols;
-  for (int q0 = lane; q0 < nq; q0 += UNR * WT) {
-    double v[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int q = q0 + u * WT;
-      v[u] = q < nq ? src[(int64_t)(q / cols) * sl + q % cols] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int q = q0 + u * WT;
-      if (q < nq) dst[(int64_t)(q / cols) * dl + q % cols] = v[u];
-    }
-  }
 }
 
 // One symmetry at one energy, one wavefront.  Returns RM_E_* bits.
@@ -957,16 +1149,11 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     }
   }
   if (L.do_t) {
-    // Pm = 1 + K K in columns [0, no), right-hand side K in [no, 2 no)
-    wave_gemm<1>(Aug, ld, Kb, n, Kb, n, no, no, no);
-    wave_copy(Aug + no, ld, Kb, n, no, no);
-    wave_sync();
-    if (wave_lu_solve(Aug, no, ld, no, W)) bits |= RM_E_SINGULAR;
-    // Q = K Y into columns [0, no)
-    wave_gemm<2>(Aug, ld, Kb, n, Aug + no, ld, no, no, no);
+    // Y in Aug's columns [no, 2 no), Q in K's place
+    if (wave_tstep(Aug, ld, Kb, n, no, W)) bits |= RM_E_SINGULAR;
     if (L.omega)
-      nonfinite |= wave_omega(S, L.n_target_out, Aug, ld, Kb, no,
-                              L.omega + (int64_t)e * L.omega_stride);
+      nonfinite |= wave_omega(S, L.n_target_out, Aug + no, ld, Kb, n, Aug, ld,
+                              no, L.omega + (int64_t)e * L.omega_stride);
   }
   if (nonfinite) bits |= RM_E_NONFINITE;
   wave_sync();
