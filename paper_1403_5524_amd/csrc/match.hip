@@ -458,25 +458,42 @@ __device__ void wave_apply_moves(double *A, int ld, int j0, int cnt, int c0,
 enum TileKind { TILE_UNIT_LOWER = 0, TILE_UPPER = 1, TILE_LOWER = 2 };
 template <int NT>
 __device__ void wave_tile_invert(WaveLds &W, int kind) {
+  static_assert(NT == 16 || NT == 32, "16 or 32");
   const int lane = lane_id();
-  if (lane < NT) {
-    const int j = lane;
-    if (kind != TILE_UPPER) {
-#pragma unroll 1
-      for (int q = 0; q < NT; ++q) {
-        double s = q == j ? 1.0 : 0.0;
-        for (int p = j; p < q; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
-        W.Ti[q][j] = kind == TILE_LOWER ? (q >= j ? s / W.T[q][q] : 0.0) : s;
-      }
-    } else {
-#pragma unroll 1
-      for (int q = NT - 1; q >= 0; --q) {
-        double s = q == j ? 1.0 : 0.0;
-        for (int p = q + 1; p <= j; ++p) s = fma(-W.T[q][p], W.Ti[p][j], s);
-        W.Ti[q][j] = q <= j ? s / W.T[q][q] : 0.0;
-      }
+  const int j = lane;  // column of the inverse formed by this lane
+  // the column in registers (two 16-wide vectors, constant indices only);
+  // the block's entries are LDS broadcasts independent of the recurrence
+  d16 xa = (d16)0.0, xb = (d16)0.0;
+#define TI_GET(q) ((q) < 16 ? xa[(q) & 15] : xb[(q) & 15])
+#define TI_SET(q, v)      \
+  if ((q) < 16)           \
+    xa[(q) & 15] = (v);   \
+  else                    \
+    xb[(q) & 15] = (v);
+  if (kind != TILE_UPPER) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      double acc = q == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int p = 0; p < q; ++p) acc = fma(-W.T[q][p], TI_GET(p), acc);
+      if (kind == TILE_LOWER) acc /= W.T[q][q];
+      TI_SET(q, acc);
+    }
+  } else {
+#pragma unroll
+    for (int q = NT - 1; q >= 0; --q) {
+      double acc = q == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int p = q + 1; p < NT; ++p) acc = fma(-W.T[q][p], TI_GET(p), acc);
+      TI_SET(q, acc / W.T[q][q]);
     }
   }
+  if (lane < NT) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) W.Ti[q][j] = TI_GET(q);
+  }
+#undef TI_GET
+#undef TI_SET
   wave_sync();
 }
 
@@ -799,8 +816,8 @@ __device__ void wave_rows_times_tit(double *A, int ld, int r0, int r1, int j0,
 }
 
 // The T step in the workspace of one energy: K (no x no, leading dimension
-// lk) in; Y in columns [no, 2 no) of Aug (leading dimension ld) and Q in K's
-// place out; Aug's columns [0, no) hold L.  Returns nonzero if 1 + K^2 was
+// lk) in; Y in columns [no, 2 no) of Aug (leading dimension ld) and the
+// lower triangle of Q in K's place out; Aug's columns [0, no) hold L.  Returns nonzero if 1 + K^2 was
 // not positive definite in floating point.
 __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
                           WaveLds &W) {
@@ -826,8 +843,8 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
                    ld, Aug + (int64_t)j0 * ld + no, ld, no - r0, no, jb);
     }
   }
-  // Q = Z^T Z in K's place
-  wave_gemm<2, G_TA>(Kb, lk, Aug + no, ld, Aug + no, ld, no, no, no);
+  // Q = Z^T Z in K's place: symmetric, so only its lower triangle
+  wave_gemm<2, G_TA | G_LOWER>(Kb, lk, Aug + no, ld, Aug + no, ld, no, no, no);
   // Y = L^-T Z, blocks from the bottom
   for (int j0 = ((no - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, no - j0);
@@ -874,8 +891,9 @@ __device__ inline void tri_decode(int64_t p, int m, int &i, int &j) {
   j = r + (int)(p - tri_row_start(r, m));
 }
 
-// Y (leading dimension ldy) and Q (ldq) over the open block in; V (ldv,
-// disjoint from Y) is scratch, and so is Q once V is formed.  Returns 1 if a
+// Y (leading dimension ldy) and the lower triangle of Q (ldq) over the open
+// block in; V (ldv, disjoint from Y) is scratch, and so is Q once V is
+// formed.  Returns 1 if a
 // contribution was not finite.
 __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
                           double *Q, int ldq, double *V, int ldv, int no,
@@ -902,7 +920,7 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
         const bool in = p0 + (int64_t)u * WT < npair;
         ti[u] = in ? S.tgt[ii[u]] : 0;
         tj[u] = in ? S.tgt[jj[u]] : 0;
-        qv[u] = in ? Q[(int64_t)ii[u] * ldq + jj[u]] : 0.0;
+        qv[u] = in ? Q[(int64_t)jj[u] * ldq + ii[u]] : 0.0;  // lower triangle
         yv[u] = in ? Y[(int64_t)ii[u] * ldy + jj[u]] : 0.0;
       }
 #pragma unroll
@@ -928,7 +946,8 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int q = q0 + u * WT;
-      qv[u] = q < nsq ? Q[(int64_t)(q / no) * ldq + q % no] : 0.0;
+      const int qi = q / no, qj = q % no;  // Q holds its lower triangle
+      qv[u] = q < nsq ? Q[(int64_t)max(qi, qj) * ldq + min(qi, qj)] : 0.0;
       yv[u] = q < nsq ? Y[(int64_t)(q / no) * ldy + q % no] : 0.0;
     }
 #pragma unroll
