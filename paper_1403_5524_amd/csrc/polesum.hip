@@ -27,10 +27,10 @@ constexpr int PS_KC = 32;   // poles per LDS stage
 constexpr int PS_EW = 4;    // energies per wave
 constexpr int PS_EG = 16;   // energies per workgroup (4 waves)
 
-struct F64Smem {
-  double As[PS_KC][PS_T];
-  double Bs[PS_KC][PS_T];
-  double Ds[PS_EG][PS_KC];
+struct F64Smem {  // two stages: one feeds the MFMAs while the next fills
+  double As[2][PS_KC][PS_T];
+  double Bs[2][PS_KC][PS_T];
+  double Ds[2][PS_EG][PS_KC];
 };
 
 __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
@@ -80,46 +80,60 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
     rb1 = *(const double2 *)(wb + 2);
   }
   double ep0 = S.E_pole[dk[0]], ep1 = S.E_pole[dk[1]];
-
-  for (int k0 = 0; k0 < S.nh_pad; k0 += PS_KC) {
-    *(double2 *)&sm.As[ld_k][ld_c] = ra0;
-    *(double2 *)&sm.As[ld_k][ld_c + 2] = ra1;
+  // stage chunk c (held in registers) into LDS buffer c % 2
+  auto stage = [&](int buf) {
+    *(double2 *)&sm.As[buf][ld_k][ld_c] = ra0;
+    *(double2 *)&sm.As[buf][ld_k][ld_c + 2] = ra1;
     if (!diag) {
-      *(double2 *)&sm.Bs[ld_k][ld_c] = rb0;
-      *(double2 *)&sm.Bs[ld_k][ld_c + 2] = rb1;
+      *(double2 *)&sm.Bs[buf][ld_k][ld_c] = rb0;
+      *(double2 *)&sm.Bs[buf][ld_k][ld_c + 2] = rb1;
     }
-    sm.Ds[de[0]][dk[0]] = ev[0] ? 1.0 / (ep0 - Eloc[0]) : 0.0;
-    sm.Ds[de[1]][dk[1]] = ev[1] ? 1.0 / (ep1 - Eloc[1]) : 0.0;
-    __syncthreads();
-    const int kn = k0 + PS_KC;
-    if (kn < S.nh_pad) {
-      const int64_t off = (int64_t)kn * n_pad;
-      ra0 = *(const double2 *)(wa + off);
-      ra1 = *(const double2 *)(wa + off + 2);
-      if (!diag) {
-        rb0 = *(const double2 *)(wb + off);
-        rb1 = *(const double2 *)(wb + off + 2);
-      }
-      ep0 = S.E_pole[kn + dk[0]];
-      ep1 = S.E_pole[kn + dk[1]];
+    sm.Ds[buf][de[0]][dk[0]] = ev[0] ? 1.0 / (ep0 - Eloc[0]) : 0.0;
+    sm.Ds[buf][de[1]][dk[1]] = ev[1] ? 1.0 / (ep1 - Eloc[1]) : 0.0;
+  };
+  // load chunk starting at pole kn into registers
+  auto fetch = [&](int kn) {
+    const int64_t off = (int64_t)kn * n_pad;
+    ra0 = *(const double2 *)(wa + off);
+    ra1 = *(const double2 *)(wa + off + 2);
+    if (!diag) {
+      rb0 = *(const double2 *)(wb + off);
+      rb1 = *(const double2 *)(wb + off + 2);
     }
-    const double(*Bsel)[PS_T] = diag ? sm.As : sm.Bs;
+    ep0 = S.E_pole[kn + dk[0]];
+    ep1 = S.E_pole[kn + dk[1]];
+  };
+  stage(0);
+  if (PS_KC < S.nh_pad) fetch(PS_KC);
+  __syncthreads();
+
+  int buf = 0;
+  for (int k0 = 0; k0 < S.nh_pad; k0 += PS_KC, buf ^= 1) {
+    const double(*As)[PS_T] = sm.As[buf];
+    const double(*Bsel)[PS_T] = diag ? sm.As[buf] : sm.Bs[buf];
+    const double(*Ds)[PS_KC] = sm.Ds[buf];
 #pragma unroll
     for (int kk = 0; kk < PS_KC; kk += 4) {
       const int kr = kk + kq;
-      const double a0 = sm.As[kr][col];
-      const double a1 = sm.As[kr][16 + col];
+      const double a0 = As[kr][col];
+      const double a1 = As[kr][16 + col];
       const double b0 = Bsel[kr][col];
       const double b1 = Bsel[kr][16 + col];
 #pragma unroll
       for (int e = 0; e < PS_EW; ++e) {
-        const double dd = sm.Ds[wave * PS_EW + e][kr];
+        const double dd = Ds[wave * PS_EW + e][kr];
         const double sa0 = a0 * dd, sa1 = a1 * dd;
         acc[e][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa0, b0, acc[e][0][0], 0, 0, 0);
         acc[e][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa0, b1, acc[e][0][1], 0, 0, 0);
         acc[e][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa1, b0, acc[e][1][0], 0, 0, 0);
         acc[e][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa1, b1, acc[e][1][1], 0, 0, 0);
       }
+    }
+    // the next chunk (already in registers) into the other buffer, then
+    // start loading the one after it; one barrier per chunk
+    if (k0 + PS_KC < S.nh_pad) {
+      stage(buf ^ 1);
+      if (k0 + 2 * PS_KC < S.nh_pad) fetch(k0 + 2 * PS_KC);
     }
     __syncthreads();
   }
@@ -152,7 +166,10 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
   }
 }
 
-__global__ __launch_bounds__(256) void polesum_f64_kernel(PsLaunch L) {
+// two workgroups per CU (41 KB of LDS and at most 256 registers per lane
+// each), so one's barrier and staging overlap the other's MFMAs
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void polesum_f64_kernel(PsLaunch L) {
   __shared__ F64Smem sm;
   __shared__ int s_item;
   const int tid = threadIdx.x;
