@@ -4,9 +4,12 @@ plus the max relative error of Omega against the FP64 CPU oracle.
 
 One step = one rm_sweep_energies call over the whole mesh (channel functions,
 pole sum, matching, K, T, Omega for every energy), inputs resident in HBM.
+The headline is the plain FP64 path (--prec); the mixed precisions named by
+--also are timed on the same workload and reported with their speedup.
 Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
+                    [--also bf16x3,fp32] [--graph] [--workload c2|c3|c4]
 """
 import argparse
 import json
@@ -28,11 +31,14 @@ PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # A figure applies only while its kernel source is the one measured.
 PMC_TRAFFIC = {
     "match_kernel": {"src": "paper_1403_5524_amd/csrc/match.hip",
-                     "sha256_16": "4f908263f1947deb",
-                     "bytes_per_energy": 30.79e6 + 17.03e6},
+                     "sha256_16": "f42786a35b6ab58e",
+                     "bytes_per_energy": 23.14e6 + 9.49e6},
     "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
-                     "sha256_16": "dc26a00f811564ec",
-                     "bytes_per_energy": 195.5e3 + 320.0e3},
+                     "sha256_16": "a245a42754ef98d7",
+                     "bytes_per_energy": 0.194e6 + 0.320e6},
+    "polesum_bf16x3": {"src": "paper_1403_5524_amd/csrc/polesum_pd.hip",
+                       "sha256_16": "964e1c800446329d",
+                       "bytes_per_energy": 0.338e6 + 0.822e6},
 }
 
 
@@ -95,7 +101,10 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=sorted(PREC_CODE))
     ap.add_argument("--M", type=int, default=100000)
     ap.add_argument("--err-sample", type=int, default=32)
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--also", default="bf16x3,fp32",
+                    help="comma-separated precisions also timed on the same "
+                         "workload (reported under other_precisions)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
                     help="c2 is the headline workload; c3 (40 symmetries) "
@@ -135,47 +144,6 @@ def main():
     E = torch.as_tensor(w.mesh, dtype=torch.float64, device=dev)
     omega = torch.empty((M, P), dtype=torch.float64, device=dev)
     status = torch.empty((M,), dtype=torch.int32, device=dev)
-    opts = native.make_opts(prec=PREC_CODE[args.prec])
-
-    for i in range(args.warmup):
-        native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
-        torch.cuda.synchronize()
-        note("warmup %d done" % (i + 1))
-    native.rm_profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    native.rm_profile(False)
-    ms = (t1 - t0) * 1e3 / args.steps
-    note("timed %d steps: %.2f ms/step" % (args.steps, ms))
-    stage = {k: native.rm_profile_query(k) for k in ("polesum", "match")}
-    graph_ms = None
-    if args.graph:
-        plan = native.Plan(hs, n_t, E, opts, omega, status)
-        plan.execute()
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        for i in range(args.steps):
-            plan.execute()
-        torch.cuda.synchronize()
-        graph_ms = (time.perf_counter() - g0) * 1e3 / args.steps
-        plan.free()
-        note("graph replays: %.2f ms/step" % graph_ms)
-
-    # accuracy against the oracle on a seeded sample of the mesh
-    idx = workloads.sample_indices(M, args.err_sample, seed=7)
-    ref = None
-    for s in w.syms:
-        r = oracle.sweep(s.as_dict(), w.mesh[idx], n_target=n_t)["omega"]
-        ref = r if ref is None else ref + r
-    got = omega[torch.as_tensor(idx, device=dev)].cpu().numpy()
-    den = np.maximum(np.abs(ref).max(axis=1), 1e-300)
-    err = float((np.abs(got - ref).max(axis=1) / den).max())
-    st = status.cpu().numpy()
-    note("max rel err of Omega on %d sampled energies: %.3e" % (idx.size, err))
 
     pairs = 0.0
     flops_step = 0.0
@@ -185,25 +153,83 @@ def main():
         pairs += float((n_open * (n_open + 1) // 2).sum())
         flops_step += float(s.n) * (s.n + 1) * s.n_poles * M   # symmetric
         mflops_step += match_flops(s.n, n_open)
-    kernels = {}
-    for key, flops, peak, stg, tkey in (
-            ("polesum_%s" % args.prec, flops_step, PEAK[args.prec], "polesum",
-             "polesum_fp64" if args.prec == "fp64" else None),
-            ("match_kernel", mflops_step, PEAK["fp64"], "match",
-             "match_kernel")):
-        ms_tot, launches = stage[stg]
-        lp = launches / args.steps if launches else 0
-        ach = flops * args.steps / (ms_tot * 1e-3) / 1e12 if ms_tot > 0 else None
-        traffic = measured_traffic(tkey, M / lp) if (tkey and lp) else None
-        kernels[key] = {
-            "bound": "mfma", "kernel": key, "achieved": ach, "peak": peak,
-            "unit": "TFLOP/s", "frac": ach / peak if ach else None,
-            "traffic": traffic,
-            "flops_per_launch": flops / lp if lp else None,
-            "avg_launch_ms": ms_tot / launches if launches else None,
-            "ms_per_step": ms_tot / args.steps}
-    dom = max(kernels.values(), key=lambda k: k["ms_per_step"])
+    idx = workloads.sample_indices(M, args.err_sample, seed=7)
+    ref = None
+    for s in w.syms:
+        r = oracle.sweep(s.as_dict(), w.mesh[idx], n_target=n_t)["omega"]
+        ref = r if ref is None else ref + r
+    den = np.maximum(np.abs(ref).max(axis=1), 1e-300)
+
+    def run(prec, graph):
+        """Warm up, time `steps` sweeps at one precision, check Omega."""
+        opts = native.make_opts(prec=PREC_CODE[prec])
+        for i in range(args.warmup):
+            native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
+            torch.cuda.synchronize()
+            note("%s warmup %d done" % (prec, i + 1))
+        native.rm_profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        native.rm_profile(False)
+        ms = (t1 - t0) * 1e3 / args.steps
+        note("%s: timed %d steps: %.2f ms/step" % (prec, args.steps, ms))
+        stage = {k: native.rm_profile_query(k) for k in ("polesum", "match")}
+        graph_ms = None
+        if graph:
+            plan = native.Plan(hs, n_t, E, opts, omega, status)
+            plan.execute()
+            torch.cuda.synchronize()
+            g0 = time.perf_counter()
+            for i in range(args.steps):
+                plan.execute()
+            torch.cuda.synchronize()
+            graph_ms = (time.perf_counter() - g0) * 1e3 / args.steps
+            plan.free()
+            note("%s: graph replays %.2f ms/step" % (prec, graph_ms))
+        got = omega[torch.as_tensor(idx, device=dev)].cpu().numpy()
+        err = float((np.abs(got - ref).max(axis=1) / den).max())
+        st = status.cpu().numpy()
+        note("%s: max rel err of Omega on %d sampled energies: %.3e"
+             % (prec, idx.size, err))
+        kernels = {}
+        for key, flops, peak, stg, tkey in (
+                ("polesum_%s" % prec, flops_step, PEAK[prec], "polesum",
+                 "polesum_%s" % prec),
+                ("match_kernel", mflops_step, PEAK["fp64"], "match",
+                 "match_kernel")):
+            ms_tot, launches = stage[stg]
+            lp = launches / args.steps if launches else 0
+            ach = (flops * args.steps / (ms_tot * 1e-3) / 1e12
+                   if ms_tot > 0 else None)
+            traffic = measured_traffic(tkey, M / lp) if (tkey and lp) else None
+            kernels[key] = {
+                "bound": "mfma", "kernel": key, "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak if ach else None,
+                "traffic": traffic,
+                "flops_per_launch": flops / lp if lp else None,
+                "avg_launch_ms": ms_tot / launches if launches else None,
+                "ms_per_step": ms_tot / args.steps}
+        return {"ms": ms, "err": err, "flagged": int((st != 0).sum()),
+                "stage": {k: v[0] / args.steps for k, v in stage.items()},
+                "kernels": kernels, "graph_ms": graph_ms}
+
+    head = run(args.prec, args.graph)
+    others = {}
+    for prec in [p for p in args.also.split(",") if p and p != args.prec]:
+        r = run(prec, False)
+        others[prec] = {
+            "value": M / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+            "max_rel_err_omega": r["err"], "status_flagged": r["flagged"],
+            "speedup_over_%s" % args.prec: head["ms"] / r["ms"],
+            "stage_ms_per_step": r["stage"], "kernels": r["kernels"]}
+    ms = head["ms"]
+    dom = max(head["kernels"].values(), key=lambda k: k["ms_per_step"])
     roof = dict(dom)
+    graph_ms = head["graph_ms"]
     out = {
         "metric": "energy points/sec (K->Omega) at n=200 ch, N_H=8000; "
                   "max rel err of Omega vs FP64 oracle",
@@ -222,15 +248,16 @@ def main():
                    "n_poles": nh, "energies": M,
                    "mesh_Ry": [float(w.mesh_spec[0]), float(w.mesh_spec[1])],
                    "precision": args.prec},
-        "max_rel_err_omega": err,
+        "max_rel_err_omega": head["err"],
         "err_sample": int(idx.size),
         "omega_per_s": pairs / (ms * 1e-3),
-        "status_flagged": int((st != 0).sum()),
-        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stage.items()},
-        "kernels": kernels,
+        "status_flagged": head["flagged"],
+        "stage_ms_per_step": head["stage"],
+        "kernels": head["kernels"],
         "graph_ms_per_step": graph_ms,
         "graph_value": (M / (graph_ms * 1e-3)) if graph_ms else None,
         "roofline": roof,
+        "other_precisions": others,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)
