@@ -20,6 +20,9 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
 * ``rmatrix.t_matrix``            T = 2iK (1 - iK)^-1
 * ``rmatrix.collision_strengths`` Omega = sum (g/2) |T|^2 per target pair
 * ``rmatrix.sweep``               all of the above over an energy mesh
+* ``postproc.gaussian_convolve``  Omega(E) convolved with a Gaussian of given
+                                   FWHM on the mesh (Sec. 4-5 figures)
+* ``postproc.effective_collision_strengths``  Maxwellian averages Upsilon(kT)
 
 It shares no code with the HIP path (``paper_1403_5524_amd``) and imports
 nothing from it; both sides receive the same seeded arrays from
@@ -30,6 +33,8 @@ from .coulomb import (coulomb_fg, open_channel_functions,
 from .rmatrix import (r_matrix, channel_data, k_matrix, k_matrix_elimination,
                       k_matrix_lambda, t_matrix, s_matrix, eigenphases, collision_strengths,
                       omega_pair_index, sweep)
+from .postproc import (gaussian_convolve, effective_collision_strengths,
+                       trapezoid_weights)
 
 __all__ = [
     "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
@@ -37,4 +42,5 @@ __all__ = [
     "k_matrix_lambda",
     "t_matrix", "s_matrix", "eigenphases", "collision_strengths",
     "omega_pair_index", "sweep",
+    "gaussian_convolve", "effective_collision_strengths", "trapezoid_weights",
 ]
