@@ -260,6 +260,56 @@ int rm_mesh_from_density(const float *dens, int32_t nw, double lo, double hi,
                          double floor_frac, int64_t M, double *E_out,
                          void *stream);
 
+/* ---- Post-processing of Omega(E) on the mesh ------------------------
+ * Omega arrays are energy-major [M][P] FP64 device arrays, P the number of
+ * packed level pairs (t <= u, row-major over t) as rm_sweep_energies writes
+ * them.  E (device [M]) must be ascending.
+ *
+ * rm_convolve_gaussian: the Gaussian smoothing applied before comparison
+ * with measurements (Sec. 4 and 5, FWHM 4-124 meV in the paper's figures):
+ *   out(E_i) = sum_j g_ij in(E_j) / sum_j g_ij,
+ *   g_ij = exp(-(E_i - E_j)^2 / (2 s^2)) dE_j,  s = fwhm / (2 sqrt(2 ln 2)),
+ * dE_j the trapezoid weights of the mesh (half intervals at its ends), the
+ * sum cut at |E_i - E_j| <= 8 s.  fwhm in the units of E.  M = 1 copies the
+ * input.  omega_out must not overlap omega_in.  The call is asynchronous on
+ * `stream` (it allocates and frees 32 M bytes of stream-ordered workspace).
+ * Errors: RM_ERR_ARG (M < 0, P < 1, fwhm not finite and > 0, null pointer,
+ * in place), RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_convolve_gaussian(const double *E, int64_t M, const double *omega_in,
+                         int64_t P, double fwhm, double *omega_out,
+                         void *stream);
+
+/* rm_effective_collision_strengths: Maxwellian averages of every level pair
+ * (t, u) at the nT temperatures kT (host [nT], > 0, units of E), the upper
+ * level e = max(e_level[t], e_level[u]) (host [n_target]) and eps = E - e:
+ *   Upsilon(kT) = int_0^inf Omega(eps) exp(-eps/kT) d(eps/kT),
+ * Omega held constant from threshold to the first mesh point above e, the
+ * trapezoid rule between mesh points, truncated at the last point (0 for a
+ * pair whose upper level is at or above the mesh top).  Output upsilon
+ * (device [P][nT], P = n_target (n_target + 1) / 2).  Host arrays are read
+ * before the call returns; the call synchronises `stream`.
+ * Errors: RM_ERR_ARG (M < 0, n_target < 1, nT < 0, kT not finite and > 0,
+ * level energy not finite, null pointer), RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_effective_collision_strengths(const double *E, int64_t M,
+                                     const double *omega, int32_t n_target,
+                                     const double *e_level, const double *kT,
+                                     int32_t nT, double *upsilon,
+                                     void *stream);
+
+/* rm_group_collision_strengths: statistical averaging over the levels of
+ * groups such as the fine-structure levels of a term (the level-averaged
+ * cross sections of Sec. 5): out[i][pair(a, b)] (device [M][n_group (n_group
+ * + 1) / 2]) is the sum of omega[i][pair(t, u)] over every level pair t <= u
+ * with {group[t], group[u]} = {a, b}; group (host [n_target]) holds values in
+ * [0, n_group).  The averaged cross section from group a follows as
+ * pi Omega(a, b) / (g_a k^2), g_a the summed statistical weight of a.  The
+ * call synchronises `stream`.
+ * Errors: RM_ERR_ARG (M < 0, n_target < 1, n_group < 1, group index out of
+ * range, null pointer), RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_group_collision_strengths(const double *omega, int64_t M,
+                                 int32_t n_target, const int32_t *group,
+                                 int32_t n_group, double *out, void *stream);
+
 /* Message for the last non-RM_OK return on this thread ("" if none). */
 const char *rm_last_error(void);
 

@@ -23,6 +23,8 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
 * ``postproc.gaussian_convolve``  Omega(E) convolved with a Gaussian of given
                                    FWHM on the mesh (Sec. 4-5 figures)
 * ``postproc.effective_collision_strengths``  Maxwellian averages Upsilon(kT)
+* ``postproc.group_collision_strengths``  Omega summed over the level pairs of
+                                   level groups (statistical averaging)
 
 It shares no code with the HIP path (``paper_1403_5524_amd``) and imports
 nothing from it; both sides receive the same seeded arrays from
@@ -34,7 +36,7 @@ from .rmatrix import (r_matrix, channel_data, k_matrix, k_matrix_elimination,
                       k_matrix_lambda, t_matrix, s_matrix, eigenphases, collision_strengths,
                       omega_pair_index, sweep)
 from .postproc import (gaussian_convolve, effective_collision_strengths,
-                       trapezoid_weights)
+                       trapezoid_weights, group_collision_strengths)
 
 __all__ = [
     "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
@@ -43,4 +45,5 @@ __all__ = [
     "t_matrix", "s_matrix", "eigenphases", "collision_strengths",
     "omega_pair_index", "sweep",
     "gaussian_convolve", "effective_collision_strengths", "trapezoid_weights",
+    "group_collision_strengths",
 ]

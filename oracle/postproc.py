@@ -26,6 +26,17 @@ plainly here):
   threshold to the first such point, the product Omega(eps) exp(-eps/kT) is
   integrated by the trapezoid rule between mesh points, and the integral is
   truncated at the last mesh point.
+* Statistical averaging over the levels of a group (the fine-structure
+  levels of a term, Sec. 5's averaged cross sections): cross sections
+  averaged over initial levels with weights g_t and summed over final levels
+  correspond to collision strengths summed over level pairs,
+      Omega_G(a, b) = sum over unordered level pairs {t, u} with
+                      {group(t), group(u)} = {a, b} of Omega(t, u),
+  so that sigma(a -> b) = pi Omega_G(a, b) / (g_a k^2) with g_a = sum of g_t
+  over the levels of a.  Each unordered level pair, elastic ones included,
+  lands in exactly one unordered group pair.
+* A one-point mesh has no trapezoid weight; its convolution is the identity
+  (the limit of the normalised sum as the weight goes to zero).
 """
 import numpy as np
 
@@ -51,6 +62,9 @@ def gaussian_convolve(E, omega, fwhm):
     s = fwhm / FWHM_PER_SIGMA
     dE = trapezoid_weights(E)
     out = np.empty_like(om)
+    if E.size == 1:
+        out[:] = om
+        return out
     for i in range(E.size):
         lo = np.searchsorted(E, E[i] - CUTOFF_SIGMAS * s, side="left")
         hi = np.searchsorted(E, E[i] + CUTOFF_SIGMAS * s, side="right")
@@ -86,3 +100,19 @@ def effective_collision_strengths(E, omega, e_level, n_target, kT):
                     total += np.sum(0.5 * (y[1:] + y[:-1]) * np.diff(x))
                 ups[p, q] = total
     return ups
+
+
+def group_collision_strengths(omega, n_target, group, n_group):
+    """Omega_G [M, n_group (n_group + 1) / 2] from Omega [M, P] and the group
+    index of every level (0 <= group[t] < n_group)."""
+    om = np.asarray(omega, dtype=np.float64)
+    group = np.asarray(group)
+    Pg = n_group * (n_group + 1) // 2
+    out = np.zeros((om.shape[0], Pg))
+    for t in range(n_target):
+        for u in range(t, n_target):
+            p = t * n_target - t * (t - 1) // 2 + (u - t)
+            a, b = sorted((int(group[t]), int(group[u])))
+            q = a * n_group - a * (a - 1) // 2 + (b - a)
+            out[:, q] += om[:, p]
+    return out

@@ -32,7 +32,9 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_mlp_get_params", "rm_mlp_set_params", "rm_mlp_forward",
             "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
             "rm_plan_create", "rm_plan_execute", "rm_plan_info",
-            "rm_plan_free", "rm_last_error")
+            "rm_plan_free", "rm_convolve_gaussian",
+            "rm_effective_collision_strengths",
+            "rm_group_collision_strengths", "rm_last_error")
 
 
 class RmError(RuntimeError):
@@ -97,6 +99,11 @@ def lib():
         L.rm_plan_execute.argtypes = [vp, vp]
         L.rm_plan_info.argtypes = [vp, vp, vp, vp, i32]
         L.rm_plan_free.argtypes = [vp]
+        L.rm_convolve_gaussian.argtypes = [vp, i64, vp, i64, f64, vp, vp]
+        L.rm_effective_collision_strengths.argtypes = [vp, i64, vp, i32, vp,
+                                                       vp, i32, vp, vp]
+        L.rm_group_collision_strengths.argtypes = [vp, i64, i32, vp, i32, vp,
+                                                   vp]
         L.rm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "rm_last_error":
@@ -360,3 +367,45 @@ class Plan:
             self.free()
         except Exception:
             pass
+
+
+def rm_convolve_gaussian(E, omega, fwhm, out=None):
+    """Gaussian smoothing of omega [M, P] (CUDA float64) on the mesh E [M]."""
+    import torch
+    M, P = int(omega.shape[0]), int(omega.shape[1])
+    if out is None:
+        out = torch.empty_like(omega)
+    _check(lib().rm_convolve_gaussian(_ptr(E), M, _ptr(omega), P,
+                                      float(fwhm), _ptr(out), _stream()))
+    return out
+
+
+def rm_effective_collision_strengths(E, omega, e_level, n_target, kT):
+    """Upsilon [P, nT] (CUDA float64) from omega [M, P]; e_level and kT are
+    host sequences."""
+    import torch
+    lev = np.ascontiguousarray(e_level, dtype=np.float64)
+    t = np.ascontiguousarray(np.atleast_1d(kT), dtype=np.float64)
+    if lev.size != n_target:
+        raise RmError(RM_ERR_ARG, "e_level must hold n_target values")
+    P = n_target * (n_target + 1) // 2
+    ups = torch.empty((P, t.size), dtype=torch.float64, device=omega.device)
+    _check(lib().rm_effective_collision_strengths(
+        _ptr(E), int(omega.shape[0]), _ptr(omega), int(n_target),
+        lev.ctypes.data, t.ctypes.data, int(t.size), _ptr(ups), _stream()))
+    return ups
+
+
+def rm_group_collision_strengths(omega, n_target, group, n_group):
+    """Omega summed over the level pairs of level groups: [M, Pg]."""
+    import torch
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    if g.size != n_target:
+        raise RmError(RM_ERR_ARG, "group must hold n_target values")
+    Pg = n_group * (n_group + 1) // 2
+    out = torch.empty((int(omega.shape[0]), Pg), dtype=torch.float64,
+                      device=omega.device)
+    _check(lib().rm_group_collision_strengths(
+        _ptr(omega), int(omega.shape[0]), int(n_target), g.ctypes.data,
+        int(n_group), _ptr(out), _stream()))
+    return out

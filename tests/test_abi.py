@@ -97,3 +97,50 @@ def test_null_handles_rejected(L):
     assert L.rm_collision_strengths(None, None, None, None, 0, 1, None,
                                     None) == native.RM_ERR_ARG
     assert L.rm_free(None) == native.RM_OK
+
+
+def test_postproc_rejects_invalid(L):
+    f64 = ctypes.c_double
+    dummy = ctypes.c_void_p(64)   # never dereferenced: rejected first
+    other = ctypes.c_void_p(128)
+    conv = L.rm_convolve_gaussian
+    assert conv(dummy, 5, dummy, 0, f64(0.1), other, None) == native.RM_ERR_ARG
+    assert conv(dummy, -1, dummy, 3, f64(0.1), other, None) == native.RM_ERR_ARG
+    for bad in (0.0, -0.1, float("nan"), float("inf")):
+        assert conv(dummy, 5, dummy, 3, f64(bad), other, None) == \
+            native.RM_ERR_ARG
+    assert b"fwhm" in L.rm_last_error()
+    assert conv(None, 5, dummy, 3, f64(0.1), other, None) == native.RM_ERR_ARG
+    assert conv(dummy, 5, dummy, 3, f64(0.1), dummy, None) == \
+        native.RM_ERR_ARG
+    assert b"in place" in L.rm_last_error()
+    assert conv(None, 0, None, 3, f64(0.1), None, None) == native.RM_OK
+
+    lev = np.array([0.0, 0.3], dtype=np.float64)
+    ups = L.rm_effective_collision_strengths
+    for kT in ([0.0], [-1.0], [float("nan")]):
+        t = np.array(kT, dtype=np.float64)
+        assert ups(dummy, 5, dummy, 2, lev.ctypes.data, t.ctypes.data, 1,
+                   other, None) == native.RM_ERR_ARG
+    t = np.array([0.5], dtype=np.float64)
+    nan_lev = np.array([0.0, float("nan")], dtype=np.float64)
+    assert ups(dummy, 5, dummy, 2, nan_lev.ctypes.data, t.ctypes.data, 1,
+               other, None) == native.RM_ERR_ARG
+    assert ups(dummy, 5, dummy, 0, lev.ctypes.data, t.ctypes.data, 1,
+               other, None) == native.RM_ERR_ARG
+    assert ups(None, 5, None, 2, lev.ctypes.data, t.ctypes.data, 1,
+               other, None) == native.RM_ERR_ARG
+
+    grp = L.rm_group_collision_strengths
+    g = np.array([0, 2], dtype=np.int32)
+    assert grp(dummy, 5, 2, g.ctypes.data, 2, other, None) == \
+        native.RM_ERR_ARG
+    assert b"group" in L.rm_last_error()
+    g = np.array([0, -1], dtype=np.int32)
+    assert grp(dummy, 5, 2, g.ctypes.data, 2, other, None) == \
+        native.RM_ERR_ARG
+    g = np.array([0, 1], dtype=np.int32)
+    assert grp(dummy, 5, 2, g.ctypes.data, 0, other, None) == \
+        native.RM_ERR_ARG
+    assert grp(None, 5, 2, g.ctypes.data, 2, None, None) == native.RM_ERR_ARG
+    assert grp(None, 0, 2, g.ctypes.data, 2, None, None) == native.RM_OK

@@ -112,3 +112,49 @@ def test_upsilon_pair_columns_and_closed_pairs():
                 # constant Omega: c (1 - e^-x0) + trapezoid of c e^-x on
                 # [x0, X], which tends to c (e^-x0 - e^-X)
                 assert abs(ups[p, 0] - cols[p] * (1 - np.exp(-X))) < 1e-6 * cols[p]
+
+
+def test_convolution_of_one_point_mesh_is_identity():
+    om = np.array([[0.5, -2.0]])
+    assert np.array_equal(oracle.gaussian_convolve(np.array([1.0]), om, 0.1), om)
+
+
+def _full_symmetric(om_row, n_t):
+    """Packed upper triangle -> full symmetric n_t x n_t matrix."""
+    F = np.zeros((n_t, n_t))
+    for t in range(n_t):
+        for u in range(t, n_t):
+            F[t, u] = F[u, t] = om_row[oracle.omega_pair_index(t, u, n_t)]
+    return F
+
+
+def test_grouping_by_ordered_pair_sums():
+    """Brute force over ordered level pairs: for a != b the block sum of the
+    full symmetric matrix; for a == b half of the block sum plus half of its
+    diagonal (each unordered pair once, elastic ones included)."""
+    rng = np.random.default_rng(3)
+    n_t, n_g = 7, 3
+    group = np.array([2, 0, 1, 0, 2, 2, 1])
+    P = n_t * (n_t + 1) // 2
+    om = rng.uniform(0.0, 1.0, size=(4, P))
+    out = oracle.group_collision_strengths(om, n_t, group, n_g)
+    for i in range(om.shape[0]):
+        F = _full_symmetric(om[i], n_t)
+        for a in range(n_g):
+            for b in range(a, n_g):
+                ia, ib = np.where(group == a)[0], np.where(group == b)[0]
+                blk = F[np.ix_(ia, ib)]
+                ref = blk.sum() if a != b else 0.5 * (blk.sum() + np.trace(blk))
+                q = oracle.omega_pair_index(a, b, n_g)
+                assert abs(out[i, q] - ref) < 1e-14 * max(1.0, abs(ref))
+
+
+def test_grouping_identity_and_total():
+    rng = np.random.default_rng(4)
+    n_t = 5
+    P = n_t * (n_t + 1) // 2
+    om = rng.normal(size=(3, P))
+    same = oracle.group_collision_strengths(om, n_t, np.arange(n_t), n_t)
+    assert np.array_equal(same, om)
+    one = oracle.group_collision_strengths(om, n_t, np.zeros(n_t, int), 1)
+    assert np.allclose(one[:, 0], om.sum(axis=1), rtol=0, atol=1e-13)
