@@ -10,6 +10,11 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
                     [--also bf16x3,fp32] [--graph] [--workload c2|c3|c4]
+                    [--no-postproc]
+
+After the headline sweep, the sweep's FP64 Omega is smoothed, averaged into
+effective collision strengths and summed over level groups; those kernels'
+times and rooflines are reported under "postproc".
 """
 import argparse
 import json
@@ -93,6 +98,59 @@ def cpu_baseline(sym, mesh, count):
                       % (count, mesh.size, dt)}
 
 
+RYD_EV = 13.605693122994
+
+
+def postproc_leg(native, torch, E, omega, mesh, e_level, n_t, steps):
+    """Time the post-processing of the sweep's Omega: Gaussian smoothing at
+    100 meV FWHM, effective collision strengths at 8 temperatures, sums over
+    20 groups of levels.  Kernel times come from rm_profile's events."""
+    M, P = int(omega.shape[0]), int(omega.shape[1])
+    fwhm = 0.1 / RYD_EV
+    s = fwhm / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+    lo = np.searchsorted(mesh, mesh - 8.0 * s, side="left")
+    hi = np.searchsorted(mesh, mesh + 8.0 * s, side="right")
+    conv_flops = 2.0 * float((hi - lo).sum()) * P
+    kT = np.geomspace(0.05, 5.0, 8)
+    n_g = max(1, n_t // 10)
+    group = np.minimum(np.arange(n_t) // 10, n_g - 1)
+    Pg = n_g * (n_g + 1) // 2
+    out = torch.empty_like(omega)
+    calls = {
+        "convolve": (lambda: native.rm_convolve_gaussian(E, omega, fwhm, out),
+                     "mfma", conv_flops, 78.6, "TFLOP/s", 1e12),
+        "upsilon": (lambda: native.rm_effective_collision_strengths(
+                        E, omega, e_level, n_t, kT),
+                    "hbm", 8.0 * M * P, 8000.0, "GB/s", 1e9),
+        "group": (lambda: native.rm_group_collision_strengths(
+                      omega, n_t, group, n_g),
+                  "hbm", 8.0 * M * (P + Pg), 8000.0, "GB/s", 1e9),
+    }
+    res = {}
+    for name, (fn, bound, units, peak, unit, scale) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        native.rm_profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        k_ms, launches = native.rm_profile_query(name)
+        native.rm_profile(False)
+        k_ms /= max(1, launches)
+        ach = units / (k_ms * 1e-3) / scale if k_ms > 0 else None
+        res[name] = {"bound": bound, "achieved": ach, "peak": peak,
+                     "unit": unit, "frac": ach / peak if ach else None,
+                     "kernel_ms": k_ms, "call_ms": wall,
+                     "algorithmic": units}
+        note("postproc %s: kernel %.3f ms, call %.3f ms" % (name, k_ms, wall))
+    res["setup"] = {"fwhm_meV": 100.0, "kT_Ry": [float(x) for x in kT],
+                    "n_group": n_g, "transitions": P}
+    del out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +169,8 @@ def main():
                          "and c4 (1500 channels) time a prefix of their mesh")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of a hipGraph-captured plan")
+    ap.add_argument("--no-postproc", action="store_true",
+                    help="skip timing the post-processing of Omega")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -218,6 +278,11 @@ def main():
                 "kernels": kernels, "graph_ms": graph_ms}
 
     head = run(args.prec, args.graph)
+    post = None
+    if not args.no_postproc and len(w.syms) == 1 and sym.target is None:
+        # every channel its own target level: level energies are thresholds
+        post = postproc_leg(native, torch, E, omega, w.mesh, sym.e_thr, n_t,
+                            max(1, args.steps))
     others = {}
     for prec in [p for p in args.also.split(",") if p and p != args.prec]:
         r = run(prec, False)
@@ -258,6 +323,7 @@ def main():
         "graph_value": (M / (graph_ms * 1e-3)) if graph_ms else None,
         "roofline": roof,
         "other_precisions": others,
+        "postproc": post,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)

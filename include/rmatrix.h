@@ -213,8 +213,11 @@ int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m,
  * every later call of this process bracket each kernel launch with HIP
  * events on the caller's stream; rm_profile(0) stops recording.
  * rm_profile_query synchronises on the recorded events and returns, for
- * stage 1 (pole sum), 2 (channel functions, matching, K, T, Omega) or 3
- * (rm_plan_execute graph replays), the summed time in milliseconds and the
+ * stage 1 (pole sum), 2 (channel functions, matching, K, T, Omega), 3
+ * (rm_plan_execute graph replays), 4 (the banded product of
+ * rm_convolve_gaussian), 5 (the pass over Omega of
+ * rm_effective_collision_strengths) or 6 (the pass of
+ * rm_group_collision_strengths), the summed time in milliseconds and the
  * number of launches (stage 0 is kept for compatibility and stays empty).
  * Not thread-safe with concurrent sweeps while enabled. */
 int rm_profile(int32_t enable);

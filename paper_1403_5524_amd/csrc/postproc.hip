@@ -15,12 +15,15 @@
 //   over every unordered level pair whose two groups form the group pair.
 //
 // Omega is energy-major [M][P].  The convolution is a banded matrix product
-// Omega~ = G Omega with G normalised row by row; it runs on the FP64 matrix
-// cores.  A workgroup owns 64 outputs and 256 transitions, walks the band of
-// mesh rows its outputs reach in stages of 16, forms those rows' weights in
-// LDS (each exp once per workgroup) beside the staged Omega rows, and every
-// wave applies its 16 outputs' weights with 16x16x4 MFMAs.  Upsilon and the
-// grouping are single passes over Omega (HBM-bound).
+// Omega~ = G Omega, each row of G divided by its sum at the end; it runs on
+// the FP64 matrix cores.  A workgroup owns 64 outputs and 256 transitions,
+// walks the band of mesh rows its outputs reach in stages of 16, forms those
+// rows' weights in LDS (each exp once per workgroup, its row sum kept on the
+// way) beside the staged Omega rows, and every wave applies its 16 outputs'
+// weights with 16x16x4 MFMAs.  Up to 128 transitions per workgroup keep it
+// at 48 KB of LDS and at most 168 registers per lane, so three workgroups
+// share a CU and one's staging and barrier overlap the others' MFMAs.  Upsilon and the grouping are single passes over Omega
+// (HBM-bound).
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -41,15 +44,42 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr double CV_CUT = 8.0;   // kernel cut, in standard deviations
 constexpr int CV_BM = 64;        // outputs per workgroup, 16 per wave
-constexpr int CV_BP = 256;       // transitions per workgroup
+constexpr int CV_BP = 128;       // transitions per workgroup, at most
 constexpr int CV_NB = CV_BP / 16;
 constexpr int CV_KC = 16;        // mesh rows per stage
-constexpr int CV_OPAD = 2;       // LDS row padding, doubles
 
-struct CvSmem {
+constexpr int CV_OPAD = 16;      // Omega row padding: the four rows an MFMA
+                                 // operand spans fall on different banks
+
+struct CvSmem {  // 53 KB: three workgroups per CU
   double O[2][CV_KC][CV_BP + CV_OPAD];
-  double W[2][CV_KC][CV_BM + CV_OPAD];
+  double W[2][CV_KC][CV_BM];
 };
+
+// exp(y) for -745 < y <= 0 (the Gaussian weights): Cody-Waite reduction
+// y = n ln2 + t with ln2 split in two (the high part has enough trailing
+// zeros that n ln2_hi is exact), exp(t) from its Taylor series to t^13
+// (truncation below 5e-18 for |t| <= ln2 / 2), then scaling by 2^n.
+__device__ inline double cv_exp(double y) {
+  y = fmax(y, -740.0);
+  const double n = rint(y * 1.4426950408889634);
+  const double t = fma(-n, 1.9082149292705877e-10, fma(-n, 6.93147180369123816490e-01, y));
+  double q = 1.0 / 6227020800.0;  // 1/13!
+  q = fma(q, t, 1.0 / 479001600.0);
+  q = fma(q, t, 1.0 / 39916800.0);
+  q = fma(q, t, 1.0 / 3628800.0);
+  q = fma(q, t, 1.0 / 362880.0);
+  q = fma(q, t, 1.0 / 40320.0);
+  q = fma(q, t, 1.0 / 5040.0);
+  q = fma(q, t, 1.0 / 720.0);
+  q = fma(q, t, 1.0 / 120.0);
+  q = fma(q, t, 1.0 / 24.0);
+  q = fma(q, t, 1.0 / 6.0);
+  q = fma(q, t, 0.5);
+  q = fma(q, t, 1.0);
+  q = fma(q, t, 1.0);
+  return ldexp(q, (int)n);
+}
 
 __device__ inline int64_t pp_first_ge(const double *E, int64_t m, double x) {
   int64_t lo = 0, hi = m;
@@ -74,10 +104,10 @@ __device__ inline int64_t pp_first_gt(const double *E, int64_t m, double x) {
   return lo;
 }
 
-// Trapezoid weights dE, each output's window [lo, hi) and 1 / sum_j g_ij.
+// Trapezoid weights dE and each output's window [lo, hi).
 __global__ void conv_window_kernel(const double *__restrict__ E, int64_t m,
-                                   double s, double r, double *dE, int64_t *lo,
-                                   int64_t *hi, double *inv_norm) {
+                                   double s, double *dE, int64_t *lo,
+                                   int64_t *hi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   const double Ei = E[i];
@@ -85,27 +115,21 @@ __global__ void conv_window_kernel(const double *__restrict__ E, int64_t m,
   if (i > 0) w += 0.5 * (Ei - E[i - 1]);
   if (i + 1 < m) w += 0.5 * (E[i + 1] - Ei);
   dE[i] = w;
-  const int64_t a = pp_first_ge(E, m, Ei - CV_CUT * s);
-  const int64_t b = pp_first_gt(E, m, Ei + CV_CUT * s);
-  double sum = 0.0;
-  for (int64_t j = a; j < b; ++j) {
-    const double x = E[j] - Ei;
-    double wj = 0.0;
-    if (j > 0) wj += 0.5 * (E[j] - E[j - 1]);
-    if (j + 1 < m) wj += 0.5 * (E[j + 1] - E[j]);
-    sum += exp(-r * x * x) * wj;
-  }
-  lo[i] = a;
-  hi[i] = b;
-  inv_norm[i] = 1.0 / sum;
+  lo[i] = pp_first_ge(E, m, Ei - CV_CUT * s);
+  hi[i] = pp_first_gt(E, m, Ei + CV_CUT * s);
 }
 
-__global__ __launch_bounds__(256) void conv_apply_kernel(
-    const double *__restrict__ E, const double *__restrict__ dE, int64_t m,
-    const double *__restrict__ in, int64_t P, double r,
-    const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
-    const double *__restrict__ inv_norm, double *__restrict__ out,
-    int n_tiles) {
+// NB column blocks of 16 per workgroup (the column tiles split the
+// transitions evenly, the last one may be narrower), so the MFMA loop has no
+// branches.
+template <int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void conv_apply_kernel(const double *__restrict__ E,
+                       const double *__restrict__ dE, int64_t m,
+                       const double *__restrict__ in, int64_t P, int64_t pbase,
+                       double r, const int64_t *__restrict__ lo,
+                       const int64_t *__restrict__ hi,
+                       double *__restrict__ out, int n_tiles) {
   __shared__ CvSmem sm;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -117,8 +141,7 @@ __global__ __launch_bounds__(256) void conv_apply_kernel(
   if (tile >= n_tiles) return;
   const int64_t i0 = (int64_t)tile * CV_BM;
   const int64_t ilast = min<int64_t>(i0 + CV_BM, m) - 1;
-  const int64_t p0 = (int64_t)blockIdx.y * CV_BP;
-  const int nblk = (int)min<int64_t>(CV_NB, (P - p0 + 15) / 16);
+  const int64_t p0 = pbase + (int64_t)blockIdx.y * (16 * NB);
   const int64_t jlo = lo[i0], jhi = hi[ilast];
 
   // this wave's 16 outputs and the rows they reach
@@ -127,88 +150,128 @@ __global__ __launch_bounds__(256) void conv_apply_kernel(
   const int64_t wlo = wact ? lo[wi0] : 0;
   const int64_t whi = wact ? hi[min<int64_t>(wi0 + 15, ilast)] : 0;
 
-  // weight staging: output i0 + (tid % 64), stage rows tid / 64 + 4 u
-  const int si = tid & 63;
-  const int sk = tid >> 6;
-  const int64_t gi = i0 + si;
+  // weight staging: output i0 + lane, stage rows wave + 4 u (wave-uniform,
+  // so E and dE of a row come through the scalar cache)
+  const int64_t gi = i0 + lane;
   const bool iv = gi <= ilast;
-  const double Ei = iv ? E[gi] : 0.0;
-  const double ninv = iv ? inv_norm[gi] : 0.0;
+  const double Ei = E[min(gi, ilast)];
   const int64_t ilo = iv ? lo[gi] : 0, ihi = iv ? hi[gi] : 0;
-  // Omega staging: column p0 + tid, the 16 rows of a stage
-  const int64_t gp = p0 + tid;
-  const bool pv = gp < P;
+  double gsum = 0.0;  // this thread's share of sum_j g_ij
+  // Omega staging: column p0 + (tid % 128), rows tid / 128 + 2 k of a stage.
+  // Loads are clamped into the band and the array: a clamped value meets a
+  // zero weight or feeds a column that is never stored.
+  const int sc = tid & (CV_BP - 1);
+  const int sr = __builtin_amdgcn_readfirstlane(tid >> 7);  // wave-uniform
+  const int64_t col_off = min(p0 + sc, P - 1);
 
-  double rO[CV_KC], rW[4];
-  auto fetch = [&](int64_t j0) {
+  double rO[CV_KC / 2], rW[4];
+  // one quarter of a stage: Omega rows sr + 2 k for k = 2 h, 2 h + 1 and the
+  // weight of row wave + 4 h
+  auto fetch_part = [&](int64_t j0, int h) {
 #pragma unroll
-    for (int k = 0; k < CV_KC; ++k) {
-      const int64_t j = j0 + k;
-      rO[k] = (pv && j < jhi) ? in[j * P + gp] : 0.0;
+    for (int k = 2 * h; k < 2 * h + 2; ++k) {
+      // row base in scalar registers, column offset per lane
+      const double *row = in + min(j0 + sr + 2 * k, jhi - 1) * P;
+      rO[k] = row[col_off];
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t j = j0 + sk + 4 * u;
-      double w = 0.0;
-      if (j >= ilo && j < ihi) {
-        const double x = E[j] - Ei;
-        w = exp(-r * x * x) * dE[j] * ninv;
-      }
-      rW[u] = w;
-    }
+    const int64_t j = j0 + wave + 4 * h;
+    const int64_t jc = min(j, m - 1);
+    const double x = E[jc] - Ei;
+    const double w = cv_exp(-r * x * x) * dE[jc];
+    rW[h] = (j >= ilo && j < ihi) ? w : 0.0;
+    gsum += rW[h];
   };
   auto stage = [&](int b) {
 #pragma unroll
-    for (int k = 0; k < CV_KC; ++k) sm.O[b][k][tid] = rO[k];
+    for (int k = 0; k < CV_KC / 2; ++k) sm.O[b][sr + 2 * k][sc] = rO[k];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) sm.W[b][sk + 4 * u][si] = rW[u];
+    for (int u = 0; u < 4; ++u) sm.W[b][wave + 4 * u][lane] = rW[u];
   };
 
-  d4 acc[CV_NB];
+  d4 acc[NB];
 #pragma unroll
-  for (int b = 0; b < CV_NB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < NB; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
   const int kq = lane >> 4;
   const int col = lane & 15;
 
-  fetch(jlo);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) fetch_part(jlo, h);
   stage(0);
-  if (jlo + CV_KC < jhi) fetch(jlo + CV_KC);
+  if (jlo + CV_KC < jhi) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) fetch_part(jlo + CV_KC, h);
+  }
   __syncthreads();
   int buf = 0;
   for (int64_t j0 = jlo; j0 < jhi; j0 += CV_KC, buf ^= 1) {
+    // the next stage, fetched during the previous one, goes to the other
+    // buffer (free since the last barrier); the one after it is fetched in
+    // four parts between this stage's MFMA steps
+    const bool more = j0 + CV_KC < jhi;
+    const bool more2 = j0 + 2 * CV_KC < jhi;
+    if (more) stage(buf ^ 1);
     if (wact && j0 < whi && j0 + CV_KC > wlo) {
 #pragma unroll
-      for (int kk = 0; kk < CV_KC; kk += 4) {
+      for (int h = 0; h < 4; ++h) {
+        const int kk = 4 * h;
         const double a = sm.W[buf][kk + kq][16 * wave + col];
+        double bv[NB];
 #pragma unroll
-        for (int b = 0; b < CV_NB; ++b)
-          if (b < nblk) {
-            const double bv = sm.O[buf][kk + kq][16 * b + col];
-            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[b], 0, 0, 0);
-          }
+        for (int b = 0; b < NB; ++b) bv[b] = sm.O[buf][kk + kq][16 * b + col];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[b], acc[b], 0, 0, 0);
+        if (more2) fetch_part(j0 + 2 * CV_KC, h);
       }
-    }
-    if (j0 + CV_KC < jhi) {
-      stage(buf ^ 1);
-      if (j0 + 2 * CV_KC < jhi) fetch(j0 + 2 * CV_KC);
+    } else if (more2) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) fetch_part(j0 + 2 * CV_KC, h);
     }
     __syncthreads();
   }
+  // row sums: the four staging threads of each output add their shares
+  // (the weight buffers are free after the last barrier)
+  double(*s_sum)[CV_BM] = sm.W[0];
+  s_sum[wave][lane] = gsum;
+  __syncthreads();
 
   // FP64 16x16x4 result: lane holds row kq + 4 q, column col of its block
   if (wact) {
+    double inv[4];
 #pragma unroll
-    for (int b = 0; b < CV_NB; ++b) {
-      if (b >= nblk) continue;
+    for (int q = 0; q < 4; ++q) {
+      const int li = 16 * wave + kq + 4 * q;
+      inv[q] = 1.0 / (((s_sum[0][li] + s_sum[1][li]) + s_sum[2][li]) + s_sum[3][li]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
       const int64_t p = p0 + 16 * b + col;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t i = wi0 + kq + 4 * q;
-        if (i <= ilast && p < P) out[i * P + p] = acc[b][q];
+        if (i <= ilast && p < P) out[i * P + p] = acc[b][q] * inv[q];
       }
     }
   }
 }
+
+template <int NB>
+static void launch_conv_apply(dim3 grid, hipStream_t st, const double *E,
+                              const double *dE, int64_t M, const double *in,
+                              int64_t P, int64_t pbase, double r,
+                              const int64_t *lo, const int64_t *hi,
+                              double *out, int n_tiles) {
+  hipLaunchKernelGGL(conv_apply_kernel<NB>, grid, dim3(256), 0, st, E, dE, M,
+                     in, P, pbase, r, lo, hi, out, n_tiles);
+}
+
+typedef void (*ConvLaunch)(dim3, hipStream_t, const double *, const double *,
+                           int64_t, const double *, int64_t, int64_t, double,
+                           const int64_t *, const int64_t *, double *, int);
+static const ConvLaunch kConvLaunch[CV_NB + 1] = {
+    nullptr,              launch_conv_apply<1>, launch_conv_apply<2>,
+    launch_conv_apply<3>, launch_conv_apply<4>, launch_conv_apply<5>,
+    launch_conv_apply<6>, launch_conv_apply<7>, launch_conv_apply<8>};
 
 __global__ void copy_kernel(const double *__restrict__ in, int64_t n,
                             double *__restrict__ out) {
@@ -227,8 +290,9 @@ __global__ void ups_factor_kernel(const double *__restrict__ E, int64_t m,
   f[q] = i > 0 ? exp(-(E[i] - E[i - 1]) / kT[t]) : 0.0;
 }
 
-constexpr int UP_T = 8;     // temperatures per pass over Omega
-constexpr int UP_SEGS = 4;  // mesh segments per workgroup (one per wave)
+constexpr int UP_T = 8;    // temperatures per pass over Omega
+constexpr int UP_W = 8;    // mesh segments (waves) per workgroup
+constexpr int UP_R = 8;    // mesh rows per block; the next block is in flight
 
 __device__ inline int64_t wave_min64(int64_t v) {
 #pragma unroll
@@ -239,98 +303,164 @@ __device__ inline int64_t wave_min64(int64_t v) {
   return v;
 }
 
-// Partial sums over one mesh segment per wave, one transition per lane:
-// part [n_seg][P][nT].  exp(-eps/kT) starts exact at each lane's first row
-// and then follows the product of the per-interval factors.
-__global__ __launch_bounds__(256) void ups_part_kernel(
+__device__ inline int64_t uniform64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ inline double lane_value(double v, int l) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// One transition per lane and one mesh segment per wave; the 8 waves of a
+// workgroup add their segments in LDS and write one partial sum per pass:
+// part [gridDim.y][P][nT].  exp(-eps/kT) starts exact at each lane's first
+// row and then follows the product of the per-interval factors f, which a
+// block of 8 rows loads as one vector (lane 8 k + q: row k, temperature q)
+// and hands out with readlane.
+__global__ __launch_bounds__(512) void ups_part_kernel(
     const double *__restrict__ E, int64_t m, const double *__restrict__ om,
     int n_target, int64_t P, const double *__restrict__ e_level,
     const double *__restrict__ kT, int nT, const double *__restrict__ f,
-    int64_t seg_len, int64_t n_seg, double *__restrict__ part) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t seg = (int64_t)blockIdx.y * UP_SEGS + wave;
-  if (seg >= n_seg) return;  // whole wave; no barriers below
+    int64_t seg_len, double *__restrict__ part) {
+  __shared__ double red[UP_W][UP_T][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t seg = (int64_t)blockIdx.y * UP_W + wave;
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
   const bool pv = p < P;
+  const int64_t pc = pv ? p : P - 1;
   // level pair (t, u), t <= u, of packed index p
   int t = 0;
-  int64_t rem = pv ? p : 0;
+  int64_t rem = pc;
   while (rem >= n_target - t) {
     rem -= n_target - t;
     ++t;
   }
   const int u = t + (int)rem;
-  const double e = pv ? fmax(e_level[t], e_level[u]) : 0.0;
-  const int64_t i0 = pv ? pp_first_gt(E, m, e) : m;  // first point above e
-  const int64_t s_lo = seg * seg_len;
+  const double e = fmax(e_level[t], e_level[u]);
+  const int64_t i0 = pp_first_gt(E, m, e);  // first point above e
+  const int64_t s_lo = min(m, seg * seg_len);
   const int64_t s_hi = min(m, s_lo + seg_len);
   const int64_t first = pv ? max(i0, s_lo) : m;
-  int64_t istart = wave_min64(first);
-  istart = ((int64_t)__builtin_amdgcn_readfirstlane((int)(istart >> 32)) << 32) |
-           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)istart);
+  const int64_t istart = uniform64(wave_min64(first));
+  const int64_t mlast = m > 0 ? m - 1 : 0;
 
   for (int t0 = 0; t0 < nT; t0 += UP_T) {
     const int nt = min(UP_T, nT - t0);
     double T[UP_T], acc[UP_T], x[UP_T];
 #pragma unroll
     for (int q = 0; q < UP_T; ++q) {
-      T[q] = q < nt ? kT[t0 + q] : 1.0;
+      T[q] = kT[t0 + min(q, nt - 1)];
       acc[q] = 0.0;
       x[q] = 0.0;
     }
-    for (int64_t i = istart; i < s_hi; ++i) {
-      const bool act = i >= first;
-      const double v = act ? om[i * P + p] : 0.0;
-      const double Ec = E[i];
-      const double wr = i + 1 < m ? 0.5 * (E[i + 1] - Ec) : 0.0;
-      const double wl = (act && i > i0) ? 0.5 * (Ec - E[i - 1]) : 0.0;
-      if (act && i == first) {
+    // block loads, clamped into the arrays (masked when used)
+    const int fq = min(lane & 7, nt - 1);
+    auto load = [&](int64_t ib, double *v, double &fv) {
 #pragma unroll
-        for (int q = 0; q < UP_T; ++q) x[q] = exp(-(Ec - e) / T[q]);
-        if (i == i0) {  // constant Omega from threshold to E_i0
+      for (int k = 0; k < UP_R; ++k) v[k] = om[min(ib + k, mlast) * P + pc];
+      fv = f[min(ib + (lane >> 3), mlast) * nT + t0 + fq];
+    };
+    double va[UP_R], fa;
+    if (istart < s_hi) load(istart, va, fa);
+    for (int64_t ib = istart; ib < s_hi; ib += UP_R) {
+      double vn[UP_R], fn;
+      load(ib + UP_R, vn, fn);
 #pragma unroll
-          for (int q = 0; q < UP_T; ++q) acc[q] = v * (1.0 - x[q]);
+      for (int k = 0; k < UP_R; ++k) {
+        const int64_t i = ib + k;
+        const bool act = i >= first && i < s_hi;
+        const double v = act ? va[k] : 0.0;
+        const int64_t ic = min(i, mlast);
+        const double Ec = E[ic];
+        const double wr = i + 1 < m ? 0.5 * (E[min(i + 1, mlast)] - Ec) : 0.0;
+        const double wl = (act && i > i0) ? 0.5 * (Ec - E[ic - 1]) : 0.0;
+        if (act && i == first) {
+#pragma unroll
+          for (int q = 0; q < UP_T; ++q) x[q] = exp(-(Ec - e) / T[q]);
+          if (i == i0) {  // constant Omega from threshold to E_i0
+#pragma unroll
+            for (int q = 0; q < UP_T; ++q) acc[q] = v * (1.0 - x[q]);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < UP_T; ++q) x[q] *= lane_value(fa, 8 * k + q);
         }
-      } else {
+        const double vw = v * (wl + wr);
 #pragma unroll
-        for (int q = 0; q < UP_T; ++q)
-          if (q < nt) x[q] *= f[i * nT + t0 + q];
+        for (int q = 0; q < UP_T; ++q) acc[q] = fma(vw * x[q], 1.0 / T[q], acc[q]);
       }
-      const double vw = v * (wl + wr);
 #pragma unroll
-      for (int q = 0; q < UP_T; ++q) acc[q] = fma(vw * x[q], 1.0 / T[q], acc[q]);
+      for (int k = 0; k < UP_R; ++k) va[k] = vn[k];
+      fa = fn;
     }
-    if (pv) {
-      double *dst = part + (seg * P + p) * nT + t0;
-      for (int q = 0; q < nt; ++q) dst[q] = acc[q];
+#pragma unroll
+    for (int q = 0; q < UP_T; ++q) red[wave][q][lane] = acc[q];
+    __syncthreads();
+    if (tid < UP_T * 64) {
+      const int q = tid >> 6, l = tid & 63;
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < UP_W; ++w) s += red[w][q][l];
+      const int64_t pp = (int64_t)blockIdx.x * 64 + l;
+      if (pp < P && q < nt) part[((int64_t)blockIdx.y * P + pp) * nT + t0 + q] = s;
     }
+    __syncthreads();
   }
 }
 
 __global__ void ups_reduce_kernel(const double *__restrict__ part,
-                                  int64_t n_seg, int64_t n, double *ups) {
+                                  int64_t n_part, int64_t n, double *ups) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   double s = 0.0;
-  for (int64_t g = 0; g < n_seg; ++g) s += part[g * n + q];
+#pragma unroll 8
+  for (int64_t g = 0; g < n_part; ++g) s += part[g * n + q];
   ups[q] = s;
 }
 
-// out [m][Pg]: each group pair sums its list of level-pair columns
-// (cols[off[q] .. off[q + 1]) of row i); one workgroup per row.
-__global__ __launch_bounds__(256) void group_kernel(
-    const double *__restrict__ om, int64_t m, int64_t P,
+constexpr int GR_LDS = 4096;  // doubles of Omega rows staged per workgroup
+
+// out [m][Pg]: each group pair q sums its level-pair columns
+// cols[off[q] .. off[q + 1]).  A workgroup copies `rows` whole rows of Omega
+// into LDS with coalesced loads, then forms their outputs from LDS.
+__global__ __launch_bounds__(256) void group_lds_kernel(
+    const double *__restrict__ om, int64_t m, int64_t P, int rows,
     const int32_t *__restrict__ off, const int32_t *__restrict__ cols,
     int64_t Pg, double *__restrict__ out) {
-  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
-    const double *row = om + i * P;
-    for (int64_t q = threadIdx.x; q < Pg; q += blockDim.x) {
-      double s = 0.0;
-      for (int c = off[q]; c < off[q + 1]; ++c) s += row[cols[c]];
-      out[i * Pg + q] = s;
-    }
+  __shared__ double buf[GR_LDS];
+  const int64_t i0 = (int64_t)blockIdx.x * rows;
+  const int nr = (int)min<int64_t>(rows, m - i0);
+  const double *src = om + i0 * P;
+  for (int64_t k = threadIdx.x; k < nr * P; k += 256) buf[k] = src[k];
+  __syncthreads();
+  for (int64_t o = threadIdx.x; o < nr * Pg; o += 256) {
+    const int64_t r = o / Pg, q = o % Pg;
+    const double *row = buf + r * P;
+    double s = 0.0;
+    for (int c = off[q]; c < off[q + 1]; ++c) s += row[cols[c]];
+    out[i0 * Pg + o] = s;
   }
+}
+
+// the same from global memory, for rows too long for LDS
+__global__ void group_kernel(const double *__restrict__ om, int64_t m,
+                             int64_t P, const int32_t *__restrict__ off,
+                             const int32_t *__restrict__ cols, int64_t Pg,
+                             double *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * Pg) return;
+  const int64_t i = idx / Pg, q = idx % Pg;
+  const double *row = om + i * P;
+  double s = 0.0;
+  for (int c = off[q]; c < off[q + 1]; ++c) s += row[cols[c]];
+  out[idx] = s;
 }
 
 static int pp_hip(const char *what, hipError_t e) {
@@ -365,27 +495,36 @@ int rm_convolve_gaussian(const double *E, int64_t M, const double *omega_in,
     return e == hipSuccess ? RM_OK : pp_hip(fn, e);
   }
   const int64_t n_tiles = (M + CV_BM - 1) / CV_BM;
-  if (n_tiles > (int64_t)1 << 30 || (P + CV_BP - 1) / CV_BP > 65535)
+  if (n_tiles > (int64_t)1 << 30 || (P + 15) / 16 > 65535)
     return pp_fail(RM_ERR_ARG, std::string(fn) + ": M or P too large");
   const double s = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
   const double r = 0.5 / (s * s);
   char *ws = nullptr;
-  const size_t bytes = (size_t)M * (2 * sizeof(double) + 2 * sizeof(int64_t));
+  const size_t bytes = (size_t)M * (sizeof(double) + 2 * sizeof(int64_t));
   hipError_t e = hipMallocAsync((void **)&ws, bytes, st);
   if (e != hipSuccess) return pp_hip(fn, e);
   double *dE = (double *)ws;
-  double *inv = dE + M;
-  int64_t *lo = (int64_t *)(inv + M);
+  int64_t *lo = (int64_t *)(dE + M);
   int64_t *hi = lo + M;
   hipLaunchKernelGGL(conv_window_kernel, dim3((unsigned)((M + 255) / 256)),
-                     dim3(256), 0, st, E, M, s, r, dE, lo, hi, inv);
+                     dim3(256), 0, st, E, M, s, dE, lo, hi);
   e = hipGetLastError();
   if (e == hipSuccess) {
+    // column tiles of nb blocks of 16 (at most 8), as even as they come;
+    // the last one takes what is left
     const unsigned gx = (unsigned)(8 * ((n_tiles + 7) / 8));
-    const unsigned gy = (unsigned)((P + CV_BP - 1) / CV_BP);
-    hipLaunchKernelGGL(conv_apply_kernel, dim3(gx, gy), dim3(256), 0, st, E,
-                       dE, M, omega_in, P, r, lo, hi, inv, omega_out,
-                       (int)n_tiles);
+    const int64_t blocks = (P + 15) / 16;
+    const int64_t n_ct = (blocks + CV_NB - 1) / CV_NB;
+    const int nb = (int)((blocks + n_ct - 1) / n_ct);
+    const int64_t full = blocks / nb;
+    const int nb_last = (int)(blocks - full * nb);
+    ProfileScope prof(4, st);
+    if (full > 0)
+      kConvLaunch[nb](dim3(gx, (unsigned)full), st, E, dE, M, omega_in, P, 0,
+                      r, lo, hi, omega_out, (int)n_tiles);
+    if (nb_last > 0)
+      kConvLaunch[nb_last](dim3(gx, 1), st, E, dE, M, omega_in, P,
+                           full * nb * 16, r, lo, hi, omega_out, (int)n_tiles);
     e = hipGetLastError();
   }
   const hipError_t ef = hipFreeAsync(ws, st);
@@ -415,16 +554,17 @@ int rm_effective_collision_strengths(const double *E, int64_t M,
   hipStream_t st = (hipStream_t)stream;
   const int64_t P = (int64_t)n_target * (n_target + 1) / 2;
   const int64_t n_col = (P + 63) / 64;
-  // enough segments for several thousand waves, none shorter than 128 rows
-  int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>((8192 + n_col - 1) / n_col,
-                                                         (M + 127) / 128));
+  // about 4096 waves, no segment shorter than 64 rows
+  int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>((4096 + n_col - 1) / n_col,
+                                                         (M + 63) / 64));
   const int64_t seg_len = std::max<int64_t>(1, (M + n_seg - 1) / n_seg);
   n_seg = std::max<int64_t>(1, (M + seg_len - 1) / seg_len);
-  if (n_col > 0x7fffffff || (n_seg + UP_SEGS - 1) / UP_SEGS > 65535)
+  const int64_t n_part = (n_seg + UP_W - 1) / UP_W;
+  if (n_col > 0x7fffffff || n_part > 65535)
     return pp_fail(RM_ERR_ARG, std::string(fn) + ": M or n_target too large");
-  const size_t n_part = (size_t)n_seg * P * nT;
   const size_t bytes = sizeof(double) *
-      ((size_t)n_target + nT + std::max<size_t>(1, (size_t)M * nT) + n_part);
+      ((size_t)n_target + nT + std::max<size_t>(1, (size_t)M * nT) +
+       (size_t)n_part * P * nT);
   char *ws = nullptr;
   hipError_t e = hipMallocAsync((void **)&ws, bytes, st);
   if (e != hipSuccess) return pp_hip(fn, e);
@@ -442,16 +582,16 @@ int rm_effective_collision_strengths(const double *E, int64_t M,
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(ups_part_kernel,
-                       dim3((unsigned)n_col, (unsigned)((n_seg + UP_SEGS - 1) / UP_SEGS)),
-                       dim3(64 * UP_SEGS), 0, st, E, M, omega, n_target, P,
-                       d_lev, d_kT, nT, f, seg_len, n_seg, part);
+    ProfileScope prof(5, st);
+    hipLaunchKernelGGL(ups_part_kernel, dim3((unsigned)n_col, (unsigned)n_part),
+                       dim3(64 * UP_W), 0, st, E, M, omega, n_target, P,
+                       d_lev, d_kT, nT, f, seg_len, part);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
     const int64_t n = P * nT;
     hipLaunchKernelGGL(ups_reduce_kernel, dim3((unsigned)((n + 255) / 256)),
-                       dim3(256), 0, st, part, n_seg, n, upsilon);
+                       dim3(256), 0, st, part, n_part, n, upsilon);
     e = hipGetLastError();
   }
   // the host arrays must outlive their asynchronous copies
@@ -499,9 +639,17 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
   e = hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
-    const unsigned grid = (unsigned)std::min<int64_t>(M, 65536);
-    hipLaunchKernelGGL(group_kernel, dim3(grid), dim3(256), 0, st, omega, M, P,
-                       d_tab, d_tab + Pg + 1, Pg, out);
+    ProfileScope prof(6, st);
+    if (P <= GR_LDS) {
+      const int rows = (int)std::min<int64_t>(64, GR_LDS / P);
+      hipLaunchKernelGGL(group_lds_kernel, dim3((unsigned)((M + rows - 1) / rows)),
+                         dim3(256), 0, st, omega, M, P, rows, d_tab,
+                         d_tab + Pg + 1, Pg, out);
+    } else {
+      hipLaunchKernelGGL(group_kernel, dim3((unsigned)((M * Pg + 255) / 256)),
+                         dim3(256), 0, st, omega, M, P, d_tab, d_tab + Pg + 1,
+                         Pg, out);
+    }
     e = hipGetLastError();
   }
   // the host table must outlive its asynchronous copy

@@ -308,6 +308,23 @@ struct StageTimer {
   }
 };
 
+ProfileScope::ProfileScope(int stage, hipStream_t st) : st_(st) {
+  if (!g_prof) return;
+  StageRec r{stage, nullptr, nullptr};
+  if (hipEventCreate(&r.beg) != hipSuccess) return;
+  if (hipEventCreate(&r.end) != hipSuccess) {
+    (void)hipEventDestroy(r.beg);
+    return;
+  }
+  (void)hipEventRecord(r.beg, st);
+  end_ = r.end;
+  g_recs.push_back(r);
+}
+
+ProfileScope::~ProfileScope() {
+  if (end_) (void)hipEventRecord(end_, st_);
+}
+
 static void clear_recs() {
   for (auto &r : g_recs) {
     (void)hipEventDestroy(r.beg);
@@ -869,7 +886,7 @@ int rm_profile(int32_t enable) {
 }
 
 int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches) {
-  if (stage < 0 || stage > 3) return fail(RM_ERR_ARG, "stage %d", stage);
+  if (stage < 0 || stage > 6) return fail(RM_ERR_ARG, "stage %d", stage);
   double tot = 0.0;
   int64_t cnt = 0;
   for (auto &r : g_recs) {

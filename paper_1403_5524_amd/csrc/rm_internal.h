@@ -184,4 +184,13 @@ hipError_t launch_unsort_square(const Sym &s, const double *src,
                                 int64_t src_estride, int src_ld, double *dst,
                                 int64_t m, hipStream_t st);
 
+// rm_profile stage timing: while rm_profile(1) is in force, the launches a
+// scope issues on `st` are bracketed by events recorded under `stage`.
+struct ProfileScope {
+  ProfileScope(int stage, hipStream_t st);
+  ~ProfileScope();
+  hipEvent_t end_ = nullptr;
+  hipStream_t st_;
+};
+
 }  // namespace rmx

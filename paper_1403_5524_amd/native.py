@@ -244,7 +244,8 @@ def rm_channel_functions(sym, E):
     return out, st
 
 
-STAGES = {"chanfn": 0, "polesum": 1, "match": 2}
+STAGES = {"chanfn": 0, "polesum": 1, "match": 2, "graph": 3, "convolve": 4,
+          "upsilon": 5, "group": 6}
 
 
 def rm_profile(enable):
