@@ -316,18 +316,26 @@ __device__ inline double lane_value(double v, int l) {
   return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One transition per lane and one mesh segment per wave; the 8 waves of a
 // workgroup add their segments in LDS and write one partial sum per pass:
-// part [gridDim.y][P][nT].  exp(-eps/kT) starts exact at each lane's first
-// row and then follows the product of the per-interval factors f, which a
-// block of 8 rows loads as one vector (lane 8 k + q: row k, temperature q)
-// and hands out with readlane.
+// part [gridDim.y][P][nT].  y_q = exp(-eps/kT_q) / kT_q starts exact at each
+// lane's first row and then follows the product of the per-interval factors
+// f.  A block of 8 rows loads its factors (lane 8 k + q: row k, temperature
+// q) and mesh energies E[ib - 1 .. ib + 8] as one vector each, parks them in
+// the wave's LDS slot and reads them back as broadcasts.
 __global__ __launch_bounds__(512) void ups_part_kernel(
     const double *__restrict__ E, int64_t m, const double *__restrict__ om,
     int n_target, int64_t P, const double *__restrict__ e_level,
     const double *__restrict__ kT, int nT, const double *__restrict__ f,
     int64_t seg_len, double *__restrict__ part) {
   __shared__ double red[UP_W][UP_T][64];
+  __shared__ double blk[UP_W][UP_R * UP_T + 16];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -350,55 +358,65 @@ __global__ __launch_bounds__(512) void ups_part_kernel(
   const int64_t first = pv ? max(i0, s_lo) : m;
   const int64_t istart = uniform64(wave_min64(first));
   const int64_t mlast = m > 0 ? m - 1 : 0;
+  double *slot = blk[wave];
 
   for (int t0 = 0; t0 < nT; t0 += UP_T) {
     const int nt = min(UP_T, nT - t0);
-    double T[UP_T], acc[UP_T], x[UP_T];
+    double T[UP_T], iT[UP_T], acc[UP_T], y[UP_T];
 #pragma unroll
     for (int q = 0; q < UP_T; ++q) {
       T[q] = kT[t0 + min(q, nt - 1)];
+      iT[q] = 1.0 / T[q];
       acc[q] = 0.0;
-      x[q] = 0.0;
+      y[q] = 0.0;
     }
     // block loads, clamped into the arrays (masked when used)
     const int fq = min(lane & 7, nt - 1);
-    auto load = [&](int64_t ib, double *v, double &fv) {
+    auto load = [&](int64_t ib, double *v, double &fv, double &ev) {
 #pragma unroll
       for (int k = 0; k < UP_R; ++k) v[k] = om[min(ib + k, mlast) * P + pc];
       fv = f[min(ib + (lane >> 3), mlast) * nT + t0 + fq];
+      const int64_t ie = min(ib - 1 + lane, mlast);
+      ev = E[ie < 0 ? 0 : ie];
     };
-    double va[UP_R], fa;
-    if (istart < s_hi) load(istart, va, fa);
+    double va[UP_R], fa, ea;
+    if (istart < s_hi) load(istart, va, fa, ea);
     for (int64_t ib = istart; ib < s_hi; ib += UP_R) {
-      double vn[UP_R], fn;
-      load(ib + UP_R, vn, fn);
+      double vn[UP_R], fn, en;
+      load(ib + UP_R, vn, fn, en);
+      wave_lds_sync();  // the previous block's reads are done
+      slot[lane] = fa;
+      if (lane < UP_R + 2) slot[UP_R * UP_T + lane] = ea;
+      wave_lds_sync();
 #pragma unroll
       for (int k = 0; k < UP_R; ++k) {
         const int64_t i = ib + k;
         const bool act = i >= first && i < s_hi;
         const double v = act ? va[k] : 0.0;
-        const int64_t ic = min(i, mlast);
-        const double Ec = E[ic];
-        const double wr = i + 1 < m ? 0.5 * (E[min(i + 1, mlast)] - Ec) : 0.0;
-        const double wl = (act && i > i0) ? 0.5 * (Ec - E[ic - 1]) : 0.0;
+        const double Em = slot[UP_R * UP_T + k];
+        const double Ec = slot[UP_R * UP_T + k + 1];
+        const double Ep = slot[UP_R * UP_T + k + 2];
+        const double wr = i + 1 < m ? 0.5 * (Ep - Ec) : 0.0;
+        const double wl = (act && i > i0) ? 0.5 * (Ec - Em) : 0.0;
         if (act && i == first) {
 #pragma unroll
-          for (int q = 0; q < UP_T; ++q) x[q] = exp(-(Ec - e) / T[q]);
-          if (i == i0) {  // constant Omega from threshold to E_i0
-#pragma unroll
-            for (int q = 0; q < UP_T; ++q) acc[q] = v * (1.0 - x[q]);
+          for (int q = 0; q < UP_T; ++q) {
+            const double x = exp(-(Ec - e) * iT[q]);
+            y[q] = x * iT[q];
+            if (i == i0) acc[q] = v * (1.0 - x);  // Omega constant from threshold
           }
         } else {
 #pragma unroll
-          for (int q = 0; q < UP_T; ++q) x[q] *= lane_value(fa, 8 * k + q);
+          for (int q = 0; q < UP_T; ++q) y[q] *= slot[UP_T * k + q];
         }
         const double vw = v * (wl + wr);
 #pragma unroll
-        for (int q = 0; q < UP_T; ++q) acc[q] = fma(vw * x[q], 1.0 / T[q], acc[q]);
+        for (int q = 0; q < UP_T; ++q) acc[q] = fma(vw, y[q], acc[q]);
       }
 #pragma unroll
       for (int k = 0; k < UP_R; ++k) va[k] = vn[k];
       fa = fn;
+      ea = en;
     }
 #pragma unroll
     for (int q = 0; q < UP_T; ++q) red[wave][q][lane] = acc[q];
@@ -425,6 +443,23 @@ __global__ void ups_reduce_kernel(const double *__restrict__ part,
   ups[q] = s;
 }
 
+// s + base[cols[k0]] + ... + base[cols[k1 - 1]], added in that order; the
+// indices are fetched 8 at a time so their loads overlap.
+__device__ inline double gather_sum(const double *base,
+                                    const int32_t *__restrict__ cols, int k0,
+                                    int k1, double s) {
+  int k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    int c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = cols[k + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += base[c[u]];
+  }
+  for (; k < k1; ++k) s += base[cols[k]];
+  return s;
+}
+
 constexpr int GR_LDS = 4096;  // doubles of Omega rows staged per workgroup
 
 // out [m][Pg]: each group pair q sums its level-pair columns
@@ -444,8 +479,49 @@ __global__ __launch_bounds__(256) void group_lds_kernel(
     const int64_t r = o / Pg, q = o % Pg;
     const double *row = buf + r * P;
     double s = 0.0;
-    for (int c = off[q]; c < off[q + 1]; ++c) s += row[cols[c]];
+    s = gather_sum(row, cols, off[q], off[q + 1], s);
     out[i0 * Pg + o] = s;
+  }
+}
+
+constexpr int GR_ACC = 4096;  // group pairs accumulated in LDS
+
+// Rows longer than GR_LDS: one row at a time in chunks of GR_LDS columns;
+// chunk c's columns of group pair q are cols[off[c Pg + q] ..
+// off[c Pg + q + 1]) (offsets inside the chunk, ascending), added to an LDS
+// accumulator owned by one thread, so every sum runs in ascending column
+// order.
+__global__ __launch_bounds__(256) void group_chunks_kernel(
+    const double *__restrict__ om, int64_t m, int64_t P, int n_ch,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ cols,
+    int64_t Pg, double *__restrict__ out) {
+  __shared__ double buf[GR_LDS];
+  __shared__ double acc[GR_ACC];
+  const int tid = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    for (int64_t q = tid; q < Pg; q += 256) acc[q] = 0.0;
+    const double *row = om + i * P;
+    for (int c = 0; c < n_ch; ++c) {
+      const int64_t base = (int64_t)c * GR_LDS;
+      const int len = (int)min<int64_t>(GR_LDS, P - base);
+      __syncthreads();  // the previous chunk has been consumed
+      double v[GR_LDS / 256];
+#pragma unroll
+      for (int u = 0; u < GR_LDS / 256; ++u) {
+        const int k = tid + 256 * u;
+        v[u] = row[base + min(k, len - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < GR_LDS / 256; ++u) buf[tid + 256 * u] = v[u];
+      __syncthreads();
+      for (int64_t q = tid; q < Pg; q += 256) {
+        double s = acc[q];
+        const int64_t o = (int64_t)c * Pg + q;
+        s = gather_sum(buf, cols, off[o], off[o + 1], s);
+        acc[q] = s;
+      }
+    }
+    for (int64_t q = tid; q < Pg; q += 256) out[i * Pg + q] = acc[q];
   }
 }
 
@@ -459,7 +535,7 @@ __global__ void group_kernel(const double *__restrict__ om, int64_t m,
   const int64_t i = idx / Pg, q = idx % Pg;
   const double *row = om + i * P;
   double s = 0.0;
-  for (int c = off[q]; c < off[q + 1]; ++c) s += row[cols[c]];
+  s = gather_sum(row, cols, off[q], off[q + 1], s);
   out[idx] = s;
 }
 
@@ -617,20 +693,27 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
   const int64_t Pg = (int64_t)n_group * (n_group + 1) / 2;
   if (P > 0x7fffffff || Pg > 0x7fffffff)
     return pp_fail(RM_ERR_ARG, std::string(fn) + ": too many levels");
-  // column lists, grouped by target column
-  std::vector<int32_t> cnt(Pg + 1, 0), tgt(P);
+  // column lists per (chunk, group pair), columns ascending within each
+  // (one chunk holding every column when a row fits in LDS)
+  const bool chunked = P > GR_LDS && Pg <= GR_ACC;
+  const bool in_lds = P <= GR_LDS || chunked;
+  const int64_t n_ch = chunked ? (P + GR_LDS - 1) / GR_LDS : 1;
+  const int64_t n_key = n_ch * Pg;
+  std::vector<int32_t> cnt(n_key + 1, 0), key(P);
   for (int t = 0, p = 0; t < n_target; ++t)
     for (int u = t; u < n_target; ++u, ++p) {
       const int a = std::min(group[t], group[u]), b = std::max(group[t], group[u]);
-      tgt[p] = (int32_t)((int64_t)a * n_group - (int64_t)a * (a - 1) / 2 + (b - a));
-      ++cnt[tgt[p] + 1];
+      const int64_t q = (int64_t)a * n_group - (int64_t)a * (a - 1) / 2 + (b - a);
+      key[p] = (int32_t)((chunked ? p / GR_LDS : 0) * Pg + q);
+      ++cnt[key[p] + 1];
     }
-  std::vector<int32_t> tab(Pg + 1 + P);
-  for (int64_t q = 0; q < Pg; ++q) cnt[q + 1] += cnt[q];
+  std::vector<int32_t> tab(n_key + 1 + P);
+  for (int64_t q = 0; q < n_key; ++q) cnt[q + 1] += cnt[q];
   std::copy(cnt.begin(), cnt.end(), tab.begin());
   {
     std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int64_t p = 0; p < P; ++p) tab[Pg + 1 + pos[tgt[p]]++] = (int32_t)p;
+    for (int64_t p = 0; p < P; ++p)
+      tab[n_key + 1 + pos[key[p]]++] = (int32_t)(chunked ? p % GR_LDS : p);
   }
   hipStream_t st = (hipStream_t)stream;
   int32_t *d_tab = nullptr;
@@ -640,15 +723,19 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
                      hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     ProfileScope prof(6, st);
+    const int32_t *d_off = d_tab, *d_cols = d_tab + n_key + 1;
     if (P <= GR_LDS) {
       const int rows = (int)std::min<int64_t>(64, GR_LDS / P);
       hipLaunchKernelGGL(group_lds_kernel, dim3((unsigned)((M + rows - 1) / rows)),
-                         dim3(256), 0, st, omega, M, P, rows, d_tab,
-                         d_tab + Pg + 1, Pg, out);
+                         dim3(256), 0, st, omega, M, P, rows, d_off, d_cols,
+                         Pg, out);
+    } else if (in_lds) {
+      hipLaunchKernelGGL(group_chunks_kernel,
+                         dim3((unsigned)std::min<int64_t>(M, 4096)), dim3(256),
+                         0, st, omega, M, P, (int)n_ch, d_off, d_cols, Pg, out);
     } else {
       hipLaunchKernelGGL(group_kernel, dim3((unsigned)((M * Pg + 255) / 256)),
-                         dim3(256), 0, st, omega, M, P, d_tab, d_tab + Pg + 1,
-                         Pg, out);
+                         dim3(256), 0, st, omega, M, P, d_off, d_cols, Pg, out);
     }
     e = hipGetLastError();
   }

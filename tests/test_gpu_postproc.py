@@ -194,7 +194,11 @@ def test_upsilon_full_size(torch_dev, nat):
     assert err < TOL
 
 
-@pytest.mark.parametrize("m,n_t,n_g", [(513, 14, 5), (3, 1, 1), (70, 9, 9)])
+@pytest.mark.parametrize("m,n_t,n_g", [
+    (513, 14, 5), (3, 1, 1), (70, 9, 9),
+    (40, 100, 7),     # 5050 transitions: rows staged in column chunks
+    (9, 95, 92),      # more group pairs than the LDS accumulator holds
+])
 def test_group_sums_bit_exact(torch_dev, nat, m, n_t, n_g):
     torch, dev = torch_dev
     rng = np.random.default_rng(m + 31 * n_t)
