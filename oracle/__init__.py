@@ -25,6 +25,8 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
 * ``postproc.effective_collision_strengths``  Maxwellian averages Upsilon(kT)
 * ``postproc.group_collision_strengths``  Omega summed over the level pairs of
                                    level groups (statistical averaging)
+* ``photo.photoionization``       photoionization cross sections from the
+                                   same solve and bound-free dipole vectors
 
 It shares no code with the HIP path (``paper_1403_5524_amd``) and imports
 nothing from it; both sides receive the same seeded arrays from
@@ -37,6 +39,8 @@ from .rmatrix import (r_matrix, channel_data, k_matrix, k_matrix_elimination,
                       omega_pair_index, sweep)
 from .postproc import (gaussian_convolve, effective_collision_strengths,
                        trapezoid_weights, group_collision_strengths)
+from .photo import (dipole_pole_sum, matching_solution, dipole_strength,
+                    photoionization, SIGMA_CONST)
 
 __all__ = [
     "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
@@ -46,4 +50,6 @@ __all__ = [
     "omega_pair_index", "sweep",
     "gaussian_convolve", "effective_collision_strengths", "trapezoid_weights",
     "group_collision_strengths",
+    "dipole_pole_sum", "matching_solution", "dipole_strength",
+    "photoionization", "SIGMA_CONST",
 ]

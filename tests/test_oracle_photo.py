@@ -1,0 +1,187 @@
+"""Pins of the photoionization oracle against closed forms that share nothing
+with the R-matrix route.  CPU only."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_5524_amd import workloads as wl
+
+
+def _cd(E, e_thr, l, z, a):
+    cd = oracle.channel_data(np.array([E]), np.asarray(e_thr, float),
+                             np.asarray(l), z, a)
+    return {k: v[0] for k, v in cd.items()}
+
+
+def _sin_overlap(k1, k2, a):
+    """int_0^a sin(k1 r) sin(k2 r) dr."""
+    return 0.5 * (np.sin((k1 - k2) * a) / (k1 - k2)
+                  - np.sin((k1 + k2) * a) / (k1 + k2))
+
+
+@pytest.mark.parametrize("V0,E,m", [(1.0, 0.3, 0), (1.0, 0.3, 3),
+                                    (2.5, 1.7, 1), (0.4, 0.05, 6)])
+def test_square_well_dipole_strength(V0, E, m):
+    """One channel, l = 0, no Coulomb, depth V0 inside r < a.  The Bloch
+    basis (b = 0) is sqrt(2/a) sin(kappa_m r), kappa_m a = (m + 1/2) pi,
+    E_m = kappa_m^2 - V0, w_m = 2 (-1)^m / sqrt(a), and R = tan(kappa a) /
+    (kappa a).  With the dipole vector picking basis state m alone, the
+    strength must equal the squared overlap of that state with the
+    energy-normalised continuum A sin(kappa r), A^2 (sin^2 kappa a +
+    (kappa/k)^2 cos^2 kappa a) = 1/(pi k)."""
+    a = 6.0
+    kap = np.sqrt(E + V0)
+    k = np.sqrt(E)
+    R = np.array([[np.tan(kap * a) / (kap * a)]])
+    km = (m + 0.5) * np.pi / a
+    wm = 2.0 * (-1) ** m / np.sqrt(a)
+    g = oracle.dipole_pole_sum([km * km - V0], [[wm]], [1.0], E)
+    S = oracle.dipole_strength(R, g, a, _cd(E, [0.0], [0], 0.0, a))
+    A2 = 1.0 / (np.pi * k * (np.sin(kap * a) ** 2
+                              + (kap / k) ** 2 * np.cos(kap * a) ** 2))
+    M = np.sqrt(2.0 / a) * _sin_overlap(kap, km, a)
+    assert abs(S - A2 * M * M) <= 1e-12 * A2 * M * M
+
+
+@pytest.mark.parametrize("E,closed", [(0.35, True), (0.9, False)])
+def test_coupled_square_well_with_closed_channel(E, closed):
+    """Two channels, l = 0, no Coulomb, a constant symmetric coupling V
+    inside r < a and thresholds (0, e2) outside.  Direct route: the regular
+    inside solution U diag(sin kappa_al r) c is matched at r = a to
+    k^-1/2 (sin + cos K) in the open channel and to exp(-phi r) (closed) or
+    k^-1/2 (cos) terms (open) in the second one; the dipole function is one
+    basis state of eigenchannel al, whose overlap is analytic.  R-matrix
+    route: R = U diag(tan(kappa a)/(kappa a)) U^T, g from that basis
+    state's surface amplitudes."""
+    a = 5.0
+    V = np.array([[-1.2, 0.35], [0.35, -0.6]])
+    v, U = np.linalg.eigh(V)
+    e2 = 0.6 if closed else 0.2
+    kap = np.sqrt(E - v)
+    R = U @ np.diag(np.tan(kap * a) / (kap * a)) @ U.T
+    al, m = 1, 2
+    km = (m + 0.5) * np.pi / a
+    Em = v[al] + km * km
+    w = np.sqrt(2.0) * U[:, al] * np.sqrt(2.0 / a) * (-1) ** m
+    g = oracle.dipole_pole_sum([Em], w[:, None], [1.0], E)
+    S = oracle.dipole_strength(R, g, a, _cd(E, [0.0, e2], [0, 0], 0.0, a))
+
+    # direct: every solution regular at 0, real, with the open channels'
+    # outside part k^-1/2 sin(kr) delta_ij + k^-1/2 cos(kr) K_ij
+    thr = np.array([0.0, e2])
+    op = E > thr
+    P = np.nonzero(op)[0]
+    strength = 0.0
+    Kfull = np.zeros((P.size, P.size))
+    Ms = np.zeros(P.size)
+    for jj, j in enumerate(P):
+        # unknowns: c (2), K_{P, j} (|P|), closed amplitudes (2 - |P|)
+        nq = 2 + 2
+        Amat = np.zeros((nq, nq))
+        rhs = np.zeros(nq)
+        for i in range(2):
+            # value row 2 i, derivative row 2 i + 1
+            for b in range(2):
+                Amat[2 * i, b] = U[i, b] * np.sin(kap[b] * a)
+                Amat[2 * i + 1, b] = U[i, b] * kap[b] * np.cos(kap[b] * a)
+            col = 2 + i
+            if op[i]:
+                ki = np.sqrt(E - thr[i])
+                Amat[2 * i, col] = -np.cos(ki * a) / np.sqrt(ki)
+                Amat[2 * i + 1, col] = np.sin(ki * a) * np.sqrt(ki)
+                if i == j:
+                    rhs[2 * i] = np.sin(ki * a) / np.sqrt(ki)
+                    rhs[2 * i + 1] = np.cos(ki * a) * np.sqrt(ki)
+            else:
+                phi = np.sqrt(thr[i] - E)
+                Amat[2 * i, col] = -np.exp(-phi * a)
+                Amat[2 * i + 1, col] = phi * np.exp(-phi * a)
+        sol = np.linalg.solve(Amat, rhs)
+        c = sol[:2]
+        Kfull[:, jj] = sol[2 + P]
+        Ms[jj] = c[al] * np.sqrt(2.0 / a) * _sin_overlap(kap[al], km, a)
+    Ks = 0.5 * (Kfull + Kfull.T)
+    strength = Ms @ np.linalg.solve(np.eye(P.size) + Ks @ Ks, Ms) / np.pi
+    assert abs(S - strength) <= 1e-11 * abs(strength)
+
+
+def test_incoming_wave_sum_identity():
+    """Sum over final channels of |pi^-1/2 M (1 - iK)^-1|^2 (complex
+    incoming-wave solutions) equals the real form used by the oracle."""
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    rng = np.random.default_rng(2)
+    d = rng.normal(size=sym["E_pole"].size)
+    for E in (0.7, 1.3, 4.0):
+        R = oracle.r_matrix(sym["E_pole"], sym["w"], sym["a"], E)[0]
+        cd = _cd(E, sym["e_thr"], sym["l"], sym["z"], sym["a"])
+        g = oracle.dipole_pole_sum(sym["E_pole"], sym["w"], d, E)
+        S = oracle.dipole_strength(R, g, sym["a"], cd)
+        Z, P, d2 = oracle.matching_solution(R, sym["a"], cd)
+        a = sym["a"]
+        M = (a * cd["sp"][P] * g[P] + Z.T @ (d2 * g)) / a
+        K = 0.5 * (Z[P] + Z[P].T)
+        Mm = np.linalg.solve((np.eye(P.size) - 1j * K).T, M)
+        S2 = float(np.sum(np.abs(Mm) ** 2)) / np.pi
+        assert abs(S - S2) <= 1e-12 * abs(S)
+
+
+def test_decoupled_channels_add():
+    """Poles coupled to one channel each: the two-channel strength is the sum
+    of the one-channel strengths."""
+    rng = np.random.default_rng(5)
+    a, z = 8.0, 1.0
+    nA, nB = 40, 30
+    EA = np.sort(rng.uniform(-1, 20, nA))
+    EB = np.sort(rng.uniform(-1, 20, nB))
+    wA = rng.normal(0, 0.3, nA)
+    wB = rng.normal(0, 0.3, nB)
+    dA = rng.normal(size=nA)
+    dB = rng.normal(size=nB)
+    Ep = np.concatenate([EA, EB])
+    W = np.zeros((2, nA + nB))
+    W[0, :nA] = wA
+    W[1, nA:] = wB
+    d = np.concatenate([dA, dB])
+    e_thr, l = [0.0, 0.15], [0, 2]
+    for E in (0.5, 2.2):
+        R = oracle.r_matrix(Ep, W, a, E)[0]
+        S = oracle.dipole_strength(R, oracle.dipole_pole_sum(Ep, W, d, E), a,
+                                   _cd(E, e_thr, l, z, a))
+        parts = 0.0
+        for ch, (Ec, wc, dc) in enumerate(((EA, wA, dA), (EB, wB, dB))):
+            Rc = oracle.r_matrix(Ec, wc[None, :], a, E)[0]
+            gc = oracle.dipole_pole_sum(Ec, wc[None, :], dc, E)
+            parts += oracle.dipole_strength(Rc, gc, a,
+                                            _cd(E, [e_thr[ch]], [l[ch]], z, a))
+        assert abs(S - parts) <= 1e-11 * abs(parts)
+
+
+def test_channel_order_does_not_matter_and_closed_gives_zero():
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=sym["E_pole"].size)
+    perm = rng.permutation(sym["e_thr"].size)
+    sym2 = dict(sym, w=sym["w"][perm], e_thr=sym["e_thr"][perm],
+                l=sym["l"][perm])
+    E = np.array([0.9, 1.6, 5.0])
+    s1 = oracle.photoionization([sym], [d], E, -1.0)
+    s2 = oracle.photoionization([sym2], [d], E, -1.0)
+    assert np.allclose(s1, s2, rtol=1e-11, atol=0.0)
+    assert np.all(s1 > 0.0)
+    below = np.array([sym["e_thr"].min() * 0.5])
+    assert oracle.photoionization([sym], [d], below, -1.0)[0] == 0.0
+
+
+def test_cross_section_constant():
+    """4 pi^2 alpha a0^2 / 3 = 2.689 Mb: sigma = 2.689 Mb x (photon energy in
+    Ry) x (dipole strength in a0^2 per Ry)."""
+    assert abs(oracle.SIGMA_CONST - 2.6891) < 1e-4
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    d = np.random.default_rng(1).normal(size=sym["E_pole"].size)
+    E = np.array([2.5])
+    s = oracle.photoionization([sym], [d], E, -0.5)[0]
+    s2 = oracle.photoionization([sym], [d], E, -1.5)[0]
+    assert abs(s2 / s - 4.0 / 3.0) < 1e-12   # proportional to E - e0
