@@ -263,6 +263,42 @@ int rm_mesh_from_density(const float *dens, int32_t nw, double lo, double hi,
                          double floor_frac, int64_t M, double *E_out,
                          void *stream);
 
+/* ---- Photoionization ---------------------------------------------------
+ * The photoionization runs of the paper (Sec. 2-3: one dipole per pair of
+ * dipole-allowed symmetries, the outer-region module for photoionization;
+ * Sec. 4-5: the N, O, Kr+, Xe+ and W3+ cross sections) reuse the
+ * scattering solve at every energy with the bound-free dipole matrix
+ * elements d_k = <psi_k | D | Psi_0> between each inner-region state k of a
+ * final symmetry and the initial state (angular factors included).  Read
+ * without radiation damping:
+ *   g_i(E)  = (1/sqrt2) sum_k w_ik d_k / (E_k - E)   (a pole sum as Eq. 1)
+ *   M_j     = sum_i u_ij'(a) g_i over every channel i, u_ij'(a) the radial
+ *             derivative at r = a of channel i of the K-matrix solution j
+ *             (s_i' delta_ij + c_i' K_ij open, e_i' X_ij closed)
+ *   S(E)    = (1/pi) M (1 + K^2)^-1 M^T           (energy-normalised,
+ *             summed over the final channels)
+ *   sigma(E)= (4 pi^2 alpha a0^2 / 3) (E - e0) S(E)  in Mb, E and e0 in Ry,
+ * summed over the symmetries passed.
+ *
+ * rm_load_dipoles: attach d (host [n_poles], finite, input pole order) to a
+ * loaded symmetry (copied to its device; replaces an earlier vector after
+ * synchronising `stream`).  Errors: RM_ERR_ARG, RM_ERR_STATE, RM_ERR_NOMEM,
+ * RM_ERR_HIP. */
+int rm_load_dipoles(rm_sym_t sym, const double *d, void *stream);
+
+/* rm_photoionization: sigma (device [M], overwritten) at the M energies E
+ * (device, total energy of the final state on the thresholds' scale) for
+ * the final symmetries `syms` (each with dipoles loaded) and the initial
+ * state energy e0 (photon energy E - e0).  opts as for rm_sweep_energies
+ * (the R-matrix pole sum may run mixed; the dipole pole sum is FP64).
+ * status (device [M] or NULL): RM_E_* bits, RM_E_NO_OPEN below every
+ * threshold (sigma 0 there).  Errors: RM_ERR_ARG (M < 0, e0 not finite,
+ * null pointer, a symmetry without dipoles, bad opts), RM_ERR_STATE,
+ * RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_photoionization(const rm_sym_t *syms, int32_t n_sym, const double *E,
+                       int64_t M, double e0, const rm_opts *opts,
+                       double *sigma, int32_t *status, void *stream);
+
 /* ---- Post-processing of Omega(E) on the mesh ------------------------
  * Omega arrays are energy-major [M][P] FP64 device arrays, P the number of
  * packed level pairs (t <= u, row-major over t) as rm_sweep_energies writes

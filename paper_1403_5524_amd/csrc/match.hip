@@ -819,12 +819,46 @@ __device__ void wave_rows_times_tit(double *A, int ld, int r0, int r1, int j0,
 // lk) in; Y in columns [no, 2 no) of Aug (leading dimension ld) and the
 // lower triangle of Q in K's place out; Aug's columns [0, no) hold L.  Returns nonzero if 1 + K^2 was
 // not positive definite in floating point.
+// Photoionization: one block step of the forward substitution y = L^-1 v
+// of the dipole amplitudes v (no entries, global memory), with Ti = L11^-1
+// of the block in W: y_b = Ti v_b, then v[r] -= L[r][b] y_b below it.  y_b
+// is broadcast through the first row of W.T, free once Ti is formed.
+__device__ void wave_photo_forward(const double *Aug, int ld, int j0, int jb,
+                                   int no, WaveLds &W, double *v) {
+  const int lane = lane_id();
+  const double vb = lane < jb ? v[j0 + lane] : 0.0;
+  double y = 0.0;
+#pragma unroll
+  for (int k = 0; k < NB2; ++k)
+    y = fma(W.Ti[lane & (NB2 - 1)][k], read_lane(vb, k), y);
+  y = lane < jb ? y : 0.0;
+  if (lane < NB2) W.T[0][lane] = y;
+  if (lane < jb) v[j0 + lane] = y;
+  wave_sync();
+  for (int r = j0 + jb + lane; r < no; r += WT) {
+    const double *Lr = Aug + (int64_t)r * ld + j0;
+    double acc = v[r];
+#pragma unroll
+    for (int k0 = 0; k0 < NB2; k0 += 8) {
+      double lv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) lv[k] = k0 + k < jb ? Lr[k0 + k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc = fma(-lv[k], W.T[0][k0 + k], acc);
+    }
+    v[r] = acc;
+  }
+  wave_sync();
+}
+
+// want_t: form Y and Q (collision strengths); pv: dipole amplitudes to be
+// replaced by L^-1 pv (photoionization), or null.
 __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
-                          WaveLds &W) {
+                          WaveLds &W, bool want_t, double *pv) {
   int flag = 0;
   // lower triangle of 1 + K^2, and K as the right-hand side
   wave_gemm<1, G_LOWER>(Aug, ld, Kb, lk, Kb, lk, no, no, no);
-  wave_copy(Aug + no, ld, Kb, lk, no, no);
+  if (want_t) wave_copy(Aug + no, ld, Kb, lk, no, no);
   wave_sync();
   // right-looking blocked Cholesky with the forward substitution Z = L^-1 K
   for (int j0 = 0; j0 < no; j0 += NB2) {
@@ -833,16 +867,20 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
     wave_tile_invert<NB2>(W, TILE_LOWER);
     const int r0 = j0 + jb;
     if (r0 < no) wave_rows_times_tit(Aug, ld, r0, no, j0, jb, W);
-    wave_tile_apply<NB2>(Aug, ld, j0, jb, no, 2 * no, W, false);
+    if (pv) wave_photo_forward(Aug, ld, j0, jb, no, W, pv);
+    if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, 2 * no, W, false);
     if (r0 < no) {
       wave_gemm<0, G_TB | G_LOWER>(Aug + (int64_t)r0 * ld + r0, ld,
                                     Aug + (int64_t)r0 * ld + j0, ld,
                                     Aug + (int64_t)r0 * ld + j0, ld, no - r0,
                                     no - r0, jb);
-      wave_gemm<0>(Aug + (int64_t)r0 * ld + no, ld, Aug + (int64_t)r0 * ld + j0,
-                   ld, Aug + (int64_t)j0 * ld + no, ld, no - r0, no, jb);
+      if (want_t)
+        wave_gemm<0>(Aug + (int64_t)r0 * ld + no, ld,
+                     Aug + (int64_t)r0 * ld + j0, ld,
+                     Aug + (int64_t)j0 * ld + no, ld, no - r0, no, jb);
     }
   }
+  if (!want_t) return flag;
   // Q = Z^T Z in K's place: symmetric, so only its lower triangle
   wave_gemm<2, G_TA | G_LOWER>(Kb, lk, Aug + no, ld, Aug + no, ld, no, no, no);
   // Y = L^-T Z, blocks from the bottom
@@ -1109,6 +1147,29 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
         if (q < nk) Kb[(int64_t)(q / no) * n + q % no] = 0.5 * (a[u] + b[u]);
       }
     }
+    if (L.sigma) {
+      // dipole amplitudes of the K-matrix solutions: with u_ij'(a) =
+      // (a s'_j delta_ij + d2_i Z_ij) / a over every channel i (Z = [K; X]),
+      // v_j = sum_i u_ij'(a) g_i
+      const double *g = Aug + (int64_t)3 * n * n;
+      double *v = Aug + (int64_t)3 * n * n + n;
+      for (int j0 = 0; j0 < no; j0 += WT) {
+        const int j = j0 + lane;
+        double acc = 0.0;
+        for (int i0 = 0; i0 < n; i0 += UNR) {
+          double z[UNR], h[UNR];
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            const int i = i0 + u;
+            z[u] = (i < n && j < no) ? Aug[(int64_t)i * ld + n + j] : 0.0;
+            h[u] = i < n ? ch[i].d2 * g[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) acc = fma(h[u], z[u], acc);
+        }
+        if (j < no) v[j] = (ch[j].asp * g[j] + acc) / S.a;
+      }
+    }
   }
   // rank of each open channel among the open channels' input indices
   if (L.K_out || k_given) {
@@ -1169,10 +1230,24 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
   }
   if (L.do_t) {
     // Y in Aug's columns [no, 2 no), Q in K's place
-    if (wave_tstep(Aug, ld, Kb, n, no, W)) bits |= RM_E_SINGULAR;
+    double *pv = (L.sigma && !k_given) ? Aug + (int64_t)3 * n * n + n : nullptr;
+    wave_sync();
+    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv))
+      bits |= RM_E_SINGULAR;
     if (L.omega)
       nonfinite |= wave_omega(S, L.n_target_out, Aug + no, ld, Kb, n, Aug, ld,
                               no, L.omega + (int64_t)e * L.omega_stride);
+    if (pv) {
+      // sigma += (4 pi^2 alpha a0^2 / 3) omega (1/pi) |L^-1 v|^2
+      double s2 = 0.0;
+      for (int j = lane; j < no; j += WT) s2 = fma(pv[j], pv[j], s2);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) s2 += __shfl_xor(s2, o);
+      const double c = 4.0 * M_PI * 7.2973525693e-3 * 28.00285205 / 3.0;
+      const double add = c * (Ee - L.e0) * s2;
+      if (!isfinite(add)) nonfinite = 1;
+      if (lane == 0) L.sigma[e] += add;
+    }
   }
   if (nonfinite) bits |= RM_E_NONFINITE;
   wave_sync();

@@ -342,7 +342,8 @@ static int free_sym(Sym *s);
 // the whole sweep is a fixed sequence of launches: per chunk one grouped
 // pole-sum launch per tile variant and one persistent matching launch.
 
-static int64_t work_doubles(int n) { return (int64_t)3 * n * n; }
+// [Aug n x 2n | K n x n | g n | v n]: g and v serve photoionization
+static int64_t work_doubles(int n) { return (int64_t)3 * n * n + 2 * n; }
 
 struct Plan {
   int device = -1;
@@ -379,6 +380,10 @@ struct Plan {
   const double *E = nullptr;
   double *omega = nullptr;
   int32_t *status = nullptr;
+  // photoionization: sigma [M] (accumulated over the symmetries), e0
+  double *sigma = nullptr;
+  double e0 = 0.0;
+  std::vector<int64_t> h_work_off;  // host copy of the workspace offsets
   // rm_kmatrix-style extras (single symmetry)
   double *K_out = nullptr;
   int32_t *n_open_out = nullptr;
@@ -722,6 +727,7 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   }
   p.work_estride = wacc;
   p.chan_estride = cacc;
+  p.h_work_off = woff;
   int64_t C = o.chunk > 0 ? o.chunk
                           : (int64_t)(ws_budget / (8.0 * wacc + 32.0 * cacc + 64.0));
   C = std::max<int64_t>(1, std::min<int64_t>(C, 4096));
@@ -785,6 +791,7 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
   const int64_t P = (int64_t)p.n_target * (p.n_target + 1) / 2;
   if (p.omega) RM_HIP(launch_fill(p.omega, p.M * P, 0.0, st));
   if (p.status) RM_HIP(launch_fill_i32(p.status, p.M, 0, st));
+  if (p.sigma) RM_HIP(launch_fill(p.sigma, p.M, 0.0, st));
   RM_HIP(launch_fill_i32(p.counters, std::max(1, p.n_chunks), 0, st));
   for (int c = 0; c < p.n_chunks; ++c) {
     const int64_t c0 = (int64_t)c * p.C;
@@ -804,6 +811,16 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
         L.prec = p.o.prec;
         L.delta = p.o.near_delta;
         RM_HIP(launch_polesum(L, set.variant, st));
+      }
+      if (p.sigma) {
+        // dipole pole sums after each symmetry's K block
+        for (size_t q = 0; q < p.syms.size(); ++q) {
+          const Sym &s = *p.syms[q];
+          RM_HIP(launch_dip_polesum(s.dev(), p.E + c0, (int)m, p.work,
+                                    p.work_estride,
+                                    p.h_work_off[q] + (int64_t)3 * s.n * s.n,
+                                    st));
+        }
       }
     }
     if (p.R_out) {
@@ -830,6 +847,8 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.n_target_out = p.n_target;
     L.status = p.status ? p.status + c0 : nullptr;
     L.do_t = p.do_t;
+    L.sigma = p.sigma ? p.sigma + c0 : nullptr;
+    L.e0 = p.e0;
     L.counter = p.counters + c;
     L.grid = p.match_grid;
     StageTimer tm(2, st);
@@ -862,7 +881,7 @@ static int free_sym(Sym *s) {
   pd_release(*s);
   void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
                   s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT,
-                  s->pair_ij, s->Ph, s->Pl, s->P32, s->P64};
+                  s->pair_ij, s->Ph, s->Pl, s->P32, s->P64, s->dip};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete[] s->h_e_thr;
@@ -1089,6 +1108,59 @@ int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
     p.E = E;
     p.omega = omega;
     p.status = status;
+    rc = plan_enqueue(p, st);
+  }
+  plan_free_device(p);
+  return rc;
+}
+
+int rm_load_dipoles(rm_sym_t sym, const double *d, void *stream) {
+  if (!sym || !d) return fail(RM_ERR_ARG, "null handle or dipoles");
+  int rc = check_device(sym);
+  if (rc) return rc;
+  std::vector<double> h((size_t)sym->nh_pad, 0.0);
+  for (int k = 0; k < sym->nh; ++k) {
+    if (!std::isfinite(d[k])) return fail(RM_ERR_ARG, "dipole %d not finite", k);
+    h[k] = d[k];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  // kernels already queued may still read the old vector
+  RM_HIP(hipStreamSynchronize(st));
+  if (!sym->dip) RM_HIP(hipMalloc((void **)&sym->dip, h.size() * sizeof(double)));
+  RM_HIP(hipMemcpy(sym->dip, h.data(), h.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+  return RM_OK;
+}
+
+int rm_photoionization(const rm_sym_t *syms, int32_t n_sym, const double *E,
+                       int64_t M, double e0, const rm_opts *opts,
+                       double *sigma, int32_t *status, void *stream) {
+  if (M < 0) return fail(RM_ERR_ARG, "M < 0");
+  if (!std::isfinite(e0)) return fail(RM_ERR_ARG, "e0 not finite");
+  rm_opts o;
+  int rc = check_opts(opts, &o);
+  if (rc) return rc;
+  if (!syms || n_sym < 1) return fail(RM_ERR_ARG, "no symmetries");
+  int n_tgt = 1;
+  for (int q = 0; q < n_sym; ++q) {
+    if (!syms[q]) return fail(RM_ERR_ARG, "null handle %d", q);
+    if (!syms[q]->dip)
+      return fail(RM_ERR_ARG, "symmetry %d has no dipoles (rm_load_dipoles)", q);
+    n_tgt = std::max(n_tgt, syms[q]->n_target);
+  }
+  if (M > 0 && (!E || !sigma)) return fail(RM_ERR_ARG, "null E or sigma");
+  if ((rc = validate_syms(syms, n_sym, n_tgt))) return rc;
+  if (M == 0) return RM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Plan p;
+  rc = plan_build(p, syms, n_sym, n_tgt, E, M, o, st, true,
+                  workspace_budget(16.0e9));
+  if (!rc) {
+    p.E = E;
+    p.sigma = sigma;
+    p.e0 = e0;
+    p.status = status;
+    p.do_t = 1;
     rc = plan_enqueue(p, st);
   }
   plan_free_device(p);

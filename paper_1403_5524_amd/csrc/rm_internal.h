@@ -39,6 +39,7 @@ struct SymDev {
   const uint16_t *Ph, *Pl;    // [np_pad][nh_pad] BF16 hi/lo of w_ik w_jk
   const float *P32;           // [np_pad][nh_pad] FP32 w_ik w_jk
   const double *P64;          // [np_pad][nh_pad] FP64 w_ik w_jk
+  const double *dip;          // [nh_pad] bound-free dipoles, or null
 };
 
 // A symmetry resident on one device.  Channels are stored sorted by
@@ -67,6 +68,7 @@ struct Sym {
   uint16_t *Ph, *Pl;    // pair products, formed on first use (owned)
   float *P32;
   double *P64;
+  double *dip = nullptr;  // [nh_pad] dipoles with the initial state (owned)
   // host copies
   double *h_e_thr;      // [n] sorted
   int32_t *h_perm;
@@ -78,7 +80,7 @@ struct Sym {
     d.e_thr = e_thr; d.l = l; d.perm = perm; d.tgt = tgt;
     d.ntu = ntu; d.ut = ut; d.G = G; d.GT = GT;
     d.np = np; d.np_pad = np_pad; d.pair_ij = pair_ij;
-    d.Ph = Ph; d.Pl = Pl; d.P32 = P32; d.P64 = P64;
+    d.Ph = Ph; d.Pl = Pl; d.P32 = P32; d.P64 = P64; d.dip = dip;
     return d;
   }
 };
@@ -157,6 +159,11 @@ struct MatchLaunch {
   int n_sym;
   const double *E;
   int m;
+  // photoionization: the dipole pole sum g of each symmetry sits after its
+  // K block in the workspace ([Aug 2n^2 | K n^2 | g n | v n]); sigma[e] is
+  // accumulated over the symmetries (nullable)
+  double *sigma;
+  double e0;
   double *work;               // [M | B] (n x 2n) then K (n x n) per symmetry
   int64_t work_estride;
   const int64_t *work_off;    // device [n_sym]
@@ -175,6 +182,13 @@ struct MatchLaunch {
   int grid;
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
+
+// Dipole pole sum g_i(E) = (1/sqrt2) sum_k w_ik d_k / (E_k - E) of one
+// symmetry (sorted channel order) at the m energies E, written to
+// out + e*estride + off + i.
+hipError_t launch_dip_polesum(const SymDev &S, const double *E, int m,
+                              double *out, int64_t estride, int64_t off,
+                              hipStream_t st);
 
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v,

@@ -32,7 +32,8 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_mlp_get_params", "rm_mlp_set_params", "rm_mlp_forward",
             "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
             "rm_plan_create", "rm_plan_execute", "rm_plan_info",
-            "rm_plan_free", "rm_convolve_gaussian",
+            "rm_plan_free", "rm_load_dipoles", "rm_photoionization",
+            "rm_convolve_gaussian",
             "rm_effective_collision_strengths",
             "rm_group_collision_strengths", "rm_last_error")
 
@@ -99,6 +100,9 @@ def lib():
         L.rm_plan_execute.argtypes = [vp, vp]
         L.rm_plan_info.argtypes = [vp, vp, vp, vp, i32]
         L.rm_plan_free.argtypes = [vp]
+        L.rm_load_dipoles.argtypes = [vp, vp, vp]
+        L.rm_photoionization.argtypes = [vp, i32, vp, i64, f64,
+                                         ctypes.POINTER(Opts), vp, vp, vp]
         L.rm_convolve_gaussian.argtypes = [vp, i64, vp, i64, f64, vp, vp]
         L.rm_effective_collision_strengths.argtypes = [vp, i64, vp, i32, vp,
                                                        vp, i32, vp, vp]
@@ -410,3 +414,27 @@ def rm_group_collision_strengths(omega, n_target, group, n_group):
         _ptr(omega), int(omega.shape[0]), int(n_target), g.ctypes.data,
         int(n_group), _ptr(out), _stream()))
     return out
+
+
+def rm_load_dipoles(sym, d):
+    """Attach the dipole vector d [n_poles] (host) to a loaded symmetry."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    if d.size != sym.n_poles:
+        raise RmError(RM_ERR_ARG, "d must hold n_poles values")
+    _check(lib().rm_load_dipoles(sym.handle, d.ctypes.data, _stream()))
+
+
+def rm_photoionization(syms, E, e0, opts=None, sigma=None, status=None):
+    """sigma [M] in Mb (CUDA float64) and status [M] at the energies E."""
+    import torch
+    M = int(E.numel())
+    if sigma is None:
+        sigma = torch.empty((M,), dtype=torch.float64, device=E.device)
+    if status is None:
+        status = torch.empty((M,), dtype=torch.int32, device=E.device)
+    arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
+    o = opts if opts is not None else make_opts()
+    _check(lib().rm_photoionization(arr, len(syms), _ptr(E), M, float(e0),
+                                    ctypes.byref(o), _ptr(sigma),
+                                    _ptr(status), _stream()))
+    return sigma, status

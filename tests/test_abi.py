@@ -144,3 +144,22 @@ def test_postproc_rejects_invalid(L):
         native.RM_ERR_ARG
     assert grp(None, 5, 2, g.ctypes.data, 2, None, None) == native.RM_ERR_ARG
     assert grp(None, 0, 2, g.ctypes.data, 2, None, None) == native.RM_OK
+
+
+def test_photo_rejects_invalid(L):
+    o = native.make_opts()
+    f64 = ctypes.c_double
+    dummy = ctypes.c_void_p(64)
+    assert L.rm_photoionization(None, 0, dummy, 4, f64(-1.0), ctypes.byref(o),
+                                dummy, None, None) == native.RM_ERR_ARG
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.rm_photoionization(arr, 1, dummy, 4, f64(-1.0), ctypes.byref(o),
+                                dummy, None, None) == native.RM_ERR_ARG
+    assert L.rm_photoionization(arr, 1, dummy, -1, f64(-1.0),
+                                ctypes.byref(o), dummy, None,
+                                None) == native.RM_ERR_ARG
+    assert L.rm_photoionization(arr, 1, dummy, 4, f64(float("nan")),
+                                ctypes.byref(o), dummy, None,
+                                None) == native.RM_ERR_ARG
+    assert b"e0" in L.rm_last_error()
+    assert L.rm_load_dipoles(None, dummy, None) == native.RM_ERR_ARG
