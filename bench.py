@@ -10,11 +10,13 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
                     [--also bf16x3,fp32] [--graph] [--workload c2|c3|c4]
-                    [--no-postproc]
+                    [--no-postproc] [--photo-M N]
 
 After the headline sweep, the sweep's FP64 Omega is smoothed, averaged into
 effective collision strengths and summed over level groups; those kernels'
-times and rooflines are reported under "postproc".
+times and rooflines are reported under "postproc".  A photoionization leg
+times rm_photoionization on the B II shape of the paper's Table 1 (400
+channels, every 50th energy of 409,600) under "photoionization".
 """
 import argparse
 import json
@@ -151,6 +153,51 @@ def postproc_leg(native, torch, E, omega, mesh, e_level, n_t, steps):
     return res
 
 
+def photo_leg(native, torch, oracle, workloads, steps, warmup, count):
+    """Photoionization on the B II shape of the paper's Table 1 (400
+    channels, 409,600 energies): `count` energies spread evenly over the
+    mesh, timed like the headline; sigma checked against the oracle on 4 of
+    them."""
+    w, d, e0 = workloads.photo_b2()
+    stride = max(1, w.mesh.size // count)
+    Em = w.mesh[::stride][:count]
+    h = native.load_symmetry(w.syms[0])
+    native.rm_load_dipoles(h, d)
+    E = torch.as_tensor(Em, dtype=torch.float64, device="cuda:0")
+    sig = torch.empty_like(E)
+    st = torch.empty(E.shape, dtype=torch.int32, device=E.device)
+    for _ in range(warmup):
+        native.rm_photoionization([h], E, e0, sigma=sig, status=st)
+    torch.cuda.synchronize()
+    native.rm_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        native.rm_photoionization([h], E, e0, sigma=sig, status=st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stage = {k: native.rm_profile_query(k)[0] / steps
+             for k in ("polesum", "match")}
+    native.rm_profile(False)
+    idx = workloads.sample_indices(Em.size, 4, seed=3)
+    ref = oracle.photoionization([w.syms[0].as_dict()], [d], Em[idx], e0)
+    got = sig.cpu().numpy()[idx]
+    err = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+    h.free()
+    note("photoionization %s: %.1f ms for %d energies, err %.2e"
+         % (w.name, ms, Em.size, err))
+    return {"workload": w.name, "energies_timed": int(Em.size),
+            "sample": "every %d-th energy of the %d-point mesh"
+                      % (stride, w.mesh.size),
+            "value": Em.size / (ms * 1e-3), "unit": "energies/s",
+            "ms_per_step": ms, "stage_ms_per_step": stage,
+            "max_rel_err_sigma": err, "err_sample": int(idx.size),
+            # the paper's Table 1: 409,600 energies in 149.70 s on 8192 Cray
+            # XE6 cores (its module also damps resonances and reads files)
+            "paper_context": {"energies_per_s": 409600 / 149.70,
+                              "hardware": "8192 Cray XE6 cores",
+                              "ratio": Em.size / (ms * 1e-3) / (409600 / 149.70)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +218,9 @@ def main():
                     help="also time replays of a hipGraph-captured plan")
     ap.add_argument("--no-postproc", action="store_true",
                     help="skip timing the post-processing of Omega")
+    ap.add_argument("--photo-M", type=int, default=8192,
+                    help="energies of the photoionization leg (B II shape); "
+                         "0 skips it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -291,6 +341,10 @@ def main():
             "max_rel_err_omega": r["err"], "status_flagged": r["flagged"],
             "speedup_over_%s" % args.prec: head["ms"] / r["ms"],
             "stage_ms_per_step": r["stage"], "kernels": r["kernels"]}
+    photo = None
+    if args.photo_M > 0:
+        photo = photo_leg(native, torch, oracle, workloads, args.steps,
+                          args.warmup, args.photo_M)
     ms = head["ms"]
     dom = max(head["kernels"].values(), key=lambda k: k["ms_per_step"])
     roof = dict(dom)
@@ -324,6 +378,7 @@ def main():
         "roofline": roof,
         "other_precisions": others,
         "postproc": post,
+        "photoionization": photo,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)

@@ -152,6 +152,19 @@ def config4(M=20000):
                   "c4_n1500_nh40000_m%d" % M)
 
 
+def photo_b2(M=409600):
+    """Stand-in for the B II K-shell photoionization run (Sec. 3, Table 1:
+    400 coupled channels, 409,600 energies): one final symmetry of 400
+    channels and 24,800 poles (62 per channel, the ratio of the Sec. 6
+    Table 3 shapes) in [-5, 200], thresholds U[0, 2], M energies in [0, 20],
+    seed 5; bound-free dipoles d_k ~ N(0, 1) from seed 105; initial state
+    at e0 = -0.8 Ry.  Returns (workload, dipoles, e0)."""
+    w = single(400, 24800, -5.0, 200.0, 0.0, 20.0, M, 5,
+               "b2_photo_n400_nh24800_m%d" % M)
+    dip = np.random.default_rng(105).normal(size=24800)
+    return w, dip, -0.8
+
+
 def tiny(n=3, n_poles=12, M=40, seed=11, pole_lo=-2.0, pole_hi=30.0,
          mesh_lo=0.0, mesh_hi=6.0):
     """Small system for quick checks."""

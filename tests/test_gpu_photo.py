@@ -130,3 +130,23 @@ def test_photo_200_channels_sampled(torch_dev, nat):
     assert err < TOL_FP64
     assert np.all(np.isfinite(sig.cpu().numpy()))
     h.free()
+
+
+def test_photo_b2_shape_sampled(torch_dev, nat):
+    """The B II photoionization shape (400 channels, 24,800 poles): 512
+    energies spread over its 409,600-point mesh on the GPU, 4 of them against
+    the oracle."""
+    torch, dev = torch_dev
+    w, d, e0 = wl.photo_b2()
+    h = nat.load_symmetry(w.syms[0])
+    nat.rm_load_dipoles(h, d)
+    Em = w.mesh[::800]
+    E = torch.as_tensor(Em, dtype=torch.float64, device=dev)
+    sig, st = nat.rm_photoionization([h], E, e0)
+    torch.cuda.synchronize()
+    idx = wl.sample_indices(Em.size, 4, seed=3)
+    ref = oracle.photoionization([w.syms[0].as_dict()], [d], Em[idx], e0)
+    err = _err(sig.cpu().numpy()[idx], ref)
+    log("photo b2 sampled: %.2e" % err)
+    assert err < TOL_FP64
+    h.free()
