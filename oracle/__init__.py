@@ -27,6 +27,8 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
                                    level groups (statistical averaging)
 * ``photo.photoionization``       photoionization cross sections from the
                                    same solve and bound-free dipole vectors
+* ``outer.sweep_propagated``      Omega with the R-matrix propagated beyond
+                                   r = a through long-range multipole coupling
 
 It shares no code with the HIP path (``paper_1403_5524_amd``) and imports
 nothing from it; both sides receive the same seeded arrays from
@@ -41,6 +43,7 @@ from .postproc import (gaussian_convolve, effective_collision_strengths,
                        trapezoid_weights, group_collision_strengths)
 from .photo import (dipole_pole_sum, matching_solution, dipole_strength,
                     photoionization, SIGMA_CONST)
+from . import outer
 
 __all__ = [
     "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
@@ -51,5 +54,5 @@ __all__ = [
     "gaussian_convolve", "effective_collision_strengths", "trapezoid_weights",
     "group_collision_strengths",
     "dipole_pole_sum", "matching_solution", "dipole_strength",
-    "photoionization", "SIGMA_CONST",
+    "photoionization", "SIGMA_CONST", "outer",
 ]

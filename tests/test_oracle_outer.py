@@ -1,0 +1,104 @@
+"""Pins of the outer-region propagation oracle: direct integration of the
+coupled radial equations, exactness for a constant potential, and the pure
+Coulomb limit.  CPU only."""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+import oracle
+from oracle import outer
+
+
+def _ode_reduced_r(W_of_r, Rr_a, a, A, E):
+    """Rr(A) = U U'^-1 from integrating U'' = (W(r) - E) U with U(a) = Rr(a),
+    U'(a) = 1 (rtol 1e-12)."""
+    n = Rr_a.shape[0]
+
+    def f(r, y):
+        U = y[: n * n].reshape(n, n)
+        Up = y[n * n:].reshape(n, n)
+        return np.concatenate([Up.ravel(), ((W_of_r(r) - E * np.eye(n)) @ U).ravel()])
+
+    y0 = np.concatenate([Rr_a.ravel(), np.eye(n).ravel()])
+    sol = solve_ivp(f, (a, A), y0, method="DOP853", rtol=1e-12, atol=1e-14)
+    U = sol.y[: n * n, -1].reshape(n, n)
+    Up = sol.y[n * n:, -1].reshape(n, n)
+    return U @ np.linalg.inv(Up)
+
+
+def _sym_matrix(rng, n, scale):
+    M = rng.normal(0.0, scale, (n, n))
+    return 0.5 * (M + M.T)
+
+
+def test_constant_potential_is_exact_in_any_number_of_sectors():
+    rng = np.random.default_rng(1)
+    n, a, A = 3, 10.0, 16.0
+    W0 = _sym_matrix(rng, n, 0.3) + np.diag([0.0, 0.4, 1.1])
+    Rr_a = _sym_matrix(rng, n, 1.0)
+    for E in (0.2, 0.8, 1.5):   # open and closed eigenchannels
+        ref = _ode_reduced_r(lambda r: W0, Rr_a, a, A, E)
+        for n_sec in (1, 7):
+            secs = outer.sectors(lambda r: W0, a, A, n_sec)
+            got = outer.propagate(Rr_a, secs, E)
+            assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_multipole_coupling_against_direct_integration():
+    """Dipole and quadrupole coupling with centrifugal and Coulomb terms:
+    the sector result converges to the direct integration at second order
+    in the sector width."""
+    rng = np.random.default_rng(2)
+    n, a, A, z = 3, 12.0, 40.0, 1.0
+    e_thr = np.array([0.0, 0.15, 0.4])
+    l = np.array([0, 1, 2])
+    beta = np.stack([_sym_matrix(rng, n, 2.0), _sym_matrix(rng, n, 8.0)])
+
+    def Wr(r):
+        return outer.potential_matrix(r, e_thr, l, z, beta)
+    Rr_a = _sym_matrix(rng, n, 2.0)
+    E = 0.3
+    ref = _ode_reduced_r(Wr, Rr_a, a, A, E)
+    errs = []
+    for n_sec in (100, 200, 400):
+        got = outer.propagate(Rr_a, outer.sectors(Wr, a, A, n_sec), E)
+        errs.append(np.abs(got - ref).max() / np.abs(ref).max())
+    assert errs[-1] < 1e-4
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_pure_coulomb_outer_region_leaves_k_unchanged():
+    """With no multipole terms the outer solutions are the Coulomb functions
+    themselves, so matching after propagation to A must give the K of
+    matching at a (up to the sector error)."""
+    from paper_1403_5524_amd import workloads as wl
+    sym = wl.config1().syms[0].as_dict()
+    n = sym["e_thr"].size
+    prop = {"A": sym["a"] + 15.0, "n_sec": 800,
+            "beta": np.zeros((1, n, n))}
+    for E in (1.3, 4.2):
+        K0, P0 = oracle.k_matrix(
+            oracle.r_matrix(sym["E_pole"], sym["w"], sym["a"], E)[0],
+            sym["a"], *[v[0] for v in _cd_args(sym, E, sym["a"])])
+        K1, P1 = outer.k_matrix_propagated(sym, prop, E)
+        assert np.array_equal(P0, P1)
+        assert np.abs(K1 - K0).max() <= 1e-5 * max(1.0, np.abs(K0).max())
+
+
+def _cd_args(sym, E, r):
+    cd = oracle.channel_data(np.array([E]), sym["e_thr"], sym["l"], sym["z"], r)
+    return [cd[k] for k in ("open", "s", "c", "sp", "cp", "L")]
+
+
+def test_no_sectors_is_identity_and_sweep_runs():
+    rng = np.random.default_rng(3)
+    Rr = _sym_matrix(rng, 4, 1.0)
+    assert np.array_equal(outer.propagate(Rr, [], 0.7), Rr)
+    from paper_1403_5524_amd import workloads as wl
+    sym = wl.tiny().syms[0].as_dict()
+    n = sym["e_thr"].size
+    prop = {"A": sym["a"] + 5.0, "n_sec": 10,
+            "beta": np.stack([_sym_matrix(rng, n, 1.0)])}
+    om = outer.sweep_propagated(sym, prop, np.array([0.5, 2.0, 5.0]))
+    assert om.shape == (3, n * (n + 1) // 2)
+    assert np.all(np.isfinite(om)) and np.all(om >= 0.0)
