@@ -263,6 +263,27 @@ int rm_mesh_from_density(const float *dens, int32_t nw, double lo, double hi,
                          double floor_frac, int64_t M, double *E_out,
                          void *stream);
 
+/* ---- Outer-region propagation -------------------------------------------
+ * The paper matches at r = a; for real targets the channels stay coupled
+ * beyond a through the long-range multipole potentials of the target.
+ * rm_set_propagation makes every later sweep of `sym` (rm_sweep_energies,
+ * rm_kmatrix, plans) carry the R-matrix from a to A before matching there:
+ * for r >= a, u'' = (W(r) - E) u with
+ *   W_ij(r) = [e_i + l_i (l_i + 1)/r^2 - 2z/r] delta_ij
+ *             + sum_{lam = 1..lmax} beta[lam - 1][i][j] / r^(lam + 1),
+ * beta (host [lmax][n_chan][n_chan], input channel order, symmetric, Ry
+ * a0^(lam+1)); n_sec sectors of equal width, W frozen at each sector's
+ * midpoint and diagonalised once here (host Jacobi), the reduced R-matrix
+ * u u'^-1 stepped exactly across each sector in its eigenbasis on the
+ * device, R(A) matched to Coulomb / Whittaker functions at r = A (terms
+ * beyond A dropped).  n_sec = 0 switches the propagation off.  rm_rmatrix
+ * still returns R(a); rm_photoionization rejects propagated symmetries.
+ * Synchronises `stream`.  Errors: RM_ERR_ARG (n_sec outside [0, 1e5], lmax
+ * outside [0, 8], A not finite or <= a, beta null, not finite or not
+ * symmetric), RM_ERR_STATE, RM_ERR_NOMEM, RM_ERR_HIP. */
+int rm_set_propagation(rm_sym_t sym, double A, int32_t n_sec, int32_t lmax,
+                       const double *beta, void *stream);
+
 /* ---- Photoionization ---------------------------------------------------
  * The photoionization runs of the paper (Sec. 2-3: one dipole per pair of
  * dipole-allowed symmetries, the outer-region module for photoionization;

@@ -1038,18 +1038,19 @@ __device__ int wave_channel_functions(const SymDev &S, double Ee,
                                       ChanSlot *ch) {
   const int lane = lane_id();
   int bits = 0;
+  const double ra = S.r_match;
   for (int i = lane; i < S.n; i += WT) {
     const double diff = Ee - S.e_thr[i];
     ChanSlot c;
     if (diff > 0.0) {
-      const OpenVals v = coulomb_open(S.l[i], S.z, sqrt(diff), S.a);
+      const OpenVals v = coulomb_open(S.l[i], S.z, sqrt(diff), ra);
       c.d1 = v.c;
-      c.d2 = S.a * v.cp;
+      c.d2 = ra * v.cp;
       c.s = v.s;
-      c.asp = S.a * v.sp;
+      c.asp = ra * v.sp;
       if (!v.ok) bits |= RM_E_CF_NOCONV;
     } else if (diff < 0.0) {
-      const ClosedVals v = whittaker_closed(S.l[i], S.z, sqrt(-diff), S.a);
+      const ClosedVals v = whittaker_closed(S.l[i], S.z, sqrt(-diff), ra);
       c.d1 = v.e;
       c.d2 = v.ep;
       c.s = 0.0;
@@ -1254,6 +1255,7 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
   return wave_or(bits);
 }
 
+#ifndef RM_MATCH_DEVICE_ONLY
 __global__ __launch_bounds__(WT *WPB) void match_kernel(MatchLaunch L) {
   __shared__ WaveLds lds[WPB];
   const int lane = lane_id();
@@ -1281,5 +1283,7 @@ hipError_t launch_match(const MatchLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(match_kernel, dim3(blocks), dim3(WT * WPB), 0, st, L);
   return hipGetLastError();
 }
+
+#endif  // RM_MATCH_DEVICE_ONLY
 
 }  // namespace rmx

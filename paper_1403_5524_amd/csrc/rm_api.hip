@@ -384,6 +384,7 @@ struct Plan {
   double *sigma = nullptr;
   double e0 = 0.0;
   std::vector<int64_t> h_work_off;  // host copy of the workspace offsets
+  bool propagate = false;           // some symmetry has outer sectors
   // rm_kmatrix-style extras (single symmetry)
   double *K_out = nullptr;
   int32_t *n_open_out = nullptr;
@@ -728,6 +729,7 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   p.work_estride = wacc;
   p.chan_estride = cacc;
   p.h_work_off = woff;
+  for (const Sym *q : v) p.propagate = p.propagate || q->n_sec > 0;
   int64_t C = o.chunk > 0 ? o.chunk
                           : (int64_t)(ws_budget / (8.0 * wacc + 32.0 * cacc + 64.0));
   C = std::max<int64_t>(1, std::min<int64_t>(C, 4096));
@@ -852,6 +854,7 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.counter = p.counters + c;
     L.grid = p.match_grid;
     StageTimer tm(2, st);
+    if (p.propagate) RM_HIP(launch_propagate(L, st));
     RM_HIP(launch_match(L, st));
   }
   return RM_OK;
@@ -881,7 +884,8 @@ static int free_sym(Sym *s) {
   pd_release(*s);
   void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
                   s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT,
-                  s->pair_ij, s->Ph, s->Pl, s->P32, s->P64, s->dip};
+                  s->pair_ij, s->Ph, s->Pl, s->P32, s->P64, s->dip,
+                  s->prop_O, s->prop_eps};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete[] s->h_e_thr;
@@ -1114,6 +1118,147 @@ int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
   return rc;
 }
 
+int rm_set_propagation(rm_sym_t sym, double A, int32_t n_sec, int32_t lmax,
+                       const double *beta, void *stream) {
+  if (!sym) return fail(RM_ERR_ARG, "null handle");
+  int rc = check_device(sym);
+  if (rc) return rc;
+  if (n_sec < 0 || n_sec > 100000) return fail(RM_ERR_ARG, "n_sec outside [0, 1e5]");
+  if (lmax < 0 || lmax > 8) return fail(RM_ERR_ARG, "lmax outside [0, 8]");
+  hipStream_t st = (hipStream_t)stream;
+  RM_HIP(hipStreamSynchronize(st));  // queued sweeps may still read the old sectors
+  if (n_sec == 0) {
+    sym->n_sec = 0;
+    return RM_OK;
+  }
+  if (!(A > sym->a) || !std::isfinite(A)) return fail(RM_ERR_ARG, "A must be finite and > a");
+  const int n = sym->n;
+  if (lmax > 0 && !beta) return fail(RM_ERR_ARG, "null beta");
+  for (int64_t q = 0; q < (int64_t)lmax * n * n; ++q)
+    if (!std::isfinite(beta[q])) return fail(RM_ERR_ARG, "beta not finite");
+  for (int lam = 0; lam < lmax; ++lam)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j) {
+        const double x = beta[((int64_t)lam * n + i) * n + j];
+        const double y = beta[((int64_t)lam * n + j) * n + i];
+        if (std::fabs(x - y) > 1e-12 * std::max(1.0, std::fabs(x)))
+          return fail(RM_ERR_ARG, "beta[%d] not symmetric", lam + 1);
+      }
+  // sorted channel order: position p holds input channel perm[p]
+  std::vector<int> lsort(n);
+  {
+    std::vector<int32_t> lh(n);
+    RM_HIP(hipMemcpy(lh.data(), sym->l, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) lsort[i] = lh[i];
+  }
+  const double h = (A - sym->a) / n_sec;
+  const size_t nsq = (size_t)n * n;
+  std::vector<double> O((size_t)(n_sec + 1) * nsq), eps((size_t)n_sec * n);
+  std::vector<double> U(nsq, 0.0), Unew(nsq), Wm(nsq), T(nsq);
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;  // previous basis
+  for (int sct = 0; sct < n_sec; ++sct) {
+    const double r = sym->a + (sct + 0.5) * h;
+    // W(r) in sorted order
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double w = 0.0;
+        if (i == j)
+          w = sym->h_e_thr[i] + lsort[i] * (lsort[i] + 1.0) / (r * r) -
+              2.0 * sym->z / r;
+        double rp = r * r;
+        for (int lam = 0; lam < lmax; ++lam) {
+          w += beta[((int64_t)lam * n + sym->h_perm[i]) * n + sym->h_perm[j]] / rp;
+          rp *= r;
+        }
+        Wm[(size_t)i * n + j] = w;
+      }
+    // warm start: B = U^T W U (nearly diagonal after the first sector),
+    // then cyclic Jacobi rotations B <- J^T B J, V <- V J until the
+    // off-diagonal part is negligible; the sector basis is U V
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += Wm[(size_t)i * n + k] * U[(size_t)k * n + j];
+        T[(size_t)i * n + j] = acc;
+      }
+    std::vector<double> B(nsq), V(nsq, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += U[(size_t)k * n + i] * T[(size_t)k * n + j];
+        B[(size_t)i * n + j] = acc;
+      }
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    double fro = 0.0;
+    for (size_t q = 0; q < nsq; ++q) fro += B[q] * B[q];
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      double off = 0.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) off += B[(size_t)i * n + j] * B[(size_t)i * n + j];
+      if (off <= 1e-32 * fro) break;
+      for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q) {
+          const double bpq = B[(size_t)p * n + q];
+          if (bpq == 0.0) continue;
+          const double bpp = B[(size_t)p * n + p], bqq = B[(size_t)q * n + q];
+          // rotation zeroing (p, q): t = sgn(th) / (|th| + sqrt(th^2 + 1)),
+          // th = (bqq - bpp) / (2 bpq)
+          const double th = (bqq - bpp) / (2.0 * bpq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+          const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+          for (int k = 0; k < n; ++k) {  // columns p, q
+            const double bkp = B[(size_t)k * n + p], bkq = B[(size_t)k * n + q];
+            B[(size_t)k * n + p] = c * bkp - sn * bkq;
+            B[(size_t)k * n + q] = sn * bkp + c * bkq;
+          }
+          for (int k = 0; k < n; ++k) {  // rows p, q
+            const double bpk = B[(size_t)p * n + k], bqk = B[(size_t)q * n + k];
+            B[(size_t)p * n + k] = c * bpk - sn * bqk;
+            B[(size_t)q * n + k] = sn * bpk + c * bqk;
+          }
+          B[(size_t)p * n + q] = B[(size_t)q * n + p] = 0.0;
+          for (int k = 0; k < n; ++k) {
+            const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+            V[(size_t)k * n + p] = c * vkp - sn * vkq;
+            V[(size_t)k * n + q] = sn * vkp + c * vkq;
+          }
+        }
+    }
+    // sector basis U_s = U V; O_s = U_prev^T U_s = V
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) acc += U[(size_t)i * n + k] * V[(size_t)k * n + j];
+        Unew[(size_t)i * n + j] = acc;
+      }
+    std::copy(V.begin(), V.end(), O.begin() + (size_t)sct * nsq);
+    for (int i = 0; i < n; ++i) eps[(size_t)sct * n + i] = B[(size_t)i * n + i];
+    U.swap(Unew);
+  }
+  // back to the channel basis: X <- O^T X O with O = U_last^T
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) O[(size_t)n_sec * nsq + (size_t)i * n + j] = U[(size_t)j * n + i];
+  double *dO = nullptr, *de = nullptr;
+  hipError_t e = hipMalloc((void **)&dO, O.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&de, eps.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(dO, O.data(), O.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(de, eps.data(), eps.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (dO) (void)hipFree(dO);
+    if (de) (void)hipFree(de);
+    return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
+                "propagation tables: %s", hipGetErrorString(e));
+  }
+  if (sym->prop_O) (void)hipFree(sym->prop_O);
+  if (sym->prop_eps) (void)hipFree(sym->prop_eps);
+  sym->prop_O = dO;
+  sym->prop_eps = de;
+  sym->n_sec = n_sec;
+  sym->A = A;
+  sym->h_sec = h;
+  return RM_OK;
+}
+
 int rm_load_dipoles(rm_sym_t sym, const double *d, void *stream) {
   if (!sym || !d) return fail(RM_ERR_ARG, "null handle or dipoles");
   int rc = check_device(sym);
@@ -1146,6 +1291,9 @@ int rm_photoionization(const rm_sym_t *syms, int32_t n_sym, const double *E,
     if (!syms[q]) return fail(RM_ERR_ARG, "null handle %d", q);
     if (!syms[q]->dip)
       return fail(RM_ERR_ARG, "symmetry %d has no dipoles (rm_load_dipoles)", q);
+    if (syms[q]->n_sec > 0)
+      return fail(RM_ERR_ARG, "symmetry %d has an outer-region propagation: "
+                  "photoionization matches at r = a", q);
     n_tgt = std::max(n_tgt, syms[q]->n_target);
   }
   if (M > 0 && (!E || !sigma)) return fail(RM_ERR_ARG, "null E or sigma");

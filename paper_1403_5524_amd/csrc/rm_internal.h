@@ -40,6 +40,15 @@ struct SymDev {
   const float *P32;           // [np_pad][nh_pad] FP32 w_ik w_jk
   const double *P64;          // [np_pad][nh_pad] FP64 w_ik w_jk
   const double *dip;          // [nh_pad] bound-free dipoles, or null
+  // outer-region propagation from a to A (n_sec = 0: none): sector s
+  // rotates the reduced R-matrix by O_s (X <- O_s^T X O_s) and then steps
+  // it across width h_sec with eigenvalues eps_s; O_{n_sec} returns to the
+  // channel basis.  Sorted channel order, leading dimension n.
+  int n_sec;
+  double A, h_sec;
+  double r_match;             // radius of the matching: A with sectors, else a
+  const double *prop_O;       // [n_sec + 1][n][n]
+  const double *prop_eps;     // [n_sec][n]
 };
 
 // A symmetry resident on one device.  Channels are stored sorted by
@@ -69,6 +78,9 @@ struct Sym {
   float *P32;
   double *P64;
   double *dip = nullptr;  // [nh_pad] dipoles with the initial state (owned)
+  int n_sec = 0;          // outer-region sectors (0: match at r = a)
+  double A = 0.0, h_sec = 0.0;
+  double *prop_O = nullptr, *prop_eps = nullptr;  // owned
   // host copies
   double *h_e_thr;      // [n] sorted
   int32_t *h_perm;
@@ -81,6 +93,9 @@ struct Sym {
     d.ntu = ntu; d.ut = ut; d.G = G; d.GT = GT;
     d.np = np; d.np_pad = np_pad; d.pair_ij = pair_ij;
     d.Ph = Ph; d.Pl = Pl; d.P32 = P32; d.P64 = P64; d.dip = dip;
+    d.n_sec = n_sec; d.A = A; d.h_sec = h_sec;
+    d.r_match = n_sec > 0 ? A : a;
+    d.prop_O = prop_O; d.prop_eps = prop_eps;
     return d;
   }
 };
@@ -182,6 +197,9 @@ struct MatchLaunch {
   int grid;
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
+// R(a) -> R(A) for the symmetries with outer-region sectors (same launch
+// description as the matching; run between the pole sum and the matching).
+hipError_t launch_propagate(const MatchLaunch &L, hipStream_t st);
 
 // Dipole pole sum g_i(E) = (1/sqrt2) sum_k w_ik d_k / (E_k - E) of one
 // symmetry (sorted channel order) at the m energies E, written to

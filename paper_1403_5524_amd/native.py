@@ -32,7 +32,8 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_mlp_get_params", "rm_mlp_set_params", "rm_mlp_forward",
             "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
             "rm_plan_create", "rm_plan_execute", "rm_plan_info",
-            "rm_plan_free", "rm_load_dipoles", "rm_photoionization",
+            "rm_plan_free", "rm_set_propagation", "rm_load_dipoles",
+            "rm_photoionization",
             "rm_convolve_gaussian",
             "rm_effective_collision_strengths",
             "rm_group_collision_strengths", "rm_last_error")
@@ -100,6 +101,7 @@ def lib():
         L.rm_plan_execute.argtypes = [vp, vp]
         L.rm_plan_info.argtypes = [vp, vp, vp, vp, i32]
         L.rm_plan_free.argtypes = [vp]
+        L.rm_set_propagation.argtypes = [vp, f64, i32, i32, vp, vp]
         L.rm_load_dipoles.argtypes = [vp, vp, vp]
         L.rm_photoionization.argtypes = [vp, i32, vp, i64, f64,
                                          ctypes.POINTER(Opts), vp, vp, vp]
@@ -438,3 +440,17 @@ def rm_photoionization(syms, E, e0, opts=None, sigma=None, status=None):
                                     ctypes.byref(o), _ptr(sigma),
                                     _ptr(status), _stream()))
     return sigma, status
+
+
+def rm_set_propagation(sym, A, n_sec, beta=None):
+    """Propagate sym's R-matrix from a to A through n_sec sectors of the
+    multipole coupling beta [lmax, n, n] (host; None: no multipoles)."""
+    if beta is None:
+        beta = np.zeros((0, sym.n, sym.n))
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if b.ndim != 3 or b.shape[1:] != (sym.n, sym.n):
+        raise RmError(RM_ERR_ARG, "beta must be [lmax, n, n]")
+    _check(lib().rm_set_propagation(sym.handle, float(A), int(n_sec),
+                                    int(b.shape[0]),
+                                    b.ctypes.data if b.size else None,
+                                    _stream()))

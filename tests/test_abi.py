@@ -163,3 +163,8 @@ def test_photo_rejects_invalid(L):
                                 None) == native.RM_ERR_ARG
     assert b"e0" in L.rm_last_error()
     assert L.rm_load_dipoles(None, dummy, None) == native.RM_ERR_ARG
+
+
+def test_propagation_rejects_invalid(L):
+    assert L.rm_set_propagation(None, ctypes.c_double(30.0), 10, 1, None,
+                                None) == native.RM_ERR_ARG
