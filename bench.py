@@ -10,13 +10,15 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
                     [--also bf16x3,fp32] [--graph] [--workload c2|c3|c4]
-                    [--no-postproc] [--photo-M N]
+                    [--no-postproc] [--photo-M N] [--outer-M N]
 
 After the headline sweep, the sweep's FP64 Omega is smoothed, averaged into
 effective collision strengths and summed over level groups; those kernels'
 times and rooflines are reported under "postproc".  A photoionization leg
 times rm_photoionization on the B II shape of the paper's Table 1 (400
-channels, every 50th energy of 409,600) under "photoionization".
+channels, every 50th energy of 409,600) under "photoionization", and an
+outer-region leg sweeps the headline symmetry with the R-matrix propagated
+through multipole coupling (rm_set_propagation) under "outer_propagation".
 """
 import argparse
 import json
@@ -198,6 +200,66 @@ def photo_leg(native, torch, oracle, workloads, steps, warmup, count):
                               "ratio": Em.size / (ms * 1e-3) / (409600 / 149.70)}}
 
 
+def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
+              n_sec=20, width=20.0):
+    """The headline symmetry with the outer-region propagation switched on
+    (dipole and quadrupole coupling, A = a + 20, 20 sectors): `count`
+    energies spread over the mesh, Omega checked against the oracle on 3."""
+    from oracle import outer
+    w = workloads.config2()
+    sym = w.syms[0]
+    beta = workloads.outer_coupling(sym.n)
+    A = sym.a + width
+    stride = max(1, w.mesh.size // count)
+    Em = w.mesh[::stride][:count]
+    h = native.load_symmetry(sym)
+    t0 = time.perf_counter()
+    native.rm_set_propagation(h, A, n_sec, beta)
+    setup = time.perf_counter() - t0
+    E = torch.as_tensor(Em, dtype=torch.float64, device="cuda:0")
+    P = w.n_target * (w.n_target + 1) // 2
+    om = torch.empty((Em.size, P), dtype=torch.float64, device=E.device)
+    st = torch.empty(E.shape, dtype=torch.int32, device=E.device)
+    opts = native.make_opts()
+    for _ in range(warmup):
+        native.rm_sweep_energies([h], w.n_target, E, opts, om, st)
+    torch.cuda.synchronize()
+    native.rm_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        native.rm_sweep_energies([h], w.n_target, E, opts, om, st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stage = {k: native.rm_profile_query(k)[0] / steps
+             for k in ("polesum", "propagate", "match")}
+    native.rm_profile(False)
+    idx = workloads.sample_indices(Em.size, 3, seed=4)
+    prop = {"A": A, "n_sec": n_sec, "beta": beta}
+    ref = outer.sweep_propagated(sym.as_dict(), prop, Em[idx], w.n_target)
+    got = om.cpu().numpy()[idx]
+    err = float((np.abs(got - ref).max(axis=1)
+                 / np.maximum(np.abs(ref).max(axis=1), 1e-300)).max())
+    h.free()
+    n = sym.n
+    # per energy: per sector X O and O^T (X O) (2 n^3 each), the LU of the
+    # sector system (2 n^3 / 3) and its n right-hand sides (2 n^3); the final
+    # basis change (4 n^3)
+    flops = Em.size * (n_sec * (4.0 + 2.0 / 3.0 + 2.0) + 4.0) * n ** 3
+    ach = flops / (stage["propagate"] * 1e-3) / 1e12 if stage["propagate"] else None
+    note("outer propagation: %.1f ms for %d energies (propagation %.1f ms), "
+         "err %.2e" % (ms, Em.size, stage["propagate"], err))
+    return {"workload": w.name + "+outer(A=a+%g, %d sectors, lmax 2)"
+                        % (width, n_sec),
+            "energies_timed": int(Em.size), "value": Em.size / (ms * 1e-3),
+            "unit": "energies/s", "ms_per_step": ms,
+            "stage_ms_per_step": stage, "setup_s": setup,
+            "max_rel_err_omega": err, "err_sample": int(idx.size),
+            "propagation_roofline": {"bound": "mfma", "achieved": ach,
+                                     "peak": 78.6, "unit": "TFLOP/s",
+                                     "frac": ach / 78.6 if ach else None,
+                                     "flops_per_step": flops}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +280,9 @@ def main():
                     help="also time replays of a hipGraph-captured plan")
     ap.add_argument("--no-postproc", action="store_true",
                     help="skip timing the post-processing of Omega")
+    ap.add_argument("--outer-M", type=int, default=2048,
+                    help="energies of the outer-region propagation leg; "
+                         "0 skips it")
     ap.add_argument("--photo-M", type=int, default=8192,
                     help="energies of the photoionization leg (B II shape); "
                          "0 skips it")
@@ -341,6 +406,10 @@ def main():
             "max_rel_err_omega": r["err"], "status_flagged": r["flagged"],
             "speedup_over_%s" % args.prec: head["ms"] / r["ms"],
             "stage_ms_per_step": r["stage"], "kernels": r["kernels"]}
+    outer_res = None
+    if args.outer_M > 0:
+        outer_res = outer_leg(native, torch, oracle, workloads, args.steps,
+                              args.warmup, args.outer_M)
     photo = None
     if args.photo_M > 0:
         photo = photo_leg(native, torch, oracle, workloads, args.steps,
@@ -379,6 +448,7 @@ def main():
         "other_precisions": others,
         "postproc": post,
         "photoionization": photo,
+        "outer_propagation": outer_res,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)

@@ -216,8 +216,9 @@ int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m,
  * stage 1 (pole sum), 2 (channel functions, matching, K, T, Omega), 3
  * (rm_plan_execute graph replays), 4 (the banded product of
  * rm_convolve_gaussian), 5 (the pass over Omega of
- * rm_effective_collision_strengths) or 6 (the pass of
- * rm_group_collision_strengths), the summed time in milliseconds and the
+ * rm_effective_collision_strengths), 6 (the pass of
+ * rm_group_collision_strengths) or 7 (the outer-region propagation of
+ * rm_set_propagation), the summed time in milliseconds and the
  * number of launches (stage 0 is kept for compatibility and stays empty).
  * Not thread-safe with concurrent sweeps while enabled. */
 int rm_profile(int32_t enable);

@@ -853,8 +853,11 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.e0 = p.e0;
     L.counter = p.counters + c;
     L.grid = p.match_grid;
+    if (p.propagate) {
+      StageTimer tp(7, st);
+      RM_HIP(launch_propagate(L, st));
+    }
     StageTimer tm(2, st);
-    if (p.propagate) RM_HIP(launch_propagate(L, st));
     RM_HIP(launch_match(L, st));
   }
   return RM_OK;
@@ -909,7 +912,7 @@ int rm_profile(int32_t enable) {
 }
 
 int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches) {
-  if (stage < 0 || stage > 6) return fail(RM_ERR_ARG, "stage %d", stage);
+  if (stage < 0 || stage > 7) return fail(RM_ERR_ARG, "stage %d", stage);
   double tot = 0.0;
   int64_t cnt = 0;
   for (auto &r : g_recs) {

@@ -251,7 +251,7 @@ def rm_channel_functions(sym, E):
 
 
 STAGES = {"chanfn": 0, "polesum": 1, "match": 2, "graph": 3, "convolve": 4,
-          "upsilon": 5, "group": 6}
+          "upsilon": 5, "group": 6, "propagate": 7}
 
 
 def rm_profile(enable):

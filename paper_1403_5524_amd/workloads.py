@@ -165,6 +165,18 @@ def photo_b2(M=409600):
     return w, dip, -0.8
 
 
+def outer_coupling(n, lmax=2, seed=6, scales=(1.0, 4.0)):
+    """Long-range multipole coefficients beta [lmax, n, n] (symmetric,
+    N(0, scale^2) off and on the diagonal; lam = 1 dipole, 2 quadrupole) for
+    the outer-region propagation, seeded."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for lam in range(lmax):
+        M = rng.normal(0.0, scales[lam], (n, n))
+        out.append(0.5 * (M + M.T))
+    return np.stack(out)
+
+
 def tiny(n=3, n_poles=12, M=40, seed=11, pole_lo=-2.0, pole_hi=30.0,
          mesh_lo=0.0, mesh_hi=6.0):
     """Small system for quick checks."""
