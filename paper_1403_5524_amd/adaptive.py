@@ -10,7 +10,7 @@ with the plain (FP64) method is the judge.
 Pipeline (all arrays for the sweep and the network live on the GPU):
   features(sym)            host: pole counts, amplitude norms, thresholds
   judge = sweep(uniform)   rm_sweep_energies over a uniform fine mesh
-  labels = log variation of Omega per window (from the judge)
+  labels = log curvature of Omega per window (from the judge)
   train                    rm_mlp_grad + rm_mlp_adam_step
   density = 10**mlp(features) -> rm_mesh_from_density -> adaptive mesh
   evaluate                 integrated Omega per transition vs the judge,
@@ -76,11 +76,14 @@ def window_features(sym, lo, hi, nw):
 
 
 class Judge:
-    """Per-transition integrals and per-window variation of a swept mesh."""
+    """Per-transition integrals and per-window variation and curvature of a
+    swept mesh."""
 
-    def __init__(self, integrals, variation, total, mesh_size):
+    def __init__(self, integrals, variation, total, mesh_size,
+                 curvature=None):
         self.integrals = integrals      # [P] float64 (numpy)
         self.variation = variation      # [nw] float64
+        self.curvature = curvature      # [nw] float64: max |second difference|
         self.total = total
         self.mesh_size = mesh_size
 
@@ -91,7 +94,9 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
 
     Returns a Judge: trapezoid integrals of every Omega(t, t') over [lo, hi]
     (end segments held constant), and, when nw is given, the total variation
-    of sum_pairs Omega in each of nw windows.
+    of sum_pairs Omega in each of nw windows and the largest second
+    difference of it there (on a uniform mesh, proportional to the
+    curvature).
     """
     import torch
     M = int(E.numel())
@@ -99,6 +104,7 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
     dev = E.device
     integ = torch.zeros(P, dtype=torch.float64, device=dev)
     var = torch.zeros(nw if nw else 1, dtype=torch.float64, device=dev)
+    curv = np.zeros(nw if nw else 1)
     prev_E, prev_om = None, None
     h = (hi - lo) / nw if nw else None
     for c0 in range(0, M, chunk):
@@ -118,19 +124,27 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
             mid = 0.5 * (Ec2[1:] + Ec2[:-1])
             wi = ((mid - lo) / h).floor().clamp(0, nw - 1).long()
             var.index_add_(0, wi, dv)
+            if sig.numel() > 2:
+                d2 = (sig[2:] - 2.0 * sig[1:-1] + sig[:-2]).abs()
+                ci = ((Ec2[1:-1] - lo) / h).floor().clamp(0, nw - 1).long()
+                d2h = d2.cpu().numpy()
+                ok = np.isfinite(d2h)
+                np.maximum.at(curv, ci.cpu().numpy()[ok], d2h[ok])
         prev_E, prev_om = Ec[-1].clone(), om[-1].clone()
         del om
     integ += prev_om * (hi - prev_E)
     torch.cuda.synchronize()
     return Judge(integ.cpu().numpy(), var.cpu().numpy() if nw else None,
-                 float(integ.sum().item()), M)
+                 float(integ.sum().item()), M,
+                 curv if nw else None)
 
 
-def labels_from_variation(variation):
-    """log10 of the window's variation relative to the mean (floored)."""
+def labels_from_variation(variation, scale="mean"):
+    """log10 of the window's variation (or curvature) relative to its mean,
+    or to its median when a few windows dominate the mean (floored)."""
     v = np.asarray(variation, dtype=np.float64)
-    mean = max(v.mean(), 1e-300)
-    return np.log10(v / mean + 1e-3).astype(np.float32)
+    ref = np.median(v) if scale == "median" else v.mean()
+    return np.log10(v / max(ref, 1e-300) + 1e-3).astype(np.float32)
 
 
 def heuristic_density(sym, lo, hi, nw):
@@ -211,9 +225,16 @@ def integrated_error(test, judge, rel_floor=1e-6):
 
 def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
                    lo=0.0, hi=20.0, M_judge=1000000, M_adapt=100000,
-                   nw=4096, steps=1500, log=print):
+                   nw=4096, steps=1500, log=print, label="curvature"):
     """Train on train_seeds, evaluate uniform / heuristic / learned meshes of
-    M_adapt points on test_seed against the M_judge uniform judge."""
+    M_adapt points on test_seed against the M_judge uniform judge.
+
+    label "curvature" (default): the network learns log10 of each window's
+    largest second difference of sum Omega (relative to the median window)
+    and the density follows its square root (a peak of width G and height
+    A has curvature ~ A/G^2, so the density grows as 1/G: what resolving it
+    takes); "variation": it learns the window's total variation (relative
+    to the mean) and the density follows it."""
     import torch
     from . import workloads as wl
     dev = torch.device("cuda:0")
@@ -226,7 +247,13 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
         E = torch.as_tensor(wl.uniform_mesh(lo, hi, M_judge), device=dev)
         j = sweep_integrals([h], n, E, lo, hi, nw=nw)
         feats.append(window_features(sym, lo, hi, nw))
-        labels.append(labels_from_variation(j.variation))
+        if label == "curvature":   # a few sharp peaks dominate its mean
+            labels.append(labels_from_variation(j.curvature, "median"))
+        else:
+            labels.append(labels_from_variation(j.variation))
+        log("labels: min %.2f median %.2f max %.2f, %d not finite"
+            % (labels[-1].min(), np.median(labels[-1]), labels[-1].max(),
+               int((~np.isfinite(labels[-1])).sum())))
         h.free()
         log("train system %d swept (%d energies)" % (s, M_judge))
     X = np.concatenate(feats)
@@ -247,10 +274,12 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
         "heuristic": native.rm_mesh_from_density(
             torch.as_tensor(heuristic_density(sym, lo, hi, nw), device=dev),
             lo, hi, 0.3, M_adapt),
-        "learned": mesh_from_log_density(pred, lo, hi, M_adapt),
+        "learned": mesh_from_log_density(
+            pred, lo, hi, M_adapt, alpha=0.5 if label == "curvature" else 1.0),
     }
     min_w = 2.0 * (hi - lo) / M_judge
-    out = {"train_loss": hist, "judge_points": M_judge, "points": M_adapt}
+    out = {"train_loss": hist, "judge_points": M_judge, "points": M_adapt,
+           "label": label}
     for name, E in meshes.items():
         r = sweep_integrals([h], n, E, lo, hi)
         mx, mean = integrated_error(r, judge)
@@ -267,6 +296,8 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
 if __name__ == "__main__":   # full-size experiment on the GPU
     import json
     import sys
-    res = run_experiment(train_seeds=list(range(1000, 1004)), test_seed=3000)
+    label = sys.argv[1] if len(sys.argv) > 1 else "curvature"
+    res = run_experiment(train_seeds=list(range(1000, 1004)), test_seed=3000,
+                         label=label)
     json.dump(res, sys.stdout)
     print()
