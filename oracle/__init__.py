@@ -29,6 +29,9 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
                                    same solve and bound-free dipole vectors
 * ``outer.sweep_propagated``      Omega with the R-matrix propagated beyond
                                    r = a through long-range multipole coupling
+* ``inner.inner_region``          poles and surface amplitudes from the full
+                                   eigen-solve of a model inner-region
+                                   Hamiltonian
 
 It shares no code with the HIP path (``paper_1403_5524_amd``) and imports
 nothing from it; both sides receive the same seeded arrays from
@@ -44,6 +47,7 @@ from .postproc import (gaussian_convolve, effective_collision_strengths,
 from .photo import (dipole_pole_sum, matching_solution, dipole_strength,
                     photoionization, SIGMA_CONST)
 from . import outer
+from . import inner
 
 __all__ = [
     "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
@@ -54,5 +58,5 @@ __all__ = [
     "gaussian_convolve", "effective_collision_strengths", "trapezoid_weights",
     "group_collision_strengths",
     "dipole_pole_sum", "matching_solution", "dipole_strength",
-    "photoionization", "SIGMA_CONST", "outer",
+    "photoionization", "SIGMA_CONST", "outer", "inner",
 ]
