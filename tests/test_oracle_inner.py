@@ -60,3 +60,40 @@ def test_rmatrix_from_poles_against_direct_integration(E):
         R[i, i] += (2.0 / a ** 2) * np.sum(1.0 / (kap ** 2 + e - E))
     Rref = ode_rmatrix(_as_system(m), E)
     assert np.abs(R - Rref).max() < 2e-5 * np.abs(Rref).max()
+
+
+@pytest.mark.parametrize("Q", [1, 2, 7, 50])
+def test_quadrature_is_gauss_legendre(Q):
+    """Nodes and weights on [0, a] agree with numpy's Gauss-Legendre rule
+    mapped there (absolute, in x), and integrate r^k exactly for k < 2Q."""
+    from numpy.polynomial import legendre as npleg
+    a = 3.0
+    r, w = inner.quadrature(a, Q)
+    x, wl = npleg.leggauss(Q)
+    assert np.abs((2.0 * r / a - 1.0) - x).max() < 4e-16
+    assert np.abs(2.0 * w / a - wl).max() < 1e-14
+    for k in range(2 * Q):
+        exact = a ** (k + 1) / (k + 1)
+        assert abs(np.sum(w * r ** k) - exact) < 1e-13 * exact
+
+
+@pytest.mark.parametrize("Q,nodes", [(50, range(50)), (400, (0, 1, 2, 200)),
+                                     (1000, (0, 1)), (4000, (0,))])
+def test_quadrature_nodes_relative_accuracy(Q, nodes):
+    """Next to r = 0 each node must carry full relative accuracy (the
+    centrifugal term scales as 1/r^2 there): the zeros of P_Q and their
+    weights 2 / ((1 - x^2) P_Q'(x)^2) from mpmath at 40 digits, compared as
+    r = 1 + x on [0, 2].  (Forming 1 - cos(theta) instead of 2 sin^2(theta/2)
+    is off by 1.5e-13 at Q = 4000.)"""
+    import mpmath as mp
+    r, w = inner.quadrature(2.0, Q)
+    with mp.workdps(40):
+        f = lambda x: mp.re(mp.legendre(Q, x))
+        for k in nodes:
+            xk = mp.re(mp.findroot(f, mp.mpf(float(r[k])) - 1,
+                                   tol=mp.mpf(10) ** -60))
+            dp = mp.re(mp.diff(f, xk))
+            rk = 1 + xk
+            wk = 2 / ((1 - xk * xk) * dp * dp)
+            assert abs(float((r[k] - rk) / rk)) < 1e-14
+            assert abs(float((w[k] - wk) / wk)) < 1e-14
