@@ -10,7 +10,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
                     [--also bf16x3,fp32] [--graph] [--workload c2|c3|c4]
-                    [--no-postproc] [--photo-M N] [--outer-M N]
+                    [--no-postproc] [--photo-M N] [--outer-M N] [--inner-N N]
 
 After the headline sweep, the sweep's FP64 Omega is smoothed, averaged into
 effective collision strengths and summed over level groups; those kernels'
@@ -19,6 +19,9 @@ times rm_photoionization on the B II shape of the paper's Table 1 (400
 channels, every 50th energy of 409,600) under "photoionization", and an
 outer-region leg sweeps the headline symmetry with the R-matrix propagated
 through multipole coupling (rm_set_propagation) under "outer_propagation".
+An inner-region leg times the full eigen-solve that supplies poles and
+amplitudes (rm_inner_region, 8 channels x 512 sine functions, D = 4096) under
+"inner_region", with the oracle's solve of the same model as its CPU baseline.
 """
 import argparse
 import json
@@ -260,6 +263,60 @@ def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
                                      "flops_per_step": flops}}
 
 
+def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
+    """The inner-region eigen-solve that supplies the poles: a model of 8
+    channels x n_basis sine functions (D = 8 n_basis), all eigenpairs on the
+    device; eigenvalues checked against the oracle within the backward-error
+    budget 8 (D + Q) eps S, S the spectrum's scale."""
+    m = workloads.inner_model()
+    n = m["e_thr"].size
+    D = n * n_basis
+    Q = n_basis + 48
+    native.rm_inner_region(m, n_basis)          # warm-up (code objects)
+    native.rm_profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        E, w, sweeps, rot = native.rm_inner_region(m, n_basis)
+    s_per = (time.perf_counter() - t0) / steps
+    jac_ms, jac_n = native.rm_profile_query("jacobi")
+    asm_ms, _ = native.rm_profile_query("assemble")
+    native.rm_profile(False)
+    jac_ms /= steps
+    asm_ms /= steps
+    Dp = D + (D & 1)
+    launches = sweeps * (Dp - 1)
+    # per step every column of A is read for the pair dots; a rotated pair
+    # writes its two A columns and reads and writes its two V columns
+    bytes_solve = launches * 8.0 * Dp * Dp + rot * 48.0 * Dp
+    ach = bytes_solve / (jac_ms * 1e-3) / 1e9 if jac_ms else None
+    t0 = time.perf_counter()
+    Eo, wo = oracle.inner.inner_region(m, n_basis)
+    cpu_s = time.perf_counter() - t0
+    S = max(float(np.abs(Eo).max()), 1.0)
+    eta = 8.0 * (D + Q) * np.finfo(float).eps * S
+    ratio = float(np.abs(E - Eo).max() / eta)
+    note("inner region D=%d: %.3f s per solve (%d sweeps, Jacobi %.1f ms, "
+         "assembly %.1f ms), eigenvalue error / budget %.2e"
+         % (D, s_per, sweeps, jac_ms, asm_ms, ratio))
+    out = {"workload": "model inner region, %d channels x %d sine functions "
+                       "(D = %d), a = %g" % (n, n_basis, D, m["a"]),
+           "value": 1.0 / s_per, "unit": "solves/s", "s_per_solve": s_per,
+           "sweeps": int(sweeps), "rotations": int(rot),
+           "jacobi_ms": jac_ms, "assembly_ms": asm_ms,
+           "jacobi_launches": int(launches),
+           "eigenvalue_err_over_budget": ratio,
+           "jacobi_roofline": {"bound": "hbm", "achieved": ach, "peak": 8000.0,
+                               "unit": "GB/s",
+                               "frac": ach / 8000.0 if ach else None,
+                               "bytes_per_solve": bytes_solve}}
+    if not no_cpu:
+        out["cpu_baseline"] = {"value": 1.0 / cpu_s, "unit": "solves/s",
+                               "cores": blas_threads(), "kind": "oracle",
+                               "sample": "one full solve of the same model "
+                                         "(quadrature, assembly, LAPACK eigh)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +340,9 @@ def main():
     ap.add_argument("--outer-M", type=int, default=2048,
                     help="energies of the outer-region propagation leg; "
                          "0 skips it")
+    ap.add_argument("--inner-N", type=int, default=512,
+                    help="sine functions per channel of the inner-region "
+                         "leg (8 channels); 0 skips it")
     ap.add_argument("--photo-M", type=int, default=8192,
                     help="energies of the photoionization leg (B II shape); "
                          "0 skips it")
@@ -414,6 +474,10 @@ def main():
     if args.photo_M > 0:
         photo = photo_leg(native, torch, oracle, workloads, args.steps,
                           args.warmup, args.photo_M)
+    inner_res = None
+    if args.inner_N > 0:
+        inner_res = inner_leg(native, oracle, workloads, max(1, min(args.steps, 2)),
+                              args.inner_N, args.no_cpu)
     ms = head["ms"]
     dom = max(head["kernels"].values(), key=lambda k: k["ms_per_step"])
     roof = dict(dom)
@@ -449,6 +513,7 @@ def main():
         "postproc": post,
         "photoionization": photo,
         "outer_propagation": outer_res,
+        "inner_region": inner_res,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)

@@ -42,7 +42,8 @@ enum rm_status {
   RM_ERR_ARG = 1,      /* invalid argument; nothing enqueued                */
   RM_ERR_NOMEM = 2,    /* device allocation failed                          */
   RM_ERR_HIP = 3,      /* a HIP runtime call failed                         */
-  RM_ERR_NUMERIC = 4,  /* reserved: per-energy trouble goes to status[]     */
+  RM_ERR_NUMERIC = 4,  /* iteration did not converge (rm_inner_region);
+                          per-energy trouble goes to status[] instead      */
   RM_ERR_STATE = 5     /* handle used on the wrong device or after rm_free  */
 };
 
@@ -217,8 +218,10 @@ int rm_channel_functions(rm_sym_t sym, const double *E, int64_t m,
  * (rm_plan_execute graph replays), 4 (the banded product of
  * rm_convolve_gaussian), 5 (the pass over Omega of
  * rm_effective_collision_strengths), 6 (the pass of
- * rm_group_collision_strengths) or 7 (the outer-region propagation of
- * rm_set_propagation), the summed time in milliseconds and the
+ * rm_group_collision_strengths), 7 (the outer-region propagation of
+ * rm_set_propagation), 8 (the Jacobi sweeps of rm_inner_region, one record
+ * per sweep) or 9 (its quadrature tables and Hamiltonian assembly), the
+ * summed time in milliseconds and the
  * number of launches (stage 0 is kept for compatibility and stays empty).
  * Not thread-safe with concurrent sweeps while enabled. */
 int rm_profile(int32_t enable);
@@ -370,6 +373,48 @@ int rm_effective_collision_strengths(const double *E, int64_t M,
 int rm_group_collision_strengths(const double *omega, int64_t M,
                                  int32_t n_target, const int32_t *group,
                                  int32_t n_group, double *out, void *stream);
+
+/* ---- Inner region ----------------------------------------------------
+ * The poles E_k and amplitudes w_ik of Eq. 1 come from the full
+ * diagonalisation of each symmetry's inner-region Hamiltonian (Sec. 2-3:
+ * every eigenpair, ScaLAPACK in the paper).  The atomic Hamiltonians are not
+ * published; rm_inner_region diagonalises a multichannel model of the same
+ * form on [0, a]:
+ *   u_i'' = sum_j [(l_i (l_i + 1)/r^2 - 2z/r + e_i - E) delta_ij + U_ij] u_j,
+ *   U_ij(r) = -depth_ij exp(-(r / range_ij)^2),
+ * in the basis sqrt(2/a) sin(kappa_m r), kappa_m a = (m + 1/2) pi, m <
+ * n_basis, per channel (index i n_basis + m), so u(0) = 0, u'(a) = 0 and the
+ * kinetic part is diag(kappa_m^2); the potential's matrix elements by
+ * n_quad-point Gauss-Legendre quadrature (0: n_basis + 48).  All eigenpairs
+ * by one-sided Jacobi on the device (round-robin column pairs, one wavefront
+ * per pair); w_ik = sqrt2 u_ik(a), the convention of rm_load_poles.
+ *
+ * e_thr [n_chan], l [n_chan], depth and range [n_chan][n_chan] (symmetric,
+ * range > 0): host.  E_pole (host [n_chan n_basis], ascending) and w (host
+ * [n_chan][n_chan n_basis], columns in the order of E_pole; the sign of a
+ * column and the basis of a degenerate eigenspace are arbitrary) are written
+ * by the call, which synchronises `stream` after each sweep; sweeps and
+ * rotations (host, each may be NULL) receive the sweeps taken and the
+ * column-pair rotations applied over all of them.  Memory: about 16 (n_chan
+ * n_basis)^2 bytes of device workspace, allocated and freed by the call.
+ * Errors: RM_ERR_ARG (n_chan < 1, n_basis < 1, n_chan n_basis > 4096, a not
+ * finite and > 0, z < 0, n_quad > 16384, l outside [0, 12], model arrays not
+ * finite / not symmetric, null pointer), RM_ERR_NOMEM, RM_ERR_HIP,
+ * RM_ERR_NUMERIC (no convergence in 40 sweeps; outputs hold the last
+ * iterate). */
+typedef struct {
+  int32_t n_chan;
+  int32_t n_basis;
+  int32_t n_quad;
+  double a;
+  double z;
+  const double *e_thr;
+  const int32_t *l;
+  const double *depth;
+  const double *range;
+} rm_inner_desc;
+int rm_inner_region(const rm_inner_desc *desc, double *E_pole, double *w,
+                    int32_t *sweeps, int64_t *rotations, void *stream);
 
 /* Message for the last non-RM_OK return on this thread ("" if none). */
 const char *rm_last_error(void);

@@ -912,7 +912,7 @@ int rm_profile(int32_t enable) {
 }
 
 int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches) {
-  if (stage < 0 || stage > 7) return fail(RM_ERR_ARG, "stage %d", stage);
+  if (stage < 0 || stage > 9) return fail(RM_ERR_ARG, "stage %d", stage);
   double tot = 0.0;
   int64_t cnt = 0;
   for (auto &r : g_recs) {

@@ -36,7 +36,8 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_photoionization",
             "rm_convolve_gaussian",
             "rm_effective_collision_strengths",
-            "rm_group_collision_strengths", "rm_last_error")
+            "rm_group_collision_strengths", "rm_inner_region",
+            "rm_last_error")
 
 
 class RmError(RuntimeError):
@@ -51,6 +52,14 @@ class PolesDesc(ctypes.Structure):
                 ("a", ctypes.c_double), ("e_thr", ctypes.c_void_p),
                 ("l", ctypes.c_void_p), ("target", ctypes.c_void_p),
                 ("z", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+class InnerDesc(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("n_basis", ctypes.c_int32),
+                ("n_quad", ctypes.c_int32), ("a", ctypes.c_double),
+                ("z", ctypes.c_double), ("e_thr", ctypes.c_void_p),
+                ("l", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("range", ctypes.c_void_p)]
 
 
 class Opts(ctypes.Structure):
@@ -110,6 +119,8 @@ def lib():
                                                        vp, i32, vp, vp]
         L.rm_group_collision_strengths.argtypes = [vp, i64, i32, vp, i32, vp,
                                                    vp]
+        L.rm_inner_region.argtypes = [ctypes.POINTER(InnerDesc), vp, vp, vp,
+                                      vp, vp]
         L.rm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "rm_last_error":
@@ -251,7 +262,8 @@ def rm_channel_functions(sym, E):
 
 
 STAGES = {"chanfn": 0, "polesum": 1, "match": 2, "graph": 3, "convolve": 4,
-          "upsilon": 5, "group": 6, "propagate": 7}
+          "upsilon": 5, "group": 6, "propagate": 7, "jacobi": 8,
+          "assemble": 9}
 
 
 def rm_profile(enable):
@@ -440,6 +452,32 @@ def rm_photoionization(syms, E, e0, opts=None, sigma=None, status=None):
                                     ctypes.byref(o), _ptr(sigma),
                                     _ptr(status), _stream()))
     return sigma, status
+
+
+def rm_inner_region(model, n_basis, n_quad=0):
+    """Poles and amplitudes of the model inner-region Hamiltonian (all
+    eigenpairs on the device).  model: dict with e_thr [n], l [n], z, a,
+    depth [n, n], range [n, n].  Returns (E_pole [n N] ascending, w [n, n N],
+    sweeps, rotations), host arrays and counts."""
+    e = np.ascontiguousarray(model["e_thr"], dtype=np.float64)
+    n = e.size
+    l = np.ascontiguousarray(model["l"], dtype=np.int32)
+    dep = np.ascontiguousarray(model["depth"], dtype=np.float64)
+    rng = np.ascontiguousarray(model["range"], dtype=np.float64)
+    if l.shape != (n,) or dep.shape != (n, n) or rng.shape != (n, n):
+        raise RmError(RM_ERR_ARG, "model arrays must be [n], [n], [n, n], [n, n]")
+    D = n * int(n_basis)
+    E = np.zeros(max(D, 0))
+    w = np.zeros((n, max(D, 0)))
+    sweeps = ctypes.c_int32(0)
+    rot = ctypes.c_int64(0)
+    d = InnerDesc(n, int(n_basis), int(n_quad), float(model["a"]),
+                  float(model["z"]), e.ctypes.data, l.ctypes.data,
+                  dep.ctypes.data, rng.ctypes.data)
+    _check(lib().rm_inner_region(ctypes.byref(d), E.ctypes.data, w.ctypes.data,
+                                 ctypes.byref(sweeps), ctypes.byref(rot),
+                                 _stream()))
+    return E, w, sweeps.value, rot.value
 
 
 def rm_set_propagation(sym, A, n_sec, beta=None):

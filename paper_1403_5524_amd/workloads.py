@@ -177,6 +177,23 @@ def outer_coupling(n, lmax=2, seed=6, scales=(1.0, 4.0)):
     return np.stack(out)
 
 
+def inner_model(n=8, seed=21, a=20.0, z=1.0, lmax=3):
+    """Model inner region of n channels on [0, a]: thresholds ~ U[0, 2]
+    sorted (the first at 0), l ~ U{0..lmax}, a symmetric Gaussian coupling
+    matrix with diagonal depths ~ U[1, 4] Ry, off-diagonal ~ U[0.1, 1] Ry,
+    ranges ~ U[1.5, 4] a0 (symmetrised), drawn in that order from PCG64."""
+    rng = np.random.default_rng(seed)
+    e = np.sort(rng.uniform(0.0, 2.0, n))
+    e[0] = 0.0
+    l = rng.integers(0, lmax + 1, n)
+    off = rng.uniform(0.1, 1.0, (n, n))
+    depth = 0.5 * (off + off.T)
+    depth[np.arange(n), np.arange(n)] = rng.uniform(1.0, 4.0, n)
+    rg = rng.uniform(1.5, 4.0, (n, n))
+    return {"e_thr": e, "l": l, "z": float(z), "a": float(a),
+            "depth": depth, "range": 0.5 * (rg + rg.T)}
+
+
 def tiny(n=3, n_poles=12, M=40, seed=11, pole_lo=-2.0, pole_hi=30.0,
          mesh_lo=0.0, mesh_hi=6.0):
     """Small system for quick checks."""
