@@ -283,11 +283,11 @@ def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
     native.rm_profile(False)
     jac_ms /= steps
     asm_ms /= steps
-    Dp = D + (D & 1)
-    launches = sweeps * (Dp - 1)
-    # per step every column of A is read for the pair dots; a rotated pair
-    # writes its two A columns and reads and writes its two V columns
-    bytes_solve = launches * 8.0 * Dp * Dp + rot * 48.0 * Dp
+    Dp = (D + 31) // 32 * 32              # 16-column blocks, an even number
+    launches = sweeps * (Dp // 16 - 1)    # round-robin steps over the blocks
+    # per step the Gram kernels read every column of A once; a rotated block
+    # pair reads and writes its 32 columns of A and of V
+    bytes_solve = launches * 8.0 * Dp * Dp + rot * 4.0 * 32 * 8 * Dp
     ach = bytes_solve / (jac_ms * 1e-3) / 1e9 if jac_ms else None
     t0 = time.perf_counter()
     Eo, wo = oracle.inner.inner_region(m, n_basis)
@@ -303,7 +303,7 @@ def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
            "value": 1.0 / s_per, "unit": "solves/s", "s_per_solve": s_per,
            "sweeps": int(sweeps), "rotations": int(rot),
            "jacobi_ms": jac_ms, "assembly_ms": asm_ms,
-           "jacobi_launches": int(launches),
+           "jacobi_steps": int(launches),
            "eigenvalue_err_over_budget": ratio,
            "jacobi_roofline": {"bound": "hbm", "achieved": ach, "peak": 8000.0,
                                "unit": "GB/s",

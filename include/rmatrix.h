@@ -386,8 +386,10 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
  * n_basis, per channel (index i n_basis + m), so u(0) = 0, u'(a) = 0 and the
  * kinetic part is diag(kappa_m^2); the potential's matrix elements by
  * n_quad-point Gauss-Legendre quadrature (0: n_basis + 48).  All eigenpairs
- * by one-sided Jacobi on the device (round-robin column pairs, one wavefront
- * per pair); w_ik = sqrt2 u_ik(a), the convention of rm_load_poles.
+ * by blocked one-sided Jacobi on the device (round-robin pairs of 16-column
+ * blocks; each pair's 32 x 32 Gram matrix diagonalised in LDS and its
+ * rotation applied with FP64 MFMA); eigenvalues as Rayleigh quotients;
+ * w_ik = sqrt2 u_ik(a), the convention of rm_load_poles.
  *
  * e_thr [n_chan], l [n_chan], depth and range [n_chan][n_chan] (symmetric,
  * range > 0): host.  E_pole (host [n_chan n_basis], ascending) and w (host
@@ -395,8 +397,8 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
  * column and the basis of a degenerate eigenspace are arbitrary) are written
  * by the call, which synchronises `stream` after each sweep; sweeps and
  * rotations (host, each may be NULL) receive the sweeps taken and the
- * column-pair rotations applied over all of them.  Memory: about 16 (n_chan
- * n_basis)^2 bytes of device workspace, allocated and freed by the call.
+ * number of block-pair rotations applied over all of them.  Memory: about
+ * 16 (n_chan n_basis)^2 bytes of device workspace, allocated and freed by the call.
  * Errors: RM_ERR_ARG (n_chan < 1, n_basis < 1, n_chan n_basis > 4096, a not
  * finite and > 0, z < 0, n_quad > 16384, l outside [0, 12], model arrays not
  * finite / not symmetric, null pointer), RM_ERR_NOMEM, RM_ERR_HIP,

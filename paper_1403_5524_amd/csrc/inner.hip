@@ -11,8 +11,10 @@
 // Gauss-Legendre quadrature; the symmetric eigenproblem by one-sided
 // (Hestenes) Jacobi on H + sigma I (sigma from Gershgorin, so the matrix is
 // positive definite): rotations V make its columns mutually orthogonal, and
-// then column k is (H + sigma I) v_k with v_k an eigenvector.  In each
-// round-robin step every column pair is orthogonalised by one wavefront.  w_ik = sqrt2 sum_m
+// then column k is (H + sigma I) v_k with v_k an eigenvector.  The rotations
+// act on pairs of 16-column blocks (Gram matrix by FP64 MFMA, its 32 x 32
+// eigenproblem in LDS, the block rotation applied by FP64 MFMA), so a sweep
+// reads the matrix nb - 1 times for nb = D / 16 blocks rather than D - 1.  w_ik = sqrt2 sum_m
 // V_(i,m),k phi_m(a) with phi_m(a) = sqrt(2/a) (-1)^m, the convention of
 // R = (1/2a) sum_k w_ik w_jk / (E_k - E).
 #include <algorithm>
@@ -106,57 +108,254 @@ __global__ void inner_init_kernel(double *A, double *V, int D, int Dp,
   V[idx] = (r == c) ? 1.0 : 0.0;
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Blocked one-sided Jacobi.  The Dp columns (Dp a multiple of 32) form
+// nb = Dp / 16 blocks; in round-robin step t every block pair (P, Q) of the
+// circle method ((t, nb - 1) for k = 0, else (t + k, t - k) mod (nb - 1))
+// is handled at once: its 32 columns X give the Gram matrix G = X^T X, the
+// eigenvectors U of G (two-sided Jacobi in LDS) make X U mutually
+// orthogonal, and X <- X U, V <- V U.  Every column pair meets in some block
+// pair each sweep, so a sweep in which no Gram fails the test
+// |G_pq| <= tol sqrt(G_pp G_qq) leaves all columns mutually orthogonal.
+constexpr int BJ_B = 16;        // columns per block
+constexpr int BJ_W = 2 * BJ_B;  // columns per block pair
+constexpr int BJ_CH = 256;      // rows per workgroup (4 waves x 64)
+
+__device__ inline void bj_pair(int nb, int t, int k, int &P, int &Qb) {
+  const int L = nb - 1;
+  if (k == 0) {
+    P = t % L;
+    Qb = L;
+  } else {
+    P = (t + k) % L;
+    Qb = (t - k + L) % L;
+  }
 }
 
-// One round-robin step t of a sweep over Dp (even) columns: pair k of the
-// circle method ((t, Dp - 1) for k = 0, else (t + k, t - k) mod (Dp - 1))
-// is orthogonalised by wavefront k.  Counts the rotations done.
-__global__ __launch_bounds__(256) void inner_jacobi_step_kernel(
-    double *A, double *V, int Dp, int t, double tol, int *rot_count) {
-  const int lane = threadIdx.x & 63;
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= Dp / 2) return;
-  const int L = Dp - 1;
-  int p, q;
-  if (k == 0) {
-    p = t % L;
-    q = L;
+// column of A (or V) at position c in [0, 32) of block pair (P, Qb)
+__device__ inline int bj_col(int P, int Qb, int c) {
+  return c < BJ_B ? P * BJ_B + c : Qb * BJ_B + (c - BJ_B);
+}
+
+// Partial Grams over the rows of chunk blockIdx.y for block pair blockIdx.x:
+// part[(k nchunk + c)][tile][i][j], tiles X_P^T X_P, X_P^T X_Q, X_Q^T X_Q.
+// FP64 MFMA 16x16x4: lane (col, kq) holds rows row0 + 4 kq + u (u < 4) of
+// column col of each block (one 32-byte load each), and the k index of step
+// u is the row row0 + 4 kq + u for both operands.
+__global__ __launch_bounds__(256) void bj_gram_kernel(
+    const double *__restrict__ A, int Dp, int nb, int t, int nchunk,
+    double *__restrict__ part) {
+  __shared__ double red[4][3][256];
+  const int k = blockIdx.x, c = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  int P, Qb;
+  bj_pair(nb, t, k, P, Qb);
+  const double *xp = A + (int64_t)(P * BJ_B + col) * Dp + 4 * kq;
+  const double *xq = A + (int64_t)(Qb * BJ_B + col) * Dp + 4 * kq;
+  d4 gpp = {0.0, 0.0, 0.0, 0.0}, gpq = gpp, gqq = gpp;
+  const int rbeg = c * BJ_CH + wave * 64;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int row0 = rbeg + 16 * g;
+    if (row0 >= Dp) break;
+    const d4 a = *(const d4 *)(xp + row0);
+    const d4 b = *(const d4 *)(xq + row0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      gpp = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], a[u], gpp, 0, 0, 0);
+      gpq = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], gpq, 0, 0, 0);
+      gqq = __builtin_amdgcn_mfma_f64_16x16x4f64(b[u], b[u], gqq, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = (kq + 4 * r) * 16 + col;
+    red[wave][0][e] = gpp[r];
+    red[wave][1][e] = gpq[r];
+    red[wave][2][e] = gqq[r];
+  }
+  __syncthreads();
+  double *out = part + ((int64_t)k * nchunk + c) * 768;
+  for (int e = threadIdx.x; e < 768; e += 256) {
+    const int tile = e >> 8, idx = e & 255;
+    out[e] = (red[0][tile][idx] + red[1][tile][idx]) +
+             (red[2][tile][idx] + red[3][tile][idx]);
+  }
+}
+
+__device__ inline void bj_pair32(int r, int kk, int &p, int &q) {
+  if (kk == 0) {
+    p = r % 31;
+    q = 31;
   } else {
-    p = (t + k) % L;
-    q = (t - k + L) % L;
+    p = (r + kk) % 31;
+    q = (r - kk + 31) % 31;
   }
-  double *ap = A + (int64_t)p * Dp, *aq = A + (int64_t)q * Dp;
-  double al = 0.0, be = 0.0, ga = 0.0;
-  for (int r = lane; r < Dp; r += 64) {
-    const double x = ap[r], y = aq[r];
-    al = fma(x, x, al);
-    be = fma(y, y, be);
-    ga = fma(x, y, ga);
+}
+
+// One workgroup per block pair: sums the partial Grams, and if any column
+// pair fails the orthogonality test, applies one cyclic sweep of two-sided
+// Jacobi to G accumulating U; else marks the pair skipped.  (One sweep per
+// visit of the block pair is cheaper overall than diagonalising G fully:
+// the outer sweeps revisit every pair anyway.)  A round applies 16
+// disjoint rotations J (pair (p, q): column p' = c p - s q, q' = s p + c q);
+// G' = J^T G J maps each 2 x 2 block (rows of pair a, columns of pair b)
+// from its own four entries, so thread a * 16 + b updates one block in
+// place and the rotated pair's off-diagonal is set to zero.  Counts the
+// block pairs rotated.
+__global__ __launch_bounds__(256) void bj_eig_kernel(
+    const double *__restrict__ part, int nchunk, double tol,
+    double *__restrict__ Uout, int *__restrict__ skip, int *__restrict__ cnt) {
+  __shared__ double G[BJ_W][BJ_W + 1];
+  __shared__ double U[BJ_W][BJ_W + 1];
+  __shared__ double cs[16][2];
+  __shared__ int need;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const double *pk = part + (int64_t)k * nchunk * 768;
+  if (tid == 0) need = 0;
+  for (int e = tid; e < 768; e += 256) {
+    double sum = 0.0;
+    for (int c = 0; c < nchunk; ++c) sum += pk[(int64_t)c * 768 + e];
+    const int tile = e >> 8, i = (e & 255) >> 4, j = e & 15;
+    if (tile == 0) {
+      G[i][j] = sum;
+    } else if (tile == 1) {
+      G[i][BJ_B + j] = sum;
+      G[BJ_B + j][i] = sum;
+    } else {
+      G[BJ_B + i][BJ_B + j] = sum;
+    }
   }
-  al = wave_sum(al);
-  be = wave_sum(be);
-  ga = wave_sum(ga);
-  if (!(fabs(ga) > tol * sqrt(al * be))) return;  // already orthogonal
-  // rotation zeroing the off-diagonal of [[al, ga], [ga, be]]
-  const double ze = (be - al) / (2.0 * ga);
-  const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-  const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-  for (int r = lane; r < Dp; r += 64) {
-    const double x = ap[r], y = aq[r];
-    ap[r] = c * x - s * y;
-    aq[r] = s * x + c * y;
+  for (int e = tid; e < BJ_W * BJ_W; e += 256)
+    U[e >> 5][e & 31] = (e >> 5) == (e & 31) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int e = tid; e < BJ_W * BJ_W; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    if (i < j && fabs(G[i][j]) > tol * sqrt(G[i][i] * G[j][j])) need = 1;
   }
-  double *vp = V + (int64_t)p * Dp, *vq = V + (int64_t)q * Dp;
-  for (int r = lane; r < Dp; r += 64) {
-    const double x = vp[r], y = vq[r];
-    vp[r] = c * x - s * y;
-    vq[r] = s * x + c * y;
+  __syncthreads();
+  if (!need) {
+    if (tid == 0) skip[k] = 1;
+    return;
   }
-  if (lane == 0) atomicAdd(rot_count, 1);
+  const int ka = tid >> 4, kb = tid & 15;  // this thread's 2 x 2 block of G
+  {
+    for (int r = 0; r < 31; ++r) {
+      if (tid < 16) {
+        int p, q;
+        bj_pair32(r, tid, p, q);
+        const double al = G[p][p], be = G[q][q], ga = G[p][q];
+        double c = 1.0, s = 0.0;
+        if (fabs(ga) > tol * sqrt(al * be)) {
+          const double ze = (be - al) / (2.0 * ga);
+          const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = c * tt;
+        }
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+      }
+      __syncthreads();
+      {
+        const double ca = cs[ka][0], sa = cs[ka][1];
+        const double cb = cs[kb][0], sb = cs[kb][1];
+        if (sa != 0.0 || sb != 0.0) {
+          int p, q, u, v;
+          bj_pair32(r, ka, p, q);
+          bj_pair32(r, kb, u, v);
+          const double gpu = G[p][u], gpv = G[p][v], gqu = G[q][u], gqv = G[q][v];
+          // columns: (u, v) -> (cb u - sb v, sb u + cb v)
+          const double hpu = cb * gpu - sb * gpv, hpv = sb * gpu + cb * gpv;
+          const double hqu = cb * gqu - sb * gqv, hqv = sb * gqu + cb * gqv;
+          // rows: (p, q) -> (ca p - sa q, sa p + ca q)
+          G[p][u] = ca * hpu - sa * hqu;
+          G[q][u] = sa * hpu + ca * hqu;
+          G[p][v] = ca * hpv - sa * hqv;
+          G[q][v] = sa * hpv + ca * hqv;
+          if (ka == kb && sa != 0.0) {
+            G[p][v] = 0.0;
+            G[q][u] = 0.0;
+          }
+        }
+      }
+      for (int e = tid; e < BJ_W * 16; e += 256) {
+        const int i = e >> 4, kk = e & 15;
+        const double s = cs[kk][1];
+        if (s != 0.0) {
+          const double c = cs[kk][0];
+          int p, q;
+          bj_pair32(r, kk, p, q);
+          const double x = U[i][p], y = U[i][q];
+          U[i][p] = c * x - s * y;
+          U[i][q] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double *uo = Uout + (int64_t)k * BJ_W * BJ_W;
+  for (int e = tid; e < BJ_W * BJ_W; e += 256) uo[e] = U[e >> 5][e & 31];
+  if (tid == 0) {
+    skip[k] = 0;
+    atomicAdd(cnt, 1);
+  }
+}
+
+// X <- X U for the 32 columns of block pair blockIdx.x, in A and in V, over
+// the rows of chunk blockIdx.y (in place: each wave loads its 16-row group
+// of all 32 columns before writing it back).  Computed as Y^T = U^T X^T so
+// that a lane's outputs run down a column: A operand U[4 s + kq][16 it +
+// col], B operand X[row0 + col][position 4 s + kq], output lane r holds
+// Y[row0 + col][position 16 it + kq + 4 r].
+__global__ __launch_bounds__(256) void bj_rotate_kernel(
+    double *A, double *V, int Dp, int nb, int t,
+    const double *__restrict__ Uall, const int *__restrict__ skip) {
+  const int k = blockIdx.x, c = blockIdx.y;
+  if (skip[k]) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  int P, Qb;
+  bj_pair(nb, t, k, P, Qb);
+  const double *Uk = Uall + (int64_t)k * BJ_W * BJ_W;
+  double ua[2][8];
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) ua[it][s] = Uk[(4 * s + kq) * BJ_W + 16 * it + col];
+  int64_t cin[8], cout0[4], cout1[4];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) cin[s] = (int64_t)bj_col(P, Qb, 4 * s + kq) * Dp;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    cout0[r] = (int64_t)bj_col(P, Qb, kq + 4 * r) * Dp;
+    cout1[r] = (int64_t)bj_col(P, Qb, BJ_B + kq + 4 * r) * Dp;
+  }
+  const int rbeg = c * BJ_CH + wave * 64;
+#pragma unroll
+  for (int mat = 0; mat < 2; ++mat) {
+    double *X = mat ? V : A;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int row0 = rbeg + 16 * g;
+      if (row0 >= Dp) break;
+      double xb[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) xb[s] = X[cin[s] + row0 + col];
+      d4 y0 = {0.0, 0.0, 0.0, 0.0}, y1 = y0;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        y0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0][s], xb[s], y0, 0, 0, 0);
+        y1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[1][s], xb[s], y1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        X[cout0[r] + row0 + col] = y0[r];
+        X[cout1[r] + row0 + col] = y1[r];
+      }
+    }
+  }
 }
 
 // Column k after convergence: a_k = (H + sigma I) v_k.  Eigenvalue by the
@@ -265,17 +464,22 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   const int Q = d->n_quad > 0 ? d->n_quad : N + 48;
   if (Q > 16384) return in_fail(RM_ERR_ARG, std::string(fn) + ": n_quad > 16384");
   hipStream_t st = (hipStream_t)stream;
-  const int D = n * N, Dp = D + (D & 1);
+  const int D = n * N, Dp = (D + BJ_W - 1) / BJ_W * BJ_W;  // even block count
+  const int nb = Dp / BJ_B, npair = nb / 2, nchunk = (Dp + BJ_CH - 1) / BJ_CH;
   std::vector<double> rq, wq;
   gauss_legendre(Q, d->a, rq, wq);
   // device: A, V [Dp][Dp]; rq, wq [Q]; model arrays; lam [D]; w [n][D];
-  // Gershgorin bounds [D]; rotation counter
+  // Gershgorin bounds [D]; quadrature tables; partial Grams [npair][nchunk]
+  // [3][16][16]; rotations [npair][32][32]; l [n]; skip flags [npair];
+  // block-pair counter
   const size_t nsq = (size_t)Dp * Dp;
+  const size_t npart = (size_t)npair * nchunk * 768, nu = (size_t)npair * BJ_W * BJ_W;
   const size_t ndbl = 2 * nsq + 2 * (size_t)Q + (size_t)n + 2 * (size_t)n * n +
                       (size_t)D + (size_t)n * D + (size_t)D + (size_t)N * Q +
-                      (size_t)n * n * Q;
+                      (size_t)n * n * Q + npart + nu;
   char *ws = nullptr;
-  const size_t bytes = ndbl * sizeof(double) + (size_t)n * sizeof(int32_t) + 64;
+  const size_t bytes = ndbl * sizeof(double) +
+                       ((size_t)n + (size_t)npair) * sizeof(int32_t) + 64;
   hipError_t e = hipMalloc((void **)&ws, bytes);
   if (e != hipSuccess)
     return in_fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
@@ -284,9 +488,12 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   double *de = dwq + Q, *ddep = de + n, *dran = ddep + (size_t)n * n;
   double *lam = dran + (size_t)n * n, *dw = lam + D, *lb = dw + (size_t)n * D;
   double *phi = lb + D, *wv = phi + (size_t)N * Q;
-  int32_t *dl = (int32_t *)(wv + (size_t)n * n * Q);
-  int *cnt = (int *)(((uintptr_t)(dl + n) + 15) & ~(uintptr_t)15);
+  double *part = wv + (size_t)n * n * Q, *Ub = part + npart;
+  int32_t *dl = (int32_t *)(Ub + nu);
+  int *skip = (int *)(dl + n);
+  int *cnt = (int *)(((uintptr_t)(skip + npair) + 15) & ~(uintptr_t)15);
   int used = 0;
+  bool converged = false;
   int64_t rot_total = 0;
   std::vector<double> hlb(D), hlam(D), hw((size_t)n * D);
   auto hip_ok = [&](hipError_t x) { if (e == hipSuccess) e = x; return e == hipSuccess; };
@@ -328,16 +535,20 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   // sweeps until no pair needs a rotation
   const int max_sweeps = 40;
   // LAPACK's one-sided Jacobi stops at sqrt(m) eps; a few times that covers
-  // the rounding of the wavefront's dot products
+  // the rounding of the Gram entries
   const double tol = 8.0 * std::sqrt((double)Dp) * 2.220446049250313e-16;
   for (int sw = 0; sw < max_sweeps && e == hipSuccess; ++sw) {
     int h_cnt = 0;
     hip_ok(hipMemsetAsync(cnt, 0, sizeof(int), st));
     {
       ProfileScope scope(8, st);
-      for (int t = 0; t < Dp - 1 && e == hipSuccess; ++t) {
-        hipLaunchKernelGGL(inner_jacobi_step_kernel, dim3((unsigned)((Dp / 2 + 3) / 4)),
-                           dim3(256), 0, st, A, V, Dp, t, tol, cnt);
+      for (int t = 0; t < nb - 1 && e == hipSuccess; ++t) {
+        hipLaunchKernelGGL(bj_gram_kernel, dim3(npair, nchunk), dim3(256), 0, st, A, Dp,
+                           nb, t, nchunk, part);
+        hipLaunchKernelGGL(bj_eig_kernel, dim3(npair), dim3(256), 0, st, part, nchunk,
+                           tol, Ub, skip, cnt);
+        hipLaunchKernelGGL(bj_rotate_kernel, dim3(npair, nchunk), dim3(256), 0, st, A, V,
+                           Dp, nb, t, Ub, skip);
         hip_ok(hipGetLastError());
       }
     }
@@ -345,7 +556,10 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
     hip_ok(hipStreamSynchronize(st));
     used = sw + 1;
     rot_total += h_cnt;
-    if (h_cnt == 0) break;
+    if (h_cnt == 0) {
+      converged = true;
+      break;
+    }
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(inner_extract_kernel, dim3((unsigned)((D + 255) / 256)), dim3(256),
@@ -369,7 +583,7 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   }
   if (sweeps) *sweeps = used;
   if (rotations) *rotations = rot_total;
-  if (used >= max_sweeps) return in_fail(RM_ERR_NUMERIC, std::string(fn) + ": Jacobi did not converge in 40 sweeps");
+  if (!converged) return in_fail(RM_ERR_NUMERIC, std::string(fn) + ": Jacobi did not converge in 40 sweeps");
   return RM_OK;
 }
 
