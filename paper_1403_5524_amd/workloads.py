@@ -165,6 +165,19 @@ def photo_b2(M=409600):
     return w, dip, -0.8
 
 
+def photo_ca2(M=6000):
+    """Stand-in for the Ca II photoionization run (Sec. 3, Table 2: 513
+    target states, 1815 coupled channels, Hamiltonian dimension 23,073,
+    6,000 energies): one final symmetry of 1815 channels and 23,073 poles
+    in [-5, 200], thresholds U[0, 2], M energies in [0, 20], seed 7;
+    bound-free dipoles d_k ~ N(0, 1) from seed 107; initial state at
+    e0 = -0.8 Ry.  Returns (workload, dipoles, e0)."""
+    w = single(1815, 23073, -5.0, 200.0, 0.0, 20.0, M, 7,
+               "ca2_photo_n1815_nh23073_m%d" % M)
+    dip = np.random.default_rng(107).normal(size=23073)
+    return w, dip, -0.8
+
+
 def outer_coupling(n, lmax=2, seed=6, scales=(1.0, 4.0)):
     """Long-range multipole coefficients beta [lmax, n, n] (symmetric,
     N(0, scale^2) off and on the diagonal; lam = 1 dipole, 2 quadrupole) for

@@ -150,3 +150,23 @@ def test_photo_b2_shape_sampled(torch_dev, nat):
     log("photo b2 sampled: %.2e" % err)
     assert err < TOL_FP64
     h.free()
+
+
+def test_photo_ca2_shape_sampled(torch_dev, nat):
+    """The Ca II photoionization shape of Table 2 (1815 channels, 23,073
+    poles): 250 energies spread over its 6000-point mesh in one chunk on the
+    GPU, 2 of them against the oracle."""
+    torch, dev = torch_dev
+    w, d, e0 = wl.photo_ca2()
+    h = nat.load_symmetry(w.syms[0])
+    nat.rm_load_dipoles(h, d)
+    Em = w.mesh[::24]
+    E = torch.as_tensor(Em, dtype=torch.float64, device=dev)
+    sig, st = nat.rm_photoionization([h], E, e0)
+    torch.cuda.synchronize()
+    idx = wl.sample_indices(Em.size, 2, seed=3)
+    ref = oracle.photoionization([w.syms[0].as_dict()], [d], Em[idx], e0)
+    err = _err(sig.cpu().numpy()[idx], ref)
+    log("photo ca2 sampled: %.2e" % err)
+    assert err < TOL_FP64
+    h.free()
