@@ -321,6 +321,46 @@ def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
                                "unit": "GB/s",
                                "frac": ach / 8000.0 if ach else None,
                                "bytes_per_solve": bytes_solve}}
+    # eight symmetries of D = 1024 (4 channels x 256), one by one and batched
+    models = [workloads.inner_model(n=4, seed=30 + b) for b in range(8)]
+    native.rm_inner_region_batch(models[:2], 256)
+    t0 = time.perf_counter()
+    for mb in models:
+        native.rm_inner_region(mb, 256)
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    native.rm_inner_region_batch(models, 256)
+    t_bat = time.perf_counter() - t0
+    out["batch_8x_D1024"] = {"s_one_by_one": t_seq, "s_batched": t_bat,
+                             "speedup": t_seq / t_bat}
+    # the D = 4096 model's poles swept like the headline symmetry: 20000
+    # energies in [0, 20] (all 8 channels their own target level)
+    import torch
+    h = native.rm_load_poles(E, w, m["a"], m["e_thr"], m["l"], m["z"], 1.0)
+    Em = workloads.uniform_mesh(0.0, 20.0, 20000)
+    Et = torch.as_tensor(Em, dtype=torch.float64, device="cuda:0")
+    om, st = native.rm_sweep_energies([h], n, Et)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om, st = native.rm_sweep_energies([h], n, Et)
+    torch.cuda.synchronize()
+    t_sw = time.perf_counter() - t0
+    idx = workloads.sample_indices(Em.size, 4, seed=5)
+    sym = {"E_pole": E, "w": w, "a": m["a"], "e_thr": m["e_thr"], "l": m["l"],
+           "z": m["z"], "g": 1.0}
+    ref = oracle.sweep(sym, Em[idx], n_target=n)["omega"]
+    got = om.cpu().numpy()[idx]
+    sw_err = float((np.abs(got - ref).max(axis=1)
+                    / np.maximum(np.abs(ref).max(axis=1), 1e-300)).max())
+    h.free()
+    out["sweep_over_these_poles"] = {"energies": int(Em.size),
+                                     "value": Em.size / t_sw,
+                                     "unit": "energies/s",
+                                     "max_rel_err_omega": sw_err,
+                                     "err_sample": int(idx.size)}
+    note("inner region: 8 x D=1024 %.3f s one by one, %.3f s batched; sweep "
+         "over the D=4096 poles %.0f energies/s (err %.1e)"
+         % (t_seq, t_bat, Em.size / t_sw, sw_err))
     if not no_cpu:
         out["cpu_baseline"] = {"value": 1.0 / cpu_s, "unit": "solves/s",
                                "cores": blas_threads(), "kind": "oracle",

@@ -418,6 +418,23 @@ typedef struct {
 int rm_inner_region(const rm_inner_desc *desc, double *E_pole, double *w,
                     int32_t *sweeps, int64_t *rotations, void *stream);
 
+/* rm_inner_region_batch: the inner-region step for `count` symmetries at
+ * once (the paper diagonalises every symmetry's Hamiltonian).  Item b is
+ * rm_inner_region(&descs[b], E_pole[b], w[b], &sweeps[b], &rotations[b]):
+ * the same kernels and the same results, bit for bit, but the items run
+ * concurrently, each on a stream of its own created on the caller's
+ * current device (default priority) and driven by one of up to 8 host
+ * threads, so that the kernels of small solves overlap.  E_pole and w are
+ * host arrays of `count` host pointers sized as for rm_inner_region;
+ * sweeps and rotations (host [count]) may be NULL.  `stream` is
+ * synchronised first; the call returns when every item is done.
+ * Workspace: each running item holds its own (at most 8 at a time).
+ * Errors: RM_ERR_ARG (count < 0, null pointer), or the first failing
+ * item's error with its index in the message (every item is attempted). */
+int rm_inner_region_batch(const rm_inner_desc *descs, int32_t count,
+                          double *const *E_pole, double *const *w,
+                          int32_t *sweeps, int64_t *rotations, void *stream);
+
 /* Message for the last non-RM_OK return on this thread ("" if none). */
 const char *rm_last_error(void);
 

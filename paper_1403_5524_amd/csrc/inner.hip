@@ -18,9 +18,11 @@
 // V_(i,m),k phi_m(a) with phi_m(a) = sqrt(2/a) (-1)^m, the convention of
 // R = (1/2a) sum_k w_ik w_jk / (E_k - E).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rm_internal.h"
@@ -584,6 +586,55 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   if (sweeps) *sweeps = used;
   if (rotations) *rotations = rot_total;
   if (!converged) return in_fail(RM_ERR_NUMERIC, std::string(fn) + ": Jacobi did not converge in 40 sweeps");
+  return RM_OK;
+}
+
+// Several model Hamiltonians at once: each solve runs on a stream of its
+// own, driven by one of up to 8 host threads (a solve waits on its stream
+// once per sweep), so the small solves' kernels overlap on the device.
+int rm_inner_region_batch(const rm_inner_desc *descs, int32_t count,
+                          double *const *E_pole, double *const *w,
+                          int32_t *sweeps, int64_t *rotations, void *stream) {
+  const char *fn = "rm_inner_region_batch";
+  if (count < 0) return in_fail(RM_ERR_ARG, std::string(fn) + ": count < 0");
+  if (count == 0) return RM_OK;
+  if (!descs || !E_pole || !w) return in_fail(RM_ERR_ARG, std::string(fn) + ": null pointer");
+  for (int b = 0; b < count; ++b)
+    if (!E_pole[b] || !w[b])
+      return in_fail(RM_ERR_ARG, std::string(fn) + ": null output of item " + std::to_string(b));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  // the caller's stream first: work already queued there precedes the solves
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return in_fail(RM_ERR_HIP, std::string(fn) + ": " + hipGetErrorString(e));
+  std::vector<int> codes(count, RM_OK);
+  std::vector<std::string> msgs(count);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    hipStream_t st = nullptr;
+    const bool own = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (int b = next++; b < count; b = next++) {
+      if (!own) {
+        codes[b] = RM_ERR_HIP;
+        msgs[b] = "stream creation failed";
+        continue;
+      }
+      codes[b] = rm_inner_region(&descs[b], E_pole[b], w[b],
+                                 sweeps ? &sweeps[b] : nullptr,
+                                 rotations ? &rotations[b] : nullptr, st);
+      if (codes[b] != RM_OK) msgs[b] = rm_last_error();
+    }
+    if (own) (void)hipStreamDestroy(st);
+  };
+  const int nt = std::min<int>(count, 8);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  for (auto &t : pool) t.join();
+  if (next.load() < count) return in_fail(RM_ERR_HIP, std::string(fn) + ": hipSetDevice failed");
+  for (int b = 0; b < count; ++b)
+    if (codes[b] != RM_OK)
+      return in_fail(codes[b], std::string(fn) + ": item " + std::to_string(b) + ": " + msgs[b]);
   return RM_OK;
 }
 

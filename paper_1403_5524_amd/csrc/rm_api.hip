@@ -286,6 +286,7 @@ struct StageRec {
 };
 static bool g_prof = false;
 static std::vector<StageRec> g_recs;
+static std::mutex g_recs_mu;  // batched inner-region solves record from threads
 
 struct StageTimer {
   hipEvent_t end_ = nullptr;
@@ -301,6 +302,7 @@ struct StageTimer {
     }
     (void)hipEventRecord(r.beg, st);
     end_ = r.end;
+    std::lock_guard<std::mutex> lk(g_recs_mu);
     g_recs.push_back(r);
   }
   ~StageTimer() {
@@ -318,6 +320,7 @@ ProfileScope::ProfileScope(int stage, hipStream_t st) : st_(st) {
   }
   (void)hipEventRecord(r.beg, st);
   end_ = r.end;
+  std::lock_guard<std::mutex> lk(g_recs_mu);
   g_recs.push_back(r);
 }
 
@@ -326,6 +329,7 @@ ProfileScope::~ProfileScope() {
 }
 
 static void clear_recs() {
+  std::lock_guard<std::mutex> lk(g_recs_mu);
   for (auto &r : g_recs) {
     (void)hipEventDestroy(r.beg);
     (void)hipEventDestroy(r.end);
@@ -915,6 +919,7 @@ int rm_profile_query(int32_t stage, double *total_ms, int64_t *launches) {
   if (stage < 0 || stage > 9) return fail(RM_ERR_ARG, "stage %d", stage);
   double tot = 0.0;
   int64_t cnt = 0;
+  std::lock_guard<std::mutex> lk(g_recs_mu);
   for (auto &r : g_recs) {
     if (r.stage != stage) continue;
     float ms = 0.0f;

@@ -37,7 +37,7 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_convolve_gaussian",
             "rm_effective_collision_strengths",
             "rm_group_collision_strengths", "rm_inner_region",
-            "rm_last_error")
+            "rm_inner_region_batch", "rm_last_error")
 
 
 class RmError(RuntimeError):
@@ -121,6 +121,8 @@ def lib():
                                                    vp]
         L.rm_inner_region.argtypes = [ctypes.POINTER(InnerDesc), vp, vp, vp,
                                       vp, vp]
+        L.rm_inner_region_batch.argtypes = [ctypes.POINTER(InnerDesc), i32,
+                                            vp, vp, vp, vp, vp]
         L.rm_last_error.restype = ctypes.c_char_p
         for name in EXPORTED:
             if name != "rm_last_error":
@@ -454,11 +456,8 @@ def rm_photoionization(syms, E, e0, opts=None, sigma=None, status=None):
     return sigma, status
 
 
-def rm_inner_region(model, n_basis, n_quad=0):
-    """Poles and amplitudes of the model inner-region Hamiltonian (all
-    eigenpairs on the device).  model: dict with e_thr [n], l [n], z, a,
-    depth [n, n], range [n, n].  Returns (E_pole [n N] ascending, w [n, n N],
-    sweeps, rotations), host arrays and counts."""
+def _inner_desc(model, n_basis, n_quad):
+    """(InnerDesc, kept arrays, n) for one model dict."""
     e = np.ascontiguousarray(model["e_thr"], dtype=np.float64)
     n = e.size
     l = np.ascontiguousarray(model["l"], dtype=np.int32)
@@ -466,18 +465,53 @@ def rm_inner_region(model, n_basis, n_quad=0):
     rng = np.ascontiguousarray(model["range"], dtype=np.float64)
     if l.shape != (n,) or dep.shape != (n, n) or rng.shape != (n, n):
         raise RmError(RM_ERR_ARG, "model arrays must be [n], [n], [n, n], [n, n]")
+    d = InnerDesc(n, int(n_basis), int(n_quad), float(model["a"]),
+                  float(model["z"]), e.ctypes.data, l.ctypes.data,
+                  dep.ctypes.data, rng.ctypes.data)
+    return d, (e, l, dep, rng), n
+
+
+def rm_inner_region(model, n_basis, n_quad=0):
+    """Poles and amplitudes of the model inner-region Hamiltonian (all
+    eigenpairs on the device).  model: dict with e_thr [n], l [n], z, a,
+    depth [n, n], range [n, n].  Returns (E_pole [n N] ascending, w [n, n N],
+    sweeps, rotations), host arrays and counts."""
+    d, keep, n = _inner_desc(model, n_basis, n_quad)
     D = n * int(n_basis)
     E = np.zeros(max(D, 0))
     w = np.zeros((n, max(D, 0)))
     sweeps = ctypes.c_int32(0)
     rot = ctypes.c_int64(0)
-    d = InnerDesc(n, int(n_basis), int(n_quad), float(model["a"]),
-                  float(model["z"]), e.ctypes.data, l.ctypes.data,
-                  dep.ctypes.data, rng.ctypes.data)
     _check(lib().rm_inner_region(ctypes.byref(d), E.ctypes.data, w.ctypes.data,
                                  ctypes.byref(sweeps), ctypes.byref(rot),
                                  _stream()))
     return E, w, sweeps.value, rot.value
+
+
+def rm_inner_region_batch(models, n_basis, n_quad=None):
+    """rm_inner_region for several models at once (concurrent on the
+    device).  n_basis (and n_quad): one value or one per model.  Returns a
+    list of (E_pole, w, sweeps, rotations)."""
+    k = len(models)
+    nb = list(n_basis) if hasattr(n_basis, "__len__") else [n_basis] * k
+    nq = (list(n_quad) if hasattr(n_quad, "__len__")
+          else [n_quad or 0] * k)
+    descs = (InnerDesc * max(k, 1))()
+    keep, Es, ws = [], [], []
+    for b, m in enumerate(models):
+        d, arrs, n = _inner_desc(m, nb[b], nq[b])
+        descs[b] = d
+        keep.append(arrs)
+        D = n * int(nb[b])
+        Es.append(np.zeros(max(D, 0)))
+        ws.append(np.zeros((n, max(D, 0))))
+    pE = (ctypes.c_void_p * max(k, 1))(*[E.ctypes.data for E in Es])
+    pw = (ctypes.c_void_p * max(k, 1))(*[w.ctypes.data for w in ws])
+    sw = np.zeros(max(k, 1), dtype=np.int32)
+    rot = np.zeros(max(k, 1), dtype=np.int64)
+    _check(lib().rm_inner_region_batch(descs, k, pE, pw, sw.ctypes.data,
+                                       rot.ctypes.data, _stream()))
+    return [(Es[b], ws[b], int(sw[b]), int(rot[b])) for b in range(k)]
 
 
 def rm_set_propagation(sym, A, n_sec, beta=None):

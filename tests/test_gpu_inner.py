@@ -173,3 +173,32 @@ def test_argument_errors(nat):
         nat.rm_inner_region(dict(good, a=0.0), 8)
     with pytest.raises(nat.RmError):
         nat.rm_inner_region(good, 0)
+
+
+def test_batch_matches_single_solves(nat):
+    """Ten models (more than the 8 worker threads; D from 1 to 1024, one
+    odd) through rm_inner_region_batch give bit for bit what rm_inner_region
+    gives for each: the same kernels on the same inputs."""
+    shapes = [(1, 1), (2, 40), (3, 15), (4, 256), (2, 64), (5, 13), (1, 300),
+              (3, 100), (2, 512), (4, 32)]
+    models = [_random_model(n, 40 + b) for b, (n, N) in enumerate(shapes)]
+    Ns = [N for _, N in shapes]
+    t0 = time.perf_counter()
+    out = nat.rm_inner_region_batch(models, Ns)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    single = [nat.rm_inner_region(m, N) for m, N in zip(models, Ns)]
+    ts = time.perf_counter() - t0
+    log("batch of %d: %.3f s, one by one %.3f s" % (len(models), tb, ts))
+    for (Eb, wb, sb, rb), (Es, ws, ss, rs) in zip(out, single):
+        assert np.array_equal(Eb, Es) and np.array_equal(wb, ws)
+        assert sb == ss and rb == rs
+
+
+def test_batch_reports_the_failing_item(nat):
+    good = _random_model(2, 1)
+    bad = dict(good, depth=np.array([[1.0, 0.2], [0.3, 1.0]]))
+    with pytest.raises(nat.RmError) as ex:
+        nat.rm_inner_region_batch([good, bad, good], 16)
+    assert ex.value.code == nat.RM_ERR_ARG and "item 1" in str(ex.value)
+    assert nat.rm_inner_region_batch([], 16) == []
