@@ -36,9 +36,12 @@ static int in_fail(int code, const std::string &msg) {
   return code;
 }
 
-// Tables of the quadrature: phi[m][q] = sqrt(2/a) sin(kappa_m r_q) and
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Tables of the quadrature, Qp = Q rounded up to a multiple of 4 with zero
+// entries beyond Q: phi[m][q] = sqrt(2/a) sin(kappa_m r_q) and
 // wv[i][j][q] = w_q W_ij(r_q) (W without E).
-__global__ void inner_tables_kernel(int n, int N, int Q, double a, double z,
+__global__ void inner_tables_kernel(int n, int N, int Q, int Qp, double a, double z,
                                     const double *__restrict__ rq,
                                     const double *__restrict__ wq,
                                     const double *__restrict__ e_thr,
@@ -48,13 +51,17 @@ __global__ void inner_tables_kernel(int n, int N, int Q, double a, double z,
                                     double *__restrict__ phi,
                                     double *__restrict__ wv) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nphi = (int64_t)N * Q, nw = (int64_t)n * n * Q;
+  const int64_t nphi = (int64_t)N * Qp, nw = (int64_t)n * n * Qp;
   if (idx < nphi) {
-    const int m = (int)(idx / Q), q = (int)(idx % Q);
-    phi[idx] = sqrt(2.0 / a) * sin((m + 0.5) * M_PI / a * rq[q]);
+    const int m = (int)(idx / Qp), q = (int)(idx % Qp);
+    phi[idx] = q < Q ? sqrt(2.0 / a) * sin((m + 0.5) * M_PI / a * rq[q]) : 0.0;
   } else if (idx < nphi + nw) {
     const int64_t t = idx - nphi;
-    const int ij = (int)(t / Q), q = (int)(t % Q);
+    const int ij = (int)(t / Qp), q = (int)(t % Qp);
+    if (q >= Q) {
+      wv[t] = 0.0;
+      return;
+    }
     const int i = ij / n, j = ij % n;
     const double r = rq[q], x = r / range[ij];
     double v = -depth[ij] * exp(-x * x);
@@ -64,28 +71,62 @@ __global__ void inner_tables_kernel(int n, int N, int Q, double a, double z,
 }
 
 // H[p][p'] (column-major, leading dimension ld) for p = i N + m:
-// kappa_m^2 delta + sum_q phi_m(r_q) w_q W_ij(r_q) phi_m'(r_q).
-__global__ void inner_assemble_kernel(int n, int N, int Q, double a,
-                                      const double *__restrict__ phi,
-                                      const double *__restrict__ wv,
-                                      double *__restrict__ H, int ld) {
-  const int64_t D = (int64_t)n * N;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= D * D) return;
-  const int64_t col = idx / D, row = idx % D;
-  if (row < col) return;  // lower triangle, mirrored below
-  const int i = (int)(row / N), m = (int)(row % N);
-  const int j = (int)(col / N), mp = (int)(col % N);
-  const double *pm = phi + (int64_t)m * Q, *pp = phi + (int64_t)mp * Q;
-  const double *w = wv + (int64_t)(i * n + j) * Q;
-  double acc = 0.0;
-  for (int q = 0; q < Q; ++q) acc = fma(pm[q] * pp[q], w[q], acc);
-  if (row == col) {
-    const double km = (m + 0.5) * M_PI / a;
-    acc += km * km;
+// kappa_m^2 delta + sum_q phi_m(r_q) w_q W_ij(r_q) phi_m'(r_q), i.e. the
+// block (i, j) is Phi diag(wv_ij) Phi^T, a product on the FP64 matrix cores.
+// One wavefront per 32 x 32 tile (block pair (i, j) = (blockIdx.x / n,
+// blockIdx.x % n), tile row blockIdx.y, tile column blockIdx.z); only the
+// lower triangle of H
+// is computed (blocks i > j whole, the diagonal blocks' tiles tr >= tc, and
+// in those only row >= column), each value written to both halves so that H
+// is exactly symmetric.  MFMA 16x16x4: lane (col, kq) holds phi[m0 + col]
+// [q0 + kq] (times wv for the A operand), k = the quadrature node.
+__global__ __launch_bounds__(64) void inner_assemble_kernel(
+    int n, int N, int Qp, double a, const double *__restrict__ phi,
+    const double *__restrict__ wv, double *__restrict__ H, int ld) {
+  const int tr = blockIdx.y, tc = blockIdx.z;
+  const int i = blockIdx.x / n, j = blockIdx.x % n;
+  if (j > i || (i == j && tc > tr)) return;
+  const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
+  const int m0 = tr * 32, c0 = tc * 32;
+  // rows beyond N read row N - 1 and are masked out
+  const int ra0 = min(m0 + col, N - 1), ra1 = min(m0 + 16 + col, N - 1);
+  const int rb0 = min(c0 + col, N - 1), rb1 = min(c0 + 16 + col, N - 1);
+  const double *pa0 = phi + (int64_t)ra0 * Qp + kq, *pa1 = phi + (int64_t)ra1 * Qp + kq;
+  const double *pb0 = phi + (int64_t)rb0 * Qp + kq, *pb1 = phi + (int64_t)rb1 * Qp + kq;
+  const double *pw = wv + (int64_t)(i * n + j) * Qp + kq;
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q0 = 0; q0 < Qp; q0 += 4) {
+    const double wq = pw[q0];
+    const double a0 = pa0[q0] * wq, a1 = pa1[q0] * wq;
+    const double b0 = pb0[q0], b1 = pb1[q0];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
-  H[col * ld + row] = acc;
-  H[row * ld + col] = acc;
+  // output lane r: row m0 + 16 x + kq + 4 r, column c0 + 16 y + col
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 16 * x + kq + 4 * r, mp = c0 + 16 * y + col;
+        if (m >= N || mp >= N) continue;
+        const int64_t row = (int64_t)i * N + m, cl = (int64_t)j * N + mp;
+        if (row < cl) continue;
+        double v = acc[x][y][r];
+        if (row == cl) {
+          const double km = (m + 0.5) * M_PI / a;
+          v += km * km;
+        }
+        H[cl * ld + row] = v;
+        H[row * ld + cl] = v;
+      }
 }
 
 // Row-wise Gershgorin lower bounds H_rr - sum_{c != r} |H_rc|.
@@ -109,8 +150,6 @@ __global__ void inner_init_kernel(double *A, double *V, int D, int Dp,
   else if (r == c) A[idx] += sigma;
   V[idx] = (r == c) ? 1.0 : 0.0;
 }
-
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Blocked one-sided Jacobi.  The Dp columns (Dp a multiple of 32) form
 // nb = Dp / 16 blocks; in round-robin step t every block pair (P, Q) of the
@@ -476,9 +515,10 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   // block-pair counter
   const size_t nsq = (size_t)Dp * Dp;
   const size_t npart = (size_t)npair * nchunk * 768, nu = (size_t)npair * BJ_W * BJ_W;
+  const int Qp = (Q + 3) / 4 * 4;
   const size_t ndbl = 2 * nsq + 2 * (size_t)Q + (size_t)n + 2 * (size_t)n * n +
-                      (size_t)D + (size_t)n * D + (size_t)D + (size_t)N * Q +
-                      (size_t)n * n * Q + npart + nu;
+                      (size_t)D + (size_t)n * D + (size_t)D + (size_t)N * Qp +
+                      (size_t)n * n * Qp + npart + nu;
   char *ws = nullptr;
   const size_t bytes = ndbl * sizeof(double) +
                        ((size_t)n + (size_t)npair) * sizeof(int32_t) + 64;
@@ -489,8 +529,8 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   double *A = (double *)ws, *V = A + nsq, *drq = V + nsq, *dwq = drq + Q;
   double *de = dwq + Q, *ddep = de + n, *dran = ddep + (size_t)n * n;
   double *lam = dran + (size_t)n * n, *dw = lam + D, *lb = dw + (size_t)n * D;
-  double *phi = lb + D, *wv = phi + (size_t)N * Q;
-  double *part = wv + (size_t)n * n * Q, *Ub = part + npart;
+  double *phi = lb + D, *wv = phi + (size_t)N * Qp;
+  double *part = wv + (size_t)n * n * Qp, *Ub = part + npart;
   int32_t *dl = (int32_t *)(Ub + nu);
   int *skip = (int *)(dl + n);
   int *cnt = (int *)(((uintptr_t)(skip + npair) + 15) & ~(uintptr_t)15);
@@ -507,15 +547,15 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   hip_ok(hipMemcpyAsync(dl, d->l, n * sizeof(int32_t), hipMemcpyHostToDevice, st));
   ProfileScope *asm_scope = new ProfileScope(9, st);
   if (e == hipSuccess) {
-    const int64_t nt = (int64_t)N * Q + (int64_t)n * n * Q;
+    const int64_t nt = (int64_t)N * Qp + (int64_t)n * n * Qp;
     hipLaunchKernelGGL(inner_tables_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256),
-                       0, st, n, N, Q, d->a, d->z, drq, dwq, de, dl, ddep, dran, phi, wv);
+                       0, st, n, N, Q, Qp, d->a, d->z, drq, dwq, de, dl, ddep, dran, phi, wv);
     hip_ok(hipGetLastError());
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(inner_assemble_kernel,
-                       dim3((unsigned)(((int64_t)D * D + 255) / 256)), dim3(256), 0, st,
-                       n, N, Q, d->a, phi, wv, A, Dp);
+    const unsigned nt32 = (unsigned)((N + 31) / 32);
+    hipLaunchKernelGGL(inner_assemble_kernel, dim3((unsigned)(n * n), nt32, nt32), dim3(64),
+                       0, st, n, N, Qp, d->a, phi, wv, A, Dp);
     hip_ok(hipGetLastError());
   }
   if (e == hipSuccess) {
