@@ -5,15 +5,15 @@ The paper's sweeps need millions of energies to resolve narrow resonances
 kernels (rm_mlp_*), predicts from cheap per-window features of a symmetry
 how much structure Omega(E) has in each energy window; rm_mesh_from_density
 turns the prediction into an adaptive mesh, and the uniform fine mesh swept
-with the plain (FP64) method is the judge.
+with the plain (FP64) method is the reference.
 
 Pipeline (all arrays for the sweep and the network live on the GPU):
   features(sym)            host: pole counts, amplitude norms, thresholds
-  judge = sweep(uniform)   rm_sweep_energies over a uniform fine mesh
-  labels = log curvature of Omega per window (from the judge)
+  fine = sweep(uniform)   rm_sweep_energies over a uniform fine mesh
+  labels = log curvature of Omega per window (from the fine sweep)
   train                    rm_mlp_grad + rm_mlp_adam_step
   density = 10**mlp(features) -> rm_mesh_from_density -> adaptive mesh
-  evaluate                 integrated Omega per transition vs the judge,
+  evaluate                 integrated Omega per transition vs the fine sweep,
                            missed narrow resonances
 """
 import math
@@ -75,7 +75,7 @@ def window_features(sym, lo, hi, nw):
     return f.astype(np.float32)
 
 
-class Judge:
+class FineSweep:
     """Per-transition integrals and per-window variation and curvature of a
     swept mesh."""
 
@@ -92,7 +92,7 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
                     opts=None):
     """Sweep a mesh (device float64, ascending) chunk by chunk.
 
-    Returns a Judge: trapezoid integrals of every Omega(t, t') over [lo, hi]
+    Returns a FineSweep: trapezoid integrals of every Omega(t, t') over [lo, hi]
     (end segments held constant), and, when nw is given, the total variation
     of sum_pairs Omega in each of nw windows and the largest second
     difference of it there (on a uniform mesh, proportional to the
@@ -134,7 +134,7 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
         del om
     integ += prev_om * (hi - prev_E)
     torch.cuda.synchronize()
-    return Judge(integ.cpu().numpy(), var.cpu().numpy() if nw else None,
+    return FineSweep(integ.cpu().numpy(), var.cpu().numpy() if nw else None,
                  float(integ.sum().item()), M,
                  curv if nw else None)
 
@@ -214,20 +214,20 @@ def missed_resonances(E, truth, min_width):
     return miss, tot
 
 
-def integrated_error(test, judge, rel_floor=1e-6):
+def integrated_error(test, fine, rel_floor=1e-6):
     """Max and mean relative error of per-transition integrals (transitions
     with integral above rel_floor times the largest)."""
-    J = judge.integrals
+    J = fine.integrals
     keep = np.abs(J) > rel_floor * np.abs(J).max()
     rel = np.abs(test.integrals[keep] - J[keep]) / np.abs(J[keep])
     return float(rel.max()), float(rel.mean())
 
 
 def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
-                   lo=0.0, hi=20.0, M_judge=1000000, M_adapt=100000,
+                   lo=0.0, hi=20.0, M_fine=1000000, M_adapt=100000,
                    nw=4096, steps=1500, log=print, label="curvature"):
     """Train on train_seeds, evaluate uniform / heuristic / learned meshes of
-    M_adapt points on test_seed against the M_judge uniform judge.
+    M_adapt points on test_seed against the M_fine uniform fine mesh.
 
     label "curvature" (default): the network learns log10 of each window's
     largest second difference of sum Omega (relative to the median window)
@@ -242,9 +242,9 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
     for s in train_seeds:
         sym, truth, spec = wl.narrow_resonance_system(
             s, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
-            mesh_hi=hi, M_judge=M_judge)
+            mesh_hi=hi, M_fine=M_fine)
         h = native.load_symmetry(sym)
-        E = torch.as_tensor(wl.uniform_mesh(lo, hi, M_judge), device=dev)
+        E = torch.as_tensor(wl.uniform_mesh(lo, hi, M_fine), device=dev)
         j = sweep_integrals([h], n, E, lo, hi, nw=nw)
         feats.append(window_features(sym, lo, hi, nw))
         if label == "curvature":   # a few sharp peaks dominate its mean
@@ -255,7 +255,7 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
             % (labels[-1].min(), np.median(labels[-1]), labels[-1].max(),
                int((~np.isfinite(labels[-1])).sum())))
         h.free()
-        log("train system %d swept (%d energies)" % (s, M_judge))
+        log("train system %d swept (%d energies)" % (s, M_fine))
     X = np.concatenate(feats)
     y = np.concatenate(labels)
     norm = Normaliser(X)
@@ -263,10 +263,10 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
 
     sym, truth, spec = wl.narrow_resonance_system(
         test_seed, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
-        mesh_hi=hi, M_judge=M_judge)
+        mesh_hi=hi, M_fine=M_fine)
     h = native.load_symmetry(sym)
-    Ej = torch.as_tensor(wl.uniform_mesh(lo, hi, M_judge), device=dev)
-    judge = sweep_integrals([h], n, Ej, lo, hi, nw=nw)
+    Ej = torch.as_tensor(wl.uniform_mesh(lo, hi, M_fine), device=dev)
+    fine = sweep_integrals([h], n, Ej, lo, hi, nw=nw)
     Xt = torch.as_tensor(norm(window_features(sym, lo, hi, nw)), device=dev)
     pred = mlp.forward(Xt)
     meshes = {
@@ -277,12 +277,12 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
         "learned": mesh_from_log_density(
             pred, lo, hi, M_adapt, alpha=0.5 if label == "curvature" else 1.0),
     }
-    min_w = 2.0 * (hi - lo) / M_judge
-    out = {"train_loss": hist, "judge_points": M_judge, "points": M_adapt,
+    min_w = 2.0 * (hi - lo) / M_fine
+    out = {"train_loss": hist, "fine_points": M_fine, "points": M_adapt,
            "label": label}
     for name, E in meshes.items():
         r = sweep_integrals([h], n, E, lo, hi)
-        mx, mean = integrated_error(r, judge)
+        mx, mean = integrated_error(r, fine)
         miss, tot = missed_resonances(E.cpu().numpy(), truth, min_w)
         out[name] = {"int_err_max": mx, "int_err_mean": mean,
                      "missed": miss, "resonances": tot}

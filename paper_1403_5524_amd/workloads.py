@@ -222,7 +222,7 @@ def sample_indices(M, count, seed=0):
 
 def narrow_resonance_system(seed, n=200, n_poles=8000, n_narrow=50,
                             pole_lo=-5.0, pole_hi=200.0, mesh_lo=0.0,
-                            mesh_hi=20.0, M_judge=1000000, width_lo=1e-5,
+                            mesh_hi=20.0, M_fine=1000000, width_lo=1e-5,
                             width_hi=1e-3):
     """C2-style symmetry plus n_narrow injected weakly coupled poles.
 
@@ -230,10 +230,10 @@ def narrow_resonance_system(seed, n=200, n_poles=8000, n_narrow=50,
     with amplitude vector c u (u a random unit vector).  c^2 is drawn so that
     a crude width proxy c^2 * mean_i sqrt(E_r - e_i)_+ lands log-uniformly in
     [width_lo, width_hi]; the nominal (E_r, proxy width) pairs are returned
-    as the truth list.  Poles and thresholds avoid the judge mesh by 1e-9.
+    as the truth list.  Poles and thresholds avoid the fine mesh by 1e-9.
     """
     rng = np.random.default_rng(seed)
-    spec = (mesh_lo, mesh_hi, M_judge)
+    spec = (mesh_lo, mesh_hi, M_fine)
     base = random_symmetry(rng, n, n_poles, pole_lo, pole_hi, mesh=spec)
 
     def pos(k):

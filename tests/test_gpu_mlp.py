@@ -87,12 +87,12 @@ def test_mesh_from_density_matches_inverse_cdf(env):
 def test_learned_mesh_gains_over_uniform(env):
     """Small narrow-resonance systems: at the same point budget the learned
     mesh misses fewer narrow resonances than the uniform one and integrates
-    Omega closer to the fine uniform judge (the method without the network
+    Omega closer to the fine uniform mesh (the method without the network
     is the uniform mesh)."""
     from paper_1403_5524_amd.adaptive import run_experiment
     res = run_experiment(train_seeds=[1000, 1001, 1002], test_seed=3000,
                          n=32, n_poles=1280, n_narrow=24, lo=0.0, hi=10.0,
-                         M_judge=200000, M_adapt=20000, nw=1024, steps=800,
+                         M_fine=200000, M_adapt=20000, nw=1024, steps=800,
                          log=log)
     u, h, m = res["uniform"], res["heuristic"], res["learned"]
     assert m["missed"] < u["missed"]
