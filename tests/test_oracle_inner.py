@@ -97,3 +97,19 @@ def test_quadrature_nodes_relative_accuracy(Q, nodes):
             wk = 2 / ((1 - xk * xk) * dp * dp)
             assert abs(float((r[k] - rk) / rk)) < 1e-14
             assert abs(float((w[k] - wk) / wk)) < 1e-14
+
+
+def test_pure_coulomb_gives_the_hydrogen_levels():
+    """z = 1 and no short-range potential: the lowest poles in a box of
+    a = 40 a0 are the hydrogenic levels -z^2/n^2 Ry (1s, 2s; 2p, 3p), the
+    box and the 1/r cusp moving them by less than 2e-5 at N = 800 (l = 0)
+    and 400 (l = 1); the 1s error falls as N^-3 (ratio ~8 per doubling)."""
+    def levels(l, N):
+        m = _model(1, [0.0], [l], 1.0, 40.0, [[0.0]], [[1.0]])
+        return inner.inner_region(m, N, Q=2 * N + 100)[0]
+    E400, E800 = levels(0, 400), levels(0, 800)
+    assert np.abs(E800[:2] - np.array([-1.0, -0.25])).max() < 2e-5
+    r = (E400[0] + 1.0) / (E800[0] + 1.0)
+    assert 6.0 < r < 10.0
+    Ep = levels(1, 400)
+    assert np.abs(Ep[:2] - np.array([-0.25, -1.0 / 9.0])).max() < 5e-6
