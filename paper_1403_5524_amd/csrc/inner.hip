@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void bj_eig_kernel(
   __syncthreads();
   for (int e = tid; e < BJ_W * BJ_W; e += 256) {
     const int i = e >> 5, j = e & 31;
-    if (i < j && fabs(G[i][j]) > tol * sqrt(G[i][i] * G[j][j])) need = 1;
+    if (i < j && G[i][j] * G[i][j] > tol * tol * (G[i][i] * G[j][j])) need = 1;
   }
   __syncthreads();
   if (!need) {
@@ -289,10 +289,14 @@ __global__ __launch_bounds__(256) void bj_eig_kernel(
         bj_pair32(r, tid, p, q);
         const double al = G[p][p], be = G[q][q], ga = G[p][q];
         double c = 1.0, s = 0.0;
-        if (fabs(ga) > tol * sqrt(al * be)) {
-          const double ze = (be - al) / (2.0 * ga);
-          const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-          c = 1.0 / sqrt(1.0 + tt * tt);
+        if (ga * ga > tol * tol * (al * be)) {
+          // the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = d / (2 ga),
+          // as sign(d) 2 ga / (|d| + sqrt(d^2 + 4 ga^2)): one square root
+          // and one division
+          const double d = be - al;
+          const double tt = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) /
+                            (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
+          c = rsqrt(1.0 + tt * tt);
           s = c * tt;
         }
         cs[tid][0] = c;
