@@ -33,15 +33,21 @@ struct F64Smem {  // two stages: one feeds the MFMAs while the next fills
   double Ds[2][PS_EG][PS_KC];
 };
 
-__device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
-                            const double *__restrict__ E, int m,
-                            double *__restrict__ Rbase, int64_t estride,
-                            int ld, F64Smem &sm) {
+// One work item: tile pair (I, J), J >= I, for PS_EG energies.  MASK bit
+// 2 a + b says whether the 16 x 16 output block (a, b) of the 32 x 32 tile
+// holds any element that is kept (row and column below n, row <= column on
+// a diagonal tile); the others are never formed.  Diagonal tiles are
+// exactly the masks without block (1, 0).
+template <int MASK>
+__device__ void ps_f64_item_m(const SymDev &S, int I, int J, int grp,
+                              const double *__restrict__ E, int m,
+                              double *__restrict__ Rbase, int64_t estride,
+                              int ld, F64Smem &sm) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int e0 = grp * PS_EG;
-  const bool diag = (I == J);
+  constexpr bool diag = !(MASK & 4);
   const int n_pad = S.n_pad;
 
   const int ld_k = tid >> 3;       // staging: 8 threads per pole row
@@ -123,10 +129,14 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
       for (int e = 0; e < PS_EW; ++e) {
         const double dd = Ds[wave * PS_EW + e][kr];
         const double sa0 = a0 * dd, sa1 = a1 * dd;
-        acc[e][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa0, b0, acc[e][0][0], 0, 0, 0);
-        acc[e][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa0, b1, acc[e][0][1], 0, 0, 0);
-        acc[e][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa1, b0, acc[e][1][0], 0, 0, 0);
-        acc[e][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa1, b1, acc[e][1][1], 0, 0, 0);
+        if constexpr (MASK & 1)
+          acc[e][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa0, b0, acc[e][0][0], 0, 0, 0);
+        if constexpr (MASK & 2)
+          acc[e][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa0, b1, acc[e][0][1], 0, 0, 0);
+        if constexpr (MASK & 4)
+          acc[e][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa1, b0, acc[e][1][0], 0, 0, 0);
+        if constexpr (MASK & 8)
+          acc[e][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa1, b1, acc[e][1][1], 0, 0, 0);
       }
     }
     // the next chunk (already in registers) into the other buffer, then
@@ -153,6 +163,7 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          if (!(MASK & (1 << (2 * a + b)))) continue;  // compile-time
           const int gi = I * PS_T + a * 16 + kq + 4 * r;
           const int gj = J * PS_T + b * 16 + col;
           // diagonal tiles: the upper triangle is mirrored so R is exactly
@@ -163,6 +174,24 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
             Re[(int64_t)gj * ld + gi] = v;
           }
         }
+  }
+}
+
+__device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
+                            const double *__restrict__ E, int m,
+                            double *__restrict__ Rbase, int64_t estride,
+                            int ld, F64Smem &sm) {
+  // the last tile may reach at most 16 rows past n (n_pad = 32 ceil(n/32))
+  if (I == J) {
+    if (S.n - I * PS_T <= 16)
+      ps_f64_item_m<1>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+    else
+      ps_f64_item_m<1 | 2 | 8>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+  } else {
+    if (S.n - J * PS_T <= 16)
+      ps_f64_item_m<1 | 4>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+    else
+      ps_f64_item_m<15>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
   }
 }
 
