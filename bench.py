@@ -49,8 +49,8 @@ PMC_TRAFFIC = {
                      "sha256_16": "9bfacccc636ba97c",
                      "bytes_per_energy": 23.26e6 + 9.49e6},
     "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
-                     "sha256_16": "a245a42754ef98d7",
-                     "bytes_per_energy": 0.194e6 + 0.320e6},
+                     "sha256_16": "922a8f7e26f5c975",
+                     "bytes_per_energy": 0.191e6 + 0.320e6},
     "polesum_bf16x3": {"src": "paper_1403_5524_amd/csrc/polesum_pd.hip",
                        "sha256_16": "964e1c800446329d",
                        "bytes_per_energy": 0.338e6 + 0.822e6},
