@@ -268,3 +268,21 @@ def test_large_symmetry_c4_sampled(torch_dev, nat):
     assert err64 < OMEGA_TOL_FP64
     assert errbf < 1e-4
     assert np.array_equal(st.cpu().numpy(), ref["status"])
+
+
+@pytest.mark.parametrize("n", [1, 8, 16, 17, 31, 32, 33, 48, 63, 64])
+def test_rmatrix_fp64_tile_edges(torch_dev, nat, n):
+    """Channel counts on both sides of each 16- and 32-channel edge: the FP64
+    pole sum forms only the 16x16 blocks of a 32x32 tile pair that hold kept
+    elements (last tile half or wholly in the padding, diagonal tiles), so
+    every shape of the last tile is compared element by element."""
+    rng = np.random.default_rng(500 + n)
+    sym = wl.random_symmetry(rng, n, 300, -2.0, 40.0).as_dict()
+    h = nat.load_symmetry(sym)
+    E = np.array([0.37, 3.1, 17.9])
+    R = nat.rm_rmatrix(h, _dev(torch_dev, E)).cpu().numpy()
+    ref = oracle.r_matrix(sym["E_pole"], sym["w"], sym["a"], E)
+    err = np.abs(R - ref).max() / np.abs(ref).max()
+    assert err < 1e-12, err
+    assert np.array_equal(R, np.transpose(R, (0, 2, 1)))
+    h.free()
