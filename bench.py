@@ -11,7 +11,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
     python bench.py [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
                     [--also bf16x3,fp32] [--graph] [--workload c2|c3|c4]
                     [--no-postproc] [--photo-M N] [--photo-ca-M N]
-                    [--outer-M N] [--inner-N N]
+                    [--outer-M N] [--inner-N N] [--table3]
 
 After the headline sweep, the sweep's FP64 Omega is smoothed, averaged into
 effective collision strengths and summed over level groups; those kernels'
@@ -369,6 +369,44 @@ def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
     return out
 
 
+def table3_leg(native, torch, oracle, workloads):
+    """The FP64 pole sum (rm_rmatrix) on the ten shapes of the paper's
+    Table 3: enough energies per shape to fill the GPU (4096, fewer for the
+    largest shapes, at least 256), kernel time from the pole-sum stage,
+    R checked against the oracle on one energy for n <= 400."""
+    rows = []
+    for n, m in workloads.TABLE3_SHAPES:
+        M = int(min(4096, max(256, 2e13 / (n * (n + 1.0) * m))))
+        sym, mesh = workloads.table3_symmetry(n, m, M)
+        h = native.load_symmetry(sym)
+        E = torch.as_tensor(mesh, dtype=torch.float64, device="cuda:0")
+        native.rm_rmatrix(h, E[:64])                # warm-up
+        torch.cuda.synchronize()
+        native.rm_profile(True)
+        R = native.rm_rmatrix(h, E)
+        torch.cuda.synchronize()
+        ms, _ = native.rm_profile_query("polesum")
+        native.rm_profile(False)
+        err = None
+        if n <= 400:
+            k = M // 3
+            ref = oracle.r_matrix(sym.E_pole, sym.w, sym.a, mesh[k:k + 1])[0]
+            err = float(np.abs(R[k].cpu().numpy() - ref).max() / np.abs(ref).max())
+        del R
+        h.free()
+        flops = n * (n + 1.0) * m * M
+        tf = flops / (ms * 1e-3) / 1e12
+        rows.append({"n": n, "m": m, "energies": M, "ms": ms,
+                     "ms_per_multiply": ms / M, "tflops": tf,
+                     "frac": tf / PEAK["fp64"], "max_rel_err_R": err})
+        note("table 3 shape %d x %d: %d energies in %.1f ms, %.1f TFLOP/s"
+             % (n, m, M, ms, tf))
+    return {"rows": rows,
+            "note": "FP64 pole sum only; flops counted as n(n+1)m per energy "
+                    "(upper triangle); the paper's Table 3 times (TITAN, unit "
+                    "ambiguous) are context only"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,6 +433,9 @@ def main():
     ap.add_argument("--inner-N", type=int, default=512,
                     help="sine functions per channel of the inner-region "
                          "leg (8 channels); 0 skips it")
+    ap.add_argument("--table3", action="store_true",
+                    help="also time the FP64 pole sum on the ten shapes of "
+                         "the paper's Table 3 (reported under table3)")
     ap.add_argument("--photo-ca-M", type=int, default=2048,
                     help="energies of the photoionization leg on the Ca II "
                          "shape (1815 channels, 6000 energies); 0 skips it")
@@ -534,6 +575,7 @@ def main():
         # one untimed-warmup-free step: the headline run has loaded the code
         photo_ca = photo_leg(native, torch, oracle, workloads, 1, 0,
                              args.photo_ca_M, shape="ca2", n_check=2)
+    table3 = table3_leg(native, torch, oracle, workloads) if args.table3 else None
     inner_res = None
     if args.inner_N > 0:
         inner_res = inner_leg(native, oracle, workloads, max(1, min(args.steps, 2)),
@@ -575,6 +617,7 @@ def main():
         "photoionization_ca2": photo_ca,
         "outer_propagation": outer_res,
         "inner_region": inner_res,
+        "table3": table3,
     }
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)

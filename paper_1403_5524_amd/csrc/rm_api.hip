@@ -1423,6 +1423,7 @@ int rm_rmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
       const int64_t c0 = (int64_t)c * p.C;
       const int64_t mc = std::min(p.C, m - c0);
       const int t = (mc == p.C) ? 0 : 1;
+      StageTimer tm(1, st);
       for (auto &set : p.sets) {
         PsLaunch L{};
         L.syms = p.d_syms;

@@ -178,6 +178,22 @@ def photo_ca2(M=6000):
     return w, dip, -0.8
 
 
+# The ten (channels n, poles m) shapes of the paper's Sec. 6 Table 3 (the
+# R-matrix formation of PSTGF for e- + Fe III), m/n ~ 62 throughout.
+TABLE3_SHAPES = [(267, 16512), (308, 19201), (399, 24666), (526, 32530),
+                 (132, 8155), (260, 16102), (837, 51573), (796, 49169),
+                 (1368, 84321), (1241, 76646)]
+
+
+def table3_symmetry(n, m, M, seed=8):
+    """One symmetry of a Table 3 shape with the c2 distributions (poles
+    U[-5, 200], w ~ N(0, 0.1^2), thresholds U[0, 2], l ~ U{0..5}) and the
+    M-point mesh on [0, 20] it is evaluated on; seed + n."""
+    rng = np.random.default_rng(seed + n)
+    sym = random_symmetry(rng, n, m, -5.0, 200.0, mesh=(0.0, 20.0, M))
+    return sym, uniform_mesh(0.0, 20.0, M)
+
+
 def outer_coupling(n, lmax=2, seed=6, scales=(1.0, 4.0)):
     """Long-range multipole coefficients beta [lmax, n, n] (symmetric,
     N(0, scale^2) off and on the diagonal; lam = 1 dipole, 2 quadrupole) for
