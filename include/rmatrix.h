@@ -398,7 +398,9 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
  * by the call, which synchronises `stream` after each sweep; sweeps and
  * rotations (host, each may be NULL) receive the sweeps taken and the
  * number of block-pair rotations applied over all of them.  Memory: about
- * 16 (n_chan n_basis)^2 bytes of device workspace, allocated and freed by the call.
+ * 16 (n_chan n_basis)^2 + 8 (n_chan^2 + n_basis) n_quad bytes of device
+ * workspace (the matrices, then the quadrature tables), allocated and freed
+ * by the call.
  * Errors: RM_ERR_ARG (n_chan < 1, n_basis < 1, n_chan n_basis > 4096, a not
  * finite and > 0, z < 0, n_quad > 16384, l outside [0, 12], model arrays not
  * finite / not symmetric, null pointer), RM_ERR_NOMEM, RM_ERR_HIP,
