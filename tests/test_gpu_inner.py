@@ -202,3 +202,13 @@ def test_batch_reports_the_failing_item(nat):
         nat.rm_inner_region_batch([good, bad, good], 16)
     assert ex.value.code == nat.RM_ERR_ARG and "item 1" in str(ex.value)
     assert nat.rm_inner_region_batch([], 16) == []
+
+
+@pytest.mark.parametrize("n,N,Q", [(2, 15, 45), (3, 10, 1), (1, 7, 30),
+                                   (2, 9, 59)])
+def test_quadrature_sizes_not_multiple_of_four(nat, n, N, Q):
+    """The assembly pads the quadrature to a multiple of 4 nodes with zero
+    weights: Q = 45, 1, 30, 59 give the oracle's poles and R with the same
+    Q."""
+    _log_and_check("n=%d N=%d Q=%d" % (n, N, Q),
+                   _compare(nat, _random_model(n, 70 + Q), N, Q=Q))
