@@ -95,6 +95,47 @@ def blas_threads():
     return os.cpu_count()
 
 
+def cpu_baseline_1thread(sym, mesh, count):
+    """The same oracle sweep with the BLAS pool held to one thread."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    idx = np.linspace(0, mesh.size - 1, count).round().astype(int)
+    with threadpool_limits(limits=1, user_api="blas"):
+        t0 = time.perf_counter()
+        oracle.sweep(sym.as_dict(), mesh[idx])
+        dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "energies/s", "cores": 1,
+            "kind": "oracle", "sample": "%d of %d mesh energies, evenly "
+                                        "spaced (%.1f s)" % (count, mesh.size, dt)}
+
+
+def library_gemm_ceiling(torch, sym, mesh, batch=32, reps=5):
+    """Context, not the path: the pole-sum shape (W diag(d)) W^T as a plain
+    FP64 library GEMM (torch.matmul, rocBLAS / hipBLASLt) over `batch`
+    energies, with W diag(d) formed beforehand; full-square flops."""
+    dev = torch.device("cuda:0")
+    W = torch.as_tensor(sym.w, dtype=torch.float64, device=dev)      # [n, N_H]
+    Wt = W.t().contiguous()                                           # [N_H, n]
+    Ek = torch.as_tensor(sym.E_pole, dtype=torch.float64, device=dev)
+    Es = torch.as_tensor(mesh[:: max(1, mesh.size // batch)][:batch],
+                         dtype=torch.float64, device=dev)
+    A = (W[None, :, :] / (Ek[None, None, :] - Es[:, None, None])).contiguous()
+    R = torch.matmul(A, Wt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        R = torch.matmul(A, Wt)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    n, nh = sym.w.shape
+    flops = 2.0 * n * n * nh * Es.numel()
+    del A, R
+    return {"kind": "torch.matmul FP64 (rocBLAS / hipBLASLt), context",
+            "energies": int(Es.numel()), "ms": dt * 1e3,
+            "tflops_full_square": flops / dt / 1e12,
+            "energies_per_s_gemm_only": Es.numel() / dt}
+
+
 def cpu_baseline(sym, mesh, count):
     """The oracle as it stands, timed on this host on a bounded sample."""
     import oracle
@@ -549,6 +590,19 @@ def main():
                 "kernels": kernels, "graph_ms": graph_ms}
 
     head = run(args.prec, args.graph)
+    # combined roofline of a step: the pole sums at the MFMA peak of their
+    # precision, the dense FP64 step at the FP64 peak, the Omega writes and
+    # energy reads at the HBM bandwidth
+    t_roof = (flops_step / (PEAK[args.prec] * 1e12)
+              + mflops_step / (PEAK["fp64"] * 1e12)
+              + (8.0 * P * M + 8.0 * M) / 8e12)
+    combined = {"t_roof_ms": t_roof * 1e3, "t_ms": head["ms"],
+                "frac": t_roof * 1e3 / head["ms"],
+                "terms_ms": {"polesum": flops_step / (PEAK[args.prec] * 1e9),
+                             "dense": mflops_step / (PEAK["fp64"] * 1e9),
+                             "hbm": (8.0 * P * M + 8.0 * M) / 8e9}}
+    gemm_ceiling = (library_gemm_ceiling(torch, sym, w.mesh)
+                    if len(w.syms) == 1 else None)
     post = None
     if not args.no_postproc and len(w.syms) == 1 and sym.target is None:
         # every channel its own target level: level energies are thresholds
@@ -611,6 +665,8 @@ def main():
         "graph_ms_per_step": graph_ms,
         "graph_value": (M / (graph_ms * 1e-3)) if graph_ms else None,
         "roofline": roof,
+        "combined_roofline": combined,
+        "library_gemm_ceiling": gemm_ceiling,
         "other_precisions": others,
         "postproc": post,
         "photoionization": photo,
@@ -622,6 +678,8 @@ def main():
     if not args.no_cpu:
         note("cpu baseline on %d energies" % args.cpu_sample)
         out["cpu_baseline"] = cpu_baseline(sym, w.mesh, args.cpu_sample)
+        out["cpu_baseline_1thread"] = cpu_baseline_1thread(
+            sym, w.mesh, max(1, args.cpu_sample // 32))
     for h in hs:
         h.free()
     print(json.dumps(out), flush=True)
