@@ -212,3 +212,24 @@ def test_quadrature_sizes_not_multiple_of_four(nat, n, N, Q):
     Q."""
     _log_and_check("n=%d N=%d Q=%d" % (n, N, Q),
                    _compare(nat, _random_model(n, 70 + Q), N, Q=Q))
+
+
+@pytest.mark.parametrize("case", ["l12_small_box", "strong_charge", "large_box"])
+def test_extreme_models(nat, case):
+    """Models at the edges of the accepted range: l = 12 in a 3 a0 box (a
+    centrifugal term of 156/r^2 dominating the spectrum), z = 5 with a deep
+    well, and a 60 a0 box; the same error budget applies."""
+    if case == "l12_small_box":
+        m = _model([0.0, 0.5], [12, 11], 1.0, 3.0, [[3.0, 1.0], [1.0, 2.0]],
+                   [[1.0, 1.5], [1.5, 1.0]])
+        N = 80
+    elif case == "strong_charge":
+        m = _model([0.0, 0.2, 0.9], [0, 1, 2], 5.0, 10.0,
+                   [[20.0, 2.0, 1.0], [2.0, 15.0, 3.0], [1.0, 3.0, 10.0]],
+                   [[0.5, 1.0, 1.5], [1.0, 0.8, 1.2], [1.5, 1.2, 2.0]])
+        N = 120
+    else:
+        m = _model([0.0, 0.1], [0, 3], 1.0, 60.0, [[2.0, 0.5], [0.5, 1.0]],
+                   [[5.0, 8.0], [8.0, 6.0]])
+        N = 300
+    _log_and_check(case, _compare(nat, m, N))
