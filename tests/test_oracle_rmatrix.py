@@ -284,3 +284,26 @@ def test_k_continuous_just_above_threshold():
         Ks.append(K)
     assert np.abs(Ks[2] - Ks[1]).max() < np.abs(Ks[1] - Ks[0]).max()
     assert np.abs(Ks[2] - Ks[1]).max() < 1e-3 * max(1.0, np.abs(Ks[1]).max())
+
+
+def test_s_matrix_eigenvalues_are_exp_of_twice_the_eigenphases():
+    """S = (1 + iK)(1 - iK)^-1 has the eigenvalues (1 + i k)/(1 - i k) =
+    exp(2 i arctan k) of K's eigenvalues k, so its spectrum is exp(2 i
+    delta) with delta the eigenphases; one channel: K = tan d gives S =
+    exp(2 i d)."""
+    rng = np.random.default_rng(11)
+    for n in (1, 3, 7):
+        M = rng.normal(0.0, 2.0, (n, n))
+        K = 0.5 * (M + M.T)
+        S = oracle.s_matrix(K)
+        d = oracle.eigenphases(K)
+        assert np.all(np.abs(d) < np.pi / 2)
+        ev = np.linalg.eigvals(S)
+        want = np.exp(2j * d)
+        # match each computed eigenvalue to the nearest expected one
+        for z in want:
+            assert np.abs(ev - z).min() < 1e-12
+        assert np.abs(S @ S.conj().T - np.eye(n)).max() < 1e-12
+    for dd in (-1.2, 0.3, 1.5):
+        S = oracle.s_matrix(np.array([[np.tan(dd)]]))
+        assert abs(S[0, 0] - np.exp(2j * dd)) < 1e-12
