@@ -162,6 +162,7 @@ __global__ void inner_init_kernel(double *A, double *V, int D, int Dp,
 constexpr int BJ_B = 16;        // columns per block
 constexpr int BJ_W = 2 * BJ_B;  // columns per block pair
 constexpr int BJ_CH = 256;      // rows per workgroup (4 waves x 64)
+constexpr int BJ_MAXCH = 16;    // row chunks at the largest Dp (4096)
 
 __device__ inline void bj_pair(int nb, int t, int k, int &P, int &Qb) {
   const int L = nb - 1;
@@ -257,8 +258,16 @@ __global__ __launch_bounds__(256) void bj_eig_kernel(
   const double *pk = part + (int64_t)k * nchunk * 768;
   if (tid == 0) need = 0;
   for (int e = tid; e < 768; e += 256) {
+    // every chunk's partial in flight at once (nchunk <= BJ_MAXCH; addresses
+    // clamped), then added in chunk order
+    double v[BJ_MAXCH];
+#pragma unroll
+    for (int c = 0; c < BJ_MAXCH; ++c)
+      v[c] = pk[(int64_t)min(c, nchunk - 1) * 768 + e];
     double sum = 0.0;
-    for (int c = 0; c < nchunk; ++c) sum += pk[(int64_t)c * 768 + e];
+#pragma unroll
+    for (int c = 0; c < BJ_MAXCH; ++c)
+      if (c < nchunk) sum += v[c];
     const int tile = e >> 8, i = (e & 255) >> 4, j = e & 15;
     if (tile == 0) {
       G[i][j] = sum;
@@ -510,6 +519,7 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   if (Q > 16384) return in_fail(RM_ERR_ARG, std::string(fn) + ": n_quad > 16384");
   hipStream_t st = (hipStream_t)stream;
   const int D = n * N, Dp = (D + BJ_W - 1) / BJ_W * BJ_W;  // even block count
+  static_assert(4096 / BJ_CH <= BJ_MAXCH, "partial Grams beyond the eigen kernel's unroll");
   const int nb = Dp / BJ_B, npair = nb / 2, nchunk = (Dp + BJ_CH - 1) / BJ_CH;
   std::vector<double> rq, wq;
   gauss_legendre(Q, d->a, rq, wq);
