@@ -14,9 +14,9 @@
 // then column k is (H + sigma I) v_k with v_k an eigenvector.  The rotations
 // act on pairs of 16-column blocks (Gram matrix by FP64 MFMA, its 32 x 32
 // eigenproblem in LDS, the block rotation applied by FP64 MFMA), so a sweep
-// reads the matrix nb - 1 times for nb = D / 16 blocks rather than D - 1.  w_ik = sqrt2 sum_m
-// V_(i,m),k phi_m(a) with phi_m(a) = sqrt(2/a) (-1)^m, the convention of
-// R = (1/2a) sum_k w_ik w_jk / (E_k - E).
+// reads the matrix nb - 1 times for nb = D / 16 blocks rather than D - 1.
+// w_ik = sqrt2 sum_m V_(i,m),k phi_m(a) with phi_m(a) = sqrt(2/a) (-1)^m,
+// the convention of R = (1/2a) sum_k w_ik w_jk / (E_k - E).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -75,10 +75,9 @@ __global__ void inner_tables_kernel(int n, int N, int Q, int Qp, double a, doubl
 // block (i, j) is Phi diag(wv_ij) Phi^T, a product on the FP64 matrix cores.
 // One wavefront per 32 x 32 tile (block pair (i, j) = (blockIdx.x / n,
 // blockIdx.x % n), tile row blockIdx.y, tile column blockIdx.z); only the
-// lower triangle of H
-// is computed (blocks i > j whole, the diagonal blocks' tiles tr >= tc, and
-// in those only row >= column), each value written to both halves so that H
-// is exactly symmetric.  MFMA 16x16x4: lane (col, kq) holds phi[m0 + col]
+// lower triangle of H is computed (blocks i > j whole, the diagonal blocks'
+// tiles tr >= tc, and in those only row >= column), each value written to
+// both halves so that H is exactly symmetric.  MFMA 16x16x4: lane (col, kq) holds phi[m0 + col]
 // [q0 + kq] (times wv for the A operand), k = the quadrature node.
 __global__ __launch_bounds__(64) void inner_assemble_kernel(
     int n, int N, int Qp, double a, const double *__restrict__ phi,
@@ -140,7 +139,8 @@ __global__ void inner_gershgorin_kernel(const double *__restrict__ H, int D,
   lb[r] = H[(int64_t)r * ld + r] - s;
 }
 
-// A = H + sigma I on the first D columns; padding column (if any) zero; V = I.
+// A = H + sigma I in its leading D x D block, the padding rows and columns
+// (up to Dp) zero; V = I.
 __global__ void inner_init_kernel(double *A, double *V, int D, int Dp,
                                   double sigma) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
