@@ -401,8 +401,9 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
  * 16 (n_chan n_basis)^2 + 8 (n_chan^2 + n_basis) n_quad bytes of device
  * workspace (the matrices, then the quadrature tables), allocated and freed
  * by the call.
- * Errors: RM_ERR_ARG (n_chan < 1, n_basis < 1, n_chan n_basis > 4096, a not
- * finite and > 0, z < 0, n_quad > 16384, l outside [0, 12], model arrays not
+ * Errors: RM_ERR_ARG (n_chan < 1, n_basis < 1, n_chan n_basis > 16384, a not
+ * finite and > 0, z < 0, n_quad > 16384, n_chan^2 n_quad over 1e9 table
+ * entries, l outside [0, 12], model arrays not
  * finite / not symmetric, null pointer), RM_ERR_NOMEM, RM_ERR_HIP,
  * RM_ERR_NUMERIC (no convergence in 40 sweeps; outputs hold the last
  * iterate). */

@@ -161,8 +161,9 @@ __global__ void inner_init_kernel(double *A, double *V, int D, int Dp,
 // |G_pq| <= tol sqrt(G_pp G_qq) leaves all columns mutually orthogonal.
 constexpr int BJ_B = 16;        // columns per block
 constexpr int BJ_W = 2 * BJ_B;  // columns per block pair
-constexpr int BJ_CH = 256;      // rows per workgroup (4 waves x 64)
-constexpr int BJ_MAXCH = 16;    // row chunks at the largest Dp (4096)
+constexpr int BJ_CH = 256;      // rows per rotation workgroup (4 waves x 64)
+constexpr int BJ_MAXCH = 16;    // row chunks of the Gram kernel, at most
+constexpr int BJ_DMAX = 16384;  // largest dimension
 
 __device__ inline void bj_pair(int nb, int t, int k, int &P, int &Qb) {
   const int L = nb - 1;
@@ -180,13 +181,14 @@ __device__ inline int bj_col(int P, int Qb, int c) {
   return c < BJ_B ? P * BJ_B + c : Qb * BJ_B + (c - BJ_B);
 }
 
-// Partial Grams over the rows of chunk blockIdx.y for block pair blockIdx.x:
+// Partial Grams over the `rows` rows (a multiple of 64; at most BJ_MAXCH
+// chunks cover Dp) of chunk blockIdx.y for block pair blockIdx.x:
 // part[(k nchunk + c)][tile][i][j], tiles X_P^T X_P, X_P^T X_Q, X_Q^T X_Q.
 // FP64 MFMA 16x16x4: lane (col, kq) holds rows row0 + 4 kq + u (u < 4) of
 // column col of each block (one 32-byte load each), and the k index of step
 // u is the row row0 + 4 kq + u for both operands.
 __global__ __launch_bounds__(256) void bj_gram_kernel(
-    const double *__restrict__ A, int Dp, int nb, int t, int nchunk,
+    const double *__restrict__ A, int Dp, int nb, int t, int nchunk, int rows,
     double *__restrict__ part) {
   __shared__ double red[4][3][256];
   const int k = blockIdx.x, c = blockIdx.y;
@@ -197,9 +199,10 @@ __global__ __launch_bounds__(256) void bj_gram_kernel(
   const double *xp = A + (int64_t)(P * BJ_B + col) * Dp + 4 * kq;
   const double *xq = A + (int64_t)(Qb * BJ_B + col) * Dp + 4 * kq;
   d4 gpp = {0.0, 0.0, 0.0, 0.0}, gpq = gpp, gqq = gpp;
-  const int rbeg = c * BJ_CH + wave * 64;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  const int per_wave = rows / 4;  // a multiple of 16
+  const int rbeg = c * rows + wave * per_wave;
+#pragma unroll 4
+  for (int g = 0; g < per_wave / 16; ++g) {
     const int row0 = rbeg + 16 * g;
     if (row0 >= Dp) break;
     const d4 a = *(const d4 *)(xp + row0);
@@ -499,8 +502,8 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   if (!d || !E_pole || !w) return in_fail(RM_ERR_ARG, std::string(fn) + ": null pointer");
   const int n = d->n_chan, N = d->n_basis;
   if (n < 1 || N < 1) return in_fail(RM_ERR_ARG, std::string(fn) + ": n_chan < 1 or n_basis < 1");
-  if ((int64_t)n * N > 4096)
-    return in_fail(RM_ERR_ARG, std::string(fn) + ": n_chan * n_basis > 4096");
+  if ((int64_t)n * N > BJ_DMAX)
+    return in_fail(RM_ERR_ARG, std::string(fn) + ": n_chan * n_basis > 16384");
   if (!(d->a > 0.0) || !std::isfinite(d->a) || !(d->z >= 0.0) || !std::isfinite(d->z))
     return in_fail(RM_ERR_ARG, std::string(fn) + ": a must be > 0 and z >= 0");
   if (!d->e_thr || !d->l || !d->depth || !d->range)
@@ -517,10 +520,15 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   }
   const int Q = d->n_quad > 0 ? d->n_quad : N + 48;
   if (Q > 16384) return in_fail(RM_ERR_ARG, std::string(fn) + ": n_quad > 16384");
+  if ((double)n * n * (Q + 3) * 8.0 > 8.0e9)
+    return in_fail(RM_ERR_ARG, std::string(fn) + ": quadrature table n_chan^2 n_quad over 8 GB");
   hipStream_t st = (hipStream_t)stream;
   const int D = n * N, Dp = (D + BJ_W - 1) / BJ_W * BJ_W;  // even block count
-  static_assert(4096 / BJ_CH <= BJ_MAXCH, "partial Grams beyond the eigen kernel's unroll");
   const int nb = Dp / BJ_B, npair = nb / 2, nchunk = (Dp + BJ_CH - 1) / BJ_CH;
+  // Gram chunks: 64-row multiples, at most BJ_MAXCH of them (the eigen
+  // kernel loads every chunk's partial at once)
+  const int gram_rows = 64 * ((Dp + 64 * BJ_MAXCH - 1) / (64 * BJ_MAXCH));
+  const int gchunk = (Dp + gram_rows - 1) / gram_rows;
   std::vector<double> rq, wq;
   gauss_legendre(Q, d->a, rq, wq);
   // device: A, V [Dp][Dp]; rq, wq [Q]; model arrays; lam [D]; w [n][D];
@@ -528,7 +536,7 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
   // [3][16][16]; rotations [npair][32][32]; l [n]; skip flags [npair];
   // block-pair counter
   const size_t nsq = (size_t)Dp * Dp;
-  const size_t npart = (size_t)npair * nchunk * 768, nu = (size_t)npair * BJ_W * BJ_W;
+  const size_t npart = (size_t)npair * gchunk * 768, nu = (size_t)npair * BJ_W * BJ_W;
   const int Qp = (Q + 3) / 4 * 4;
   const size_t ndbl = 2 * nsq + 2 * (size_t)Q + (size_t)n + 2 * (size_t)n * n +
                       (size_t)D + (size_t)n * D + (size_t)D + (size_t)N * Qp +
@@ -599,9 +607,9 @@ int rm_inner_region(const rm_inner_desc *d, double *E_pole, double *w,
     {
       ProfileScope scope(8, st);
       for (int t = 0; t < nb - 1 && e == hipSuccess; ++t) {
-        hipLaunchKernelGGL(bj_gram_kernel, dim3(npair, nchunk), dim3(256), 0, st, A, Dp,
-                           nb, t, nchunk, part);
-        hipLaunchKernelGGL(bj_eig_kernel, dim3(npair), dim3(256), 0, st, part, nchunk,
+        hipLaunchKernelGGL(bj_gram_kernel, dim3(npair, gchunk), dim3(256), 0, st, A, Dp,
+                           nb, t, gchunk, gram_rows, part);
+        hipLaunchKernelGGL(bj_eig_kernel, dim3(npair), dim3(256), 0, st, part, gchunk,
                            tol, Ub, skip, cnt);
         hipLaunchKernelGGL(bj_rotate_kernel, dim3(npair, nchunk), dim3(256), 0, st, A, V,
                            Dp, nb, t, Ub, skip);

@@ -161,7 +161,7 @@ def test_sweep_over_the_inner_region_poles(nat):
 def test_argument_errors(nat):
     good = _random_model(2, 1)
     with pytest.raises(nat.RmError) as ex:
-        nat.rm_inner_region(good, 2049)
+        nat.rm_inner_region(good, 8193)
     assert ex.value.code == nat.RM_ERR_ARG
     bad = dict(good, depth=np.array([[1.0, 0.2], [0.3, 1.0]]))
     with pytest.raises(nat.RmError):
@@ -233,3 +233,54 @@ def test_extreme_models(nat, case):
                    [[5.0, 8.0], [8.0, 6.0]])
         N = 300
     _log_and_check(case, _compare(nat, m, N))
+
+
+def _invariants(nat, m, N):
+    """Device solve of a large model against what the oracle's H fixes
+    without its eigen-solve: by Weyl each eigenvalue is within eta, so
+    sum(E) is within D eta of tr H and sum(E^2) within 2 eta sum|E| + D eta^2
+    of |H|_F^2."""
+    t0 = time.perf_counter()
+    Eg, wg, sweeps, _ = nat.rm_inner_region(m, N)
+    t_dev = time.perf_counter() - t0
+    Q = N + 48
+    H = inner.hamiltonian(m, N, Q)
+    D = H.shape[0]
+    S = max(np.abs(Eg).max(), 1.0)
+    eta = 8.0 * (D + Q) * np.finfo(float).eps * S
+    r_tr = abs(Eg.sum() - np.trace(H)) / (D * eta)
+    r_fro = abs((Eg ** 2).sum() - (H * H).sum()) / (
+        2.0 * eta * np.abs(Eg).sum() + D * eta ** 2)
+    log("D=%d: device solve %.2f s, %d sweeps; trace %.2e, Frobenius %.2e of "
+        "their bounds" % (D, t_dev, sweeps, r_tr, r_fro))
+    assert np.all(np.diff(Eg) >= 0.0)
+    assert r_tr < 1.0 and r_fro < 1.0
+    return Eg, wg, H, eta
+
+
+def test_dimension_8192_against_a_direct_solve(nat):
+    """D = 8192: the invariants, and R(E) between the two lowest poles
+    against (1/2a) B (H - E)^-1 B^T solved directly on the host, within
+    (eta/2a) sqrt(G_i G_j), G_i = |(H - E)^-1 b_i|^2."""
+    import scipy.linalg
+    m = _random_model(4, 90)
+    N = 2048
+    Eg, wg, H, eta = _invariants(nat, m, N)
+    n, D, a = 4, H.shape[0], m["a"]
+    E = 0.5 * (Eg[0] + Eg[1])
+    B = np.zeros((n, D))
+    phia = np.sqrt(2.0) * np.sqrt(2.0 / a) * (-1.0) ** np.arange(N)
+    for i in range(n):
+        B[i, i * N:(i + 1) * N] = phia
+    X = scipy.linalg.solve(H - E * np.eye(D), B.T, assume_a="sym")
+    Rd = B @ X / (2.0 * a)
+    Rg = (wg / (Eg - E)) @ wg.T / (2.0 * a)
+    G = (X * X).sum(axis=0)
+    ratio = (np.abs(Rg - Rd) / (eta / (2.0 * a) * np.sqrt(np.outer(G, G)))).max()
+    log("D=8192: R between the lowest poles %.2e of its bound" % ratio)
+    assert ratio < 1.0
+
+
+def test_dimension_16384(nat):
+    """D = 16384, the entry point's limit: the invariants."""
+    _invariants(nat, _random_model(8, 91), 2048)
