@@ -134,7 +134,7 @@ def test_several_blocks(nat):
 
 
 def test_maximum_dimension(nat):
-    """D = 4096, the entry point's limit."""
+    """D = 4096, the largest size compared with the oracle's full eigen-solve."""
     _log_and_check("n=2 N=2048", _compare(nat, _random_model(2, 4), 2048))
 
 
