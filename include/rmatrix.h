@@ -47,14 +47,20 @@ enum rm_status {
   RM_ERR_STATE = 5     /* handle used on the wrong device or after rm_free  */
 };
 
-/* Arithmetic of the pole sum (Sec. 6, Eq. 1-2).  The matching and T steps
- * are always FP64. */
+/* Arithmetic of the pole sum (Sec. 6, Eq. 1-2).  The mixed precisions split
+ * the poles of each energy into three tiers by their distance to E:
+ *   near  |E_k - E| <  near_delta:  FP64 operands, FP64 sum;
+ *   band  near_delta <= |E_k - E| < band_delta:  operands w_ik, w_jk and
+ *         d_k rounded to FP32, products and sum in FP64 (the rounding of
+ *         each term is then that of a slightly moved pole with slightly
+ *         changed amplitudes, not an independent error per matrix entry);
+ *   far   the rest: the MFMA precision below with FP32 accumulation.
+ * The matching solve is FP64 unless rm_opts.solve_fp32 is set. */
 enum rm_precision {
   RM_PREC_FP64 = 0,    /* FP64 MFMA over every pole                          */
-  RM_PREC_FP32 = 1,    /* FP32 MFMA, FP32 accumulation, far poles only;
-                          |E_k - E| < near_delta summed in FP64             */
+  RM_PREC_FP32 = 1,    /* FP32 MFMA, FP32 accumulation, far poles only       */
   RM_PREC_BF16X3 = 2   /* split-BF16 (hi*hi + hi*lo + lo*hi) MFMA, FP32
-                          accumulation, far poles only; near poles in FP64   */
+                          accumulation, far poles only                        */
 };
 
 /* Per-energy status bits (status[] of rm_sweep_energies / rm_kmatrix).
@@ -98,12 +104,15 @@ typedef struct {
 /* Options; a zero-initialised struct selects the defaults. */
 typedef struct {
   int32_t prec;          /* rm_precision                                   */
-  double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-2           */
+  double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-3           */
   int32_t solve_fp32;    /* must be 0: the matching solve is FP64 (a
                             nonzero value returns RM_ERR_ARG)              */
   int32_t refine_iters;  /* reserved, must be >= 0                         */
   int32_t chunk;         /* energies per internal chunk; 0 -> automatic    */
   uint32_t flags;        /* RM_FLAG_* bits                                 */
+  double band_delta;     /* Ry, mixed precisions only: the outer edge of the
+                            FP32-operand band; 0 -> 10 near_delta; must be
+                            >= near_delta                                  */
 } rm_opts;
 
 /* rm_opts.flags: time the pole-sum tile variants on the first plan of each

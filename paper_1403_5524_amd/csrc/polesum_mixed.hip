@@ -1,17 +1,20 @@
-// Mixed-precision pole sum (paper Sec. 6, Eq. 1-2) with an FP64 near-pole
-// correction.
+// Mixed-precision pole sum (paper Sec. 6, Eq. 1-2) in three tiers.
 //
-//   R_ij(E) = (1/2a) [ sum_{k far} w_ik w_jk d_k  +  sum_{k near} w_ik w_jk d_k ]
+//   R_ij(E) = (1/2a) [ sum_{k far} + sum_{k band} + sum_{k near} ] w_ik w_jk d_k
 //
-// with d_k = 1/(E_k - E) formed in FP64 and only then rounded, and "near"
-// meaning |E_k - E| < delta (a contiguous index range of the sorted poles).
+// with d_k = 1/(E_k - E) formed in FP64 and only then rounded; "near" means
+// |E_k - E| < delta, "band" delta <= |E_k - E| < band (contiguous index
+// ranges of the sorted poles), "far" the rest.
 // The far sum runs on the matrix cores with FP32 accumulation, either
 //   * FP32: v_mfma_f32_16x16x4f32 on FP32 W and FP32 d_k w_ik, or
 //   * split BF16: x = d_k w_ik and W are each written as hi + lo in BF16 and
 //     x W^T ~ xh Wh^T + xh Wl^T + xl Wh^T (v_mfma_f32_16x16x32_bf16), which
 //     keeps about 16 significant bits per product;
 // the near sum, where d_k is large and FP32 would lose the cancellation in
-// E_k - E, is added in FP64 in the epilogue.
+// E_k - E, is added in FP64 in the epilogue, and so is the band sum from
+// FP32-rounded w_ik, w_jk and d_k (FP64 products and sum): its terms are the
+// largest of the rest, and accumulated in FP32 they would set the rounding
+// of every term added after them.
 //
 // Work decomposition: a work item is one 16-row block I of R of one
 // symmetry, a run of up to JMAX column blocks J >= I (upper triangle), and
@@ -57,7 +60,8 @@ struct MxSmem {
 template <bool BF16, int JMAX, int EW>
 __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
                               const double *__restrict__ E, int m,
-                              double delta, double *__restrict__ Rbase,
+                              double delta, double band,
+                              double *__restrict__ Rbase,
                               int64_t estride, int ld,
                               MxSmem<BF16, JMAX, EW> &sm) {
   constexpr int EG = 4 * EW;
@@ -72,9 +76,10 @@ __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
     int lo = 0, hi = 0;
     if (e < m) {
       const double Ee = E[e];
-      // superset of the near set; the epilogue applies the exact test
-      lo = lower_bound_pole(S.E_pole, S.nh, Ee - 2.0 * delta);
-      hi = lower_bound_pole(S.E_pole, S.nh, Ee + 2.0 * delta);
+      // superset of the near and band tiers; the epilogue applies the
+      // exact tests
+      lo = lower_bound_pole(S.E_pole, S.nh, Ee - 2.0 * band);
+      hi = lower_bound_pole(S.E_pole, S.nh, Ee + 2.0 * band);
     }
     sm.nlo[tid] = lo;
     sm.nhi[tid] = hi;
@@ -127,7 +132,7 @@ __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
         float dv = 0.f;
         if (e0 + de < m) {
           const double diff = S.E_pole[k0 + dk] - E[e0 + de];  // FP64
-          if (!(fabs(diff) < delta)) dv = (float)(1.0 / diff);
+          if (!(fabs(diff) < band)) dv = (float)(1.0 / diff);
         }
         sm.Ds[de][dk] = dv;
       }
@@ -186,7 +191,7 @@ __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
     __syncthreads();
   }
 
-  // epilogue: FP64 near-pole correction, scale, store both triangles.
+  // epilogue: the near and band tiers, scale, store both triangles.
   // FP32/BF16 16x16 MFMA result: D[i][j] at lane j + 16 (i / 4), reg i % 4.
   const double scale = 1.0 / (2.0 * S.a);
 #pragma unroll
@@ -210,8 +215,13 @@ __device__ void ps_mixed_item(const SymDev &S, int IB, int JB0, int grp,
         double v = (double)acc[e][b][r];
         for (int k = klo; k < khi; ++k) {
           const double diff = S.E_pole[k] - Ee;
-          if (!(fabs(diff) < delta)) continue;  // same test as the d_k staging
-          v += S.Wt[(int64_t)k * S.n_pad + gi] * S.Wt[(int64_t)k * S.n_pad + gj] / diff;
+          if (!(fabs(diff) < band)) continue;  // same test as the d_k staging
+          const double wi = S.Wt[(int64_t)k * S.n_pad + gi];
+          const double wj = S.Wt[(int64_t)k * S.n_pad + gj];
+          if (fabs(diff) < delta)
+            v += wi * wj / diff;
+          else
+            v += (double)(float)wi * (double)(float)wj * (double)(float)(1.0 / diff);
         }
         v *= scale;
         Re[(int64_t)gi * ld + gj] = v;
@@ -243,7 +253,8 @@ __global__ __launch_bounds__(256) void polesum_mixed_kernel(PsLaunch L) {
     const PsItem item = L.items[it];
     const SymDev &S = L.syms[item.sym];
     ps_mixed_item<BF16, JMAX, EW>(S, item.x, item.y, item.grp, L.E, L.m,
-                                  L.delta, L.out.out + L.out.off[item.sym],
+                                  L.delta, L.band,
+                                  L.out.out + L.out.off[item.sym],
                                   L.out.estride, L.out.ld_mult * S.n, sm);
     if (!L.counter) break;
   }

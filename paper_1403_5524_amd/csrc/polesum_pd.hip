@@ -6,8 +6,9 @@
 // formed once per symmetry (FP64 products, then rounded: FP32, or hi + lo
 // BF16) and D generated inside the kernel from the pole and mesh energies
 // (E_k - E_e from hi + lo FP32 splits of both energies, then one FP32
-// reciprocal).  Poles with |E_k - E_e| < delta get D = 0 here and are summed
-// in FP64 in the epilogue.
+// reciprocal).  Poles with |E_k - E_e| < band get D = 0 here and are added
+// in the epilogue: the near tier (< delta) from FP64 operands, the band tier
+// from FP32-rounded w_ik, w_jk and D_ke with FP64 products and sum.
 //
 //   * FP32:       v_mfma_f32_16x16x4f32 on FP32 P and D;
 //   * split BF16: P and D as hi + lo in BF16, Ph Dh + Ph Dl + Pl Dh with
@@ -277,7 +278,7 @@ __device__ inline void pd_step(const SymDev &S, PdSmem<PREC> &sm,
 template <int PREC>
 __device__ void pd_item(const SymDev &S, int pb, int grp,
                         const double *__restrict__ E, int m, double delta,
-                        double *__restrict__ Rbase, int64_t estride, int ld,
+                        double band, double *__restrict__ Rbase, int64_t estride, int ld,
                         PdSmem<PREC> &sm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
@@ -285,6 +286,7 @@ __device__ void pd_item(const SymDev &S, int pb, int grp,
   const int e0 = grp * PD_BN;
   const int nk = S.nh_pad / PD_KC;
   const float delta32 = (float)delta;
+  const float band32 = (float)band;
   if (tid < PD_KC) {
     sm.Ep[0][tid] = pd_split(S.E_pole[tid]);
     if (nk > 1) sm.Ep[1][tid] = pd_split(S.E_pole[PD_KC + tid]);
@@ -295,9 +297,10 @@ __device__ void pd_item(const SymDev &S, int pb, int grp,
     double Ee = 0.0;
     if (e < m) {
       Ee = E[e];
-      // superset of the near set; the epilogue applies the exact test
-      lo = pd_lower_bound(S.E_pole, S.nh, Ee - 2.0 * delta);
-      hi = pd_lower_bound(S.E_pole, S.nh, Ee + 2.0 * delta);
+      // superset of the near and band tiers; the epilogue applies the
+      // exact tests
+      lo = pd_lower_bound(S.E_pole, S.nh, Ee - 2.0 * band);
+      hi = pd_lower_bound(S.E_pole, S.nh, Ee + 2.0 * band);
     }
     sm.Ee[tid] = Ee;
     sm.Ee2[tid] = pd_split(Ee);
@@ -316,12 +319,12 @@ __device__ void pd_item(const SymDev &S, int pb, int grp,
   // in registers while chunk c's MFMAs run
   typename PdReg<PREC>::T pr[8];
   pd_load_p<PREC>(S, row0, 0, pr);
-  pd_gen_d<PREC>(sm, 0, 0, e0, m, delta32);
+  pd_gen_d<PREC>(sm, 0, 0, e0, m, band32);
   pd_store_p<PREC>(sm, 0, pr);
   __syncthreads();
-  for (int kc = 0; kc < nk; ++kc) pd_step<PREC>(S, sm, acc, kc, nk, row0, e0, m, delta32, pr);
+  for (int kc = 0; kc < nk; ++kc) pd_step<PREC>(S, sm, acc, kc, nk, row0, e0, m, band32, pr);
 
-  // epilogue: FP64 near-pole correction, scale, store both triangles.
+  // epilogue: the near and band tiers, scale, store both triangles.
   // 16x16 FP32 MFMA result: D[i][j] at lane j + 16 (i / 4), register i % 4.
   const double scale = 1.0 / (2.0 * S.a);
 #pragma unroll
@@ -344,8 +347,16 @@ __device__ void pd_item(const SymDev &S, int pb, int grp,
         double v = (double)acc[a][b][r];
         for (int k = klo; k < khi; ++k) {
           const double ek = S.E_pole[k];
-          if (!pd_near(pd_split(ek), ee, delta32)) continue;  // D's test
-          v += S.Wt[(int64_t)k * S.n_pad + gi] * S.Wt[(int64_t)k * S.n_pad + gj] / (ek - Ee);
+          const f2 ek2 = pd_split(ek);
+          if (!pd_near(ek2, ee, band32)) continue;  // D's test: in the GEMM
+          const double wi = S.Wt[(int64_t)k * S.n_pad + gi];
+          const double wj = S.Wt[(int64_t)k * S.n_pad + gj];
+          if (pd_near(ek2, ee, delta32)) {
+            v += wi * wj / (ek - Ee);
+          } else {
+            const double d32 = (double)__builtin_amdgcn_rcpf(pd_diff(ek2, ee));
+            v += (double)(float)wi * (double)(float)wj * d32;
+          }
         }
         v *= scale;
         Re[(int64_t)gi * ld + gj] = v;
@@ -375,7 +386,7 @@ __global__ __launch_bounds__(256) void polesum_pd_kernel(PsLaunch L) {
     if (it >= L.n_items) break;
     const PsItem item = L.items[it];
     const SymDev &S = L.syms[item.sym];
-    pd_item<PREC>(S, item.x, item.grp, L.E, L.m, L.delta,
+    pd_item<PREC>(S, item.x, item.grp, L.E, L.m, L.delta, L.band,
                   L.out.out + L.out.off[item.sym], L.out.estride,
                   L.out.ld_mult * S.n, sm);
     if (!L.counter) break;

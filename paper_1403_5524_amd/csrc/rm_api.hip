@@ -239,10 +239,16 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
     return fail(RM_ERR_ARG, "unknown precision %d", d.prec);
   if (!(d.near_delta >= 0.0) || !std::isfinite(d.near_delta))
     return fail(RM_ERR_ARG, "near_delta must be finite and >= 0");
-  // default near-pole window 1e-2 Ry: with 1e-3 the FP32-accumulated far
-  // sum still carries poles a few 1e-3 Ry away, whose large terms put
-  // Omega's error above 1e-4 near them
-  if (d.near_delta == 0.0) d.near_delta = 1e-2;
+  if (!(d.band_delta >= 0.0) || !std::isfinite(d.band_delta))
+    return fail(RM_ERR_ARG, "band_delta must be finite and >= 0");
+  if (d.near_delta == 0.0) d.near_delta = 1e-3;
+  // the FP32-operand band: poles a few near_delta away carry the largest
+  // terms of the far sum; accumulated in FP32 after them, every later term
+  // is rounded against their size
+  if (d.band_delta == 0.0) d.band_delta = 10.0 * d.near_delta;
+  if (d.band_delta < d.near_delta)
+    return fail(RM_ERR_ARG, "band_delta %g < near_delta %g", d.band_delta,
+                d.near_delta);
   if (d.refine_iters < 0) return fail(RM_ERR_ARG, "refine_iters < 0");
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");
@@ -447,8 +453,17 @@ static void tune_load() {
   FILE *f = std::fopen(path, "r");
   if (!f) return;
   int n, nh, prec, v;
-  while (std::fscanf(f, "%d %d %d %d", &n, &nh, &prec, &v) == 4)
-    if (v >= PS_F64_T32_E16 && v <= PS_PD64) g_tuned[{n, nh, prec}] = v;
+  while (std::fscanf(f, "%d %d %d %d", &n, &nh, &prec, &v) == 4) {
+    // an entry counts only if its variant belongs to its precision: an FP64
+    // kernel launched for a mixed sweep (or the reverse) would read staged
+    // operands the sweep never formed
+    const bool ok64 = prec == RM_PREC_FP64 &&
+                      (v == PS_F64_T32_E16 || v == PS_PD64);
+    const bool okmx = (prec == RM_PREC_FP32 || prec == RM_PREC_BF16X3) &&
+                      (v == PS_MX_J16_E8 || v == PS_MX_J8_E8 ||
+                       v == PS_MX_J16_E4 || v == PS_PD);
+    if (n > 0 && nh > 0 && (ok64 || okmx)) g_tuned[{n, nh, prec}] = v;
+  }
   std::fclose(f);
 }
 
@@ -530,26 +545,27 @@ static void build_items(const Plan &p, int variant, int64_t m,
 
 // Time every mixed variant on up to 512 energies of E (device) and keep the
 // fastest.  Synchronises `st`.
-static int tune_variants(const Sym &s, int prec, double delta, const double *E,
-                         int64_t m, hipStream_t st, const std::vector<int> &cands,
-                         int *chosen);
+static int tune_variants(const Sym &s, int prec, double delta, double band,
+                         const double *E, int64_t m, hipStream_t st,
+                         const std::vector<int> &cands, int *chosen);
 
-static int tune_sym(const Sym &s, int prec, double delta, const double *E,
-                    int64_t m, hipStream_t st, bool with_pd, int *chosen) {
+static int tune_sym(const Sym &s, int prec, double delta, double band,
+                    const double *E, int64_t m, hipStream_t st, bool with_pd,
+                    int *chosen) {
   std::vector<int> c = {PS_MX_J16_E8, PS_MX_J8_E8, PS_MX_J16_E4};
   if (with_pd) c.push_back(PS_PD);
-  return tune_variants(s, prec, delta, E, m, st, c, chosen);
+  return tune_variants(s, prec, delta, band, E, m, st, c, chosen);
 }
 
 static int tune_f64(const Sym &s, const double *E, int64_t m, hipStream_t st,
                     int *chosen) {
-  return tune_variants(s, RM_PREC_FP64, 0.0, E, m, st,
+  return tune_variants(s, RM_PREC_FP64, 0.0, 0.0, E, m, st,
                        {PS_F64_T32_E16, PS_PD64}, chosen);
 }
 
-static int tune_variants(const Sym &s, int prec, double delta, const double *E,
-                         int64_t m, hipStream_t st, const std::vector<int> &cands,
-                         int *chosen) {
+static int tune_variants(const Sym &s, int prec, double delta, double band,
+                         const double *E, int64_t m, hipStream_t st,
+                         const std::vector<int> &cands, int *chosen) {
   const int64_t mt = std::min<int64_t>(m, 512);
   const int64_t nn = (int64_t)s.n * s.n;
   double *R = nullptr;
@@ -590,6 +606,7 @@ static int tune_variants(const Sym &s, int prec, double delta, const double *E,
     L.out = PsOut{R, nn, doff, 1};
     L.prec = prec;
     L.delta = delta;
+    L.band = band;
     float ms_min = 1e30f;
     for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
       err = hipEventRecord(b, st);
@@ -620,6 +637,9 @@ static int tune_variants(const Sym &s, int prec, double delta, const double *E,
 static int pick_variant(Sym &s, const rm_opts &o, const double *E, int64_t M,
                         hipStream_t st, int *v) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  // the cache file first: tune_store rewrites it from g_tuned, so entries
+  // not yet read would be lost
+  tune_load();
   if (o.prec == RM_PREC_FP64) {
     // the FP64 pair-major GEMM is no faster than the scaled-W tiles on the
     // 200-channel case and costs 8 bytes per pair and pole; it is used only
@@ -648,7 +668,6 @@ static int pick_variant(Sym &s, const rm_opts &o, const double *E, int64_t M,
     *v = PS_PD;
     return RM_OK;
   }
-  tune_load();
   auto it = g_tuned.find({s.n, s.nh, o.prec});
   if (it != g_tuned.end() && (pd || it->second != PS_PD)) {
     *v = it->second;
@@ -658,7 +677,7 @@ static int pick_variant(Sym &s, const rm_opts &o, const double *E, int64_t M,
     *v = pd ? PS_PD : default_variant(o.prec);
     return RM_OK;
   }
-  int rc = tune_sym(s, o.prec, o.near_delta, E, M, st, pd, v);
+  int rc = tune_sym(s, o.prec, o.near_delta, o.band_delta, E, M, st, pd, v);
   if (rc) return rc;
   if (pd) g_tuned[{s.n, s.nh, o.prec}] = *v;  // a table without the pair
   tune_store();                               // form is not cached
@@ -816,6 +835,7 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
         L.out = PsOut{p.work, p.work_estride, p.d_work_off, 2};
         L.prec = p.o.prec;
         L.delta = p.o.near_delta;
+        L.band = p.o.band_delta;
         RM_HIP(launch_polesum(L, set.variant, st));
       }
       if (p.sigma) {
@@ -1434,6 +1454,7 @@ int rm_rmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
         L.out = PsOut{p.work, p.work_estride, p.d_work_off, 2};
         L.prec = p.o.prec;
         L.delta = p.o.near_delta;
+        L.band = p.o.band_delta;
         hipError_t e = launch_polesum(L, set.variant, st);
         if (e != hipSuccess) rc = fail(RM_ERR_HIP, "pole sum: %s", hipGetErrorString(e));
       }

@@ -141,8 +141,9 @@ hipError_t launch_chanfn(const Sym &s, const double *E, int64_t m,
 
 // Grouped pole sum (Sec. 6, Eq. 1-2) over a table of work items that may
 // span several symmetries.  FP64 variants use MFMA over every pole; mixed
-// variants use FP32 or split-BF16 MFMA over the far poles with an FP64
-// near-pole correction for |E_k - E| < delta.  With a counter (device int
+// variants use FP32 or split-BF16 MFMA over the far poles, |E_k - E| >=
+// band, and add the near tier (|E_k - E| < delta, FP64 operands) and the
+// band tier (FP32 operands, FP64 products and sum) in their epilogues.  With a counter (device int
 // holding 0) the grid is persistent and pulls items from it.
 struct PsLaunch {
   const SymDev *syms;
@@ -154,7 +155,8 @@ struct PsLaunch {
   int m;
   PsOut out;
   int prec;
-  double delta;
+  double delta;         // near tier: FP64 operands
+  double band;          // band tier (>= delta): FP32 operands, FP64 sum
 };
 hipError_t launch_polesum(const PsLaunch &L, int variant, hipStream_t st);
 hipError_t launch_polesum_pd(const PsLaunch &L, hipStream_t st);

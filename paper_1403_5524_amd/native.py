@@ -66,7 +66,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("near_delta", ctypes.c_double),
                 ("solve_fp32", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("band_delta", ctypes.c_double)]
 
 
 _lib = None
@@ -140,14 +140,55 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _dev(t, dtype, numel=None, name="tensor", optional=False):
+    """Device pointer of ``t`` after checking what the C ABI cannot: a torch
+    tensor of the given dtype, contiguous, with ``numel`` elements (when
+    given), on a GPU.  Raises RmError(RM_ERR_ARG) before any library call
+    otherwise; ``optional`` admits None (a NULL pointer)."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise RmError(RM_ERR_ARG, "%s must be a tensor" % name)
+    if not isinstance(t, torch.Tensor):
+        raise RmError(RM_ERR_ARG, "%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise RmError(RM_ERR_ARG, "%s must be %s, got %s" % (name, dtype,
+                                                             t.dtype))
+    if not t.is_contiguous():
+        raise RmError(RM_ERR_ARG, "%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise RmError(RM_ERR_ARG, "%s must hold %d elements, got %d"
+                      % (name, numel, t.numel()))
+    if not t.is_cuda:
+        raise RmError(RM_ERR_ARG, "%s must be on a GPU" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t, numel=None, name="tensor", optional=False):
+    import torch
+    return _dev(t, torch.float64, numel, name, optional)
+
+
+def _i32(t, numel=None, name="tensor", optional=False):
+    import torch
+    return _dev(t, torch.int32, numel, name, optional)
+
+
+def _f32(t, numel=None, name="tensor", optional=False):
+    import torch
+    return _dev(t, torch.float32, numel, name, optional)
+
+
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def make_opts(prec=RM_PREC_FP64, near_delta=0.0, solve_fp32=0, refine_iters=0,
-              chunk=0, flags=0):
-    return Opts(prec, near_delta, solve_fp32, refine_iters, chunk, flags)
+              chunk=0, flags=0, band_delta=0.0):
+    return Opts(prec, near_delta, solve_fp32, refine_iters, chunk, flags,
+                band_delta)
 
 
 class Symmetry:
@@ -204,23 +245,26 @@ def load_symmetry(sym):
 def rm_sweep_energies(syms, n_target, E, opts=None, omega=None, status=None):
     """E: CUDA float64 tensor [M].  Returns (omega [M, P], status [M])."""
     import torch
+    pE = _f64(E, name="E")
     M = int(E.numel())
     P = n_target * (n_target + 1) // 2
     if omega is None:
         omega = torch.empty((M, P), dtype=torch.float64, device=E.device)
     if status is None:
         status = torch.empty((M,), dtype=torch.int32, device=E.device)
+    po = _f64(omega, M * P, "omega")
+    ps = _i32(status, M, "status")
     arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
     o = opts if opts is not None else make_opts()
-    _check(lib().rm_sweep_energies(arr, len(syms), n_target, _ptr(E), M,
-                                   ctypes.byref(o), _ptr(omega), _ptr(status),
-                                   _stream()))
+    _check(lib().rm_sweep_energies(arr, len(syms), n_target, pE, M,
+                                   ctypes.byref(o), po, ps, _stream()))
     return omega, status
 
 
 def rm_kmatrix(sym, E, opts=None, want_R=False):
     """Returns (K [m, n, n], n_open [m], R [m, n, n] or None, status [m])."""
     import torch
+    pE = _f64(E, name="E")
     m, n = int(E.numel()), sym.n
     K = torch.empty((m, n, n), dtype=torch.float64, device=E.device)
     no = torch.empty((m,), dtype=torch.int32, device=E.device)
@@ -228,26 +272,31 @@ def rm_kmatrix(sym, E, opts=None, want_R=False):
     R = torch.empty((m, n, n), dtype=torch.float64, device=E.device) \
         if want_R else None
     o = opts if opts is not None else make_opts()
-    _check(lib().rm_kmatrix(sym.handle, _ptr(E), m, ctypes.byref(o), _ptr(K),
+    _check(lib().rm_kmatrix(sym.handle, pE, m, ctypes.byref(o), _ptr(K),
                             _ptr(no), _ptr(R), _ptr(st), _stream()))
     return K, no, R, st
 
 
 def rm_collision_strengths(sym, K, n_open, E, n_target, omega):
     """Accumulates into omega [m, P] (device float64)."""
+    pE = _f64(E, name="E")
     m = int(E.numel())
-    _check(lib().rm_collision_strengths(sym.handle, _ptr(K), _ptr(n_open),
-                                        _ptr(E), m, n_target, _ptr(omega),
-                                        _stream()))
+    P = n_target * (n_target + 1) // 2
+    pK = _f64(K, m * sym.n * sym.n, "K")
+    pn = _i32(n_open, m, "n_open")
+    po = _f64(omega, m * P, "omega")
+    _check(lib().rm_collision_strengths(sym.handle, pK, pn, pE, m, n_target,
+                                        po, _stream()))
     return omega
 
 
 def rm_rmatrix(sym, E, opts=None):
     import torch
+    pE = _f64(E, name="E")
     m, n = int(E.numel()), sym.n
     R = torch.empty((m, n, n), dtype=torch.float64, device=E.device)
     o = opts if opts is not None else make_opts()
-    _check(lib().rm_rmatrix(sym.handle, _ptr(E), m, ctypes.byref(o), _ptr(R),
+    _check(lib().rm_rmatrix(sym.handle, pE, m, ctypes.byref(o), _ptr(R),
                             _stream()))
     return R
 
@@ -255,10 +304,11 @@ def rm_rmatrix(sym, E, opts=None):
 def rm_channel_functions(sym, E):
     """Returns (out [m, n, 4], status [m])."""
     import torch
+    pE = _f64(E, name="E")
     m, n = int(E.numel()), sym.n
     out = torch.empty((m, n, 4), dtype=torch.float64, device=E.device)
     st = torch.empty((m,), dtype=torch.int32, device=E.device)
-    _check(lib().rm_channel_functions(sym.handle, _ptr(E), m, _ptr(out),
+    _check(lib().rm_channel_functions(sym.handle, pE, m, _ptr(out),
                                       _ptr(st), _stream()))
     return out, st
 
@@ -312,17 +362,22 @@ class Mlp:
         return out
 
     def set_params(self, p):
-        _check(lib().rm_mlp_set_params(self.handle, _ptr(p), _stream()))
+        pp = _f32(p, self.n_params, "params")
+        _check(lib().rm_mlp_set_params(self.handle, pp, _stream()))
 
     def forward(self, X):
         import torch
-        Y = torch.empty((X.shape[0],), dtype=torch.float32, device=X.device)
-        _check(lib().rm_mlp_forward(self.handle, _ptr(X), int(X.shape[0]),
-                                    _ptr(Y), _stream()))
+        B = int(X.shape[0]) if X is not None and X.dim() > 0 else 0
+        pX = _f32(X, B * self.d_in, "X")
+        Y = torch.empty((B,), dtype=torch.float32, device=X.device)
+        _check(lib().rm_mlp_forward(self.handle, pX, B, _ptr(Y), _stream()))
         return Y
 
     def grad(self, X, target, want_grad=False):
         import torch
+        B = int(X.shape[0]) if X is not None and X.dim() > 0 else 0
+        _f32(X, B * self.d_in, "X")
+        _f32(target, B, "target")
         loss = torch.empty((1,), dtype=torch.float32, device=X.device)
         g = torch.empty((self.n_params,), dtype=torch.float32,
                         device=X.device) if want_grad else None
@@ -338,8 +393,9 @@ class Mlp:
 
 def rm_mesh_from_density(dens, lo, hi, floor_frac, M):
     import torch
+    pd = _f32(dens, name="dens")
     E = torch.empty((M,), dtype=torch.float64, device=dens.device)
-    _check(lib().rm_mesh_from_density(_ptr(dens), int(dens.numel()), lo, hi,
+    _check(lib().rm_mesh_from_density(pd, int(dens.numel()), lo, hi,
                                       floor_frac, M, _ptr(E), _stream()))
     return E
 
@@ -349,6 +405,8 @@ class Plan:
 
     def __init__(self, syms, n_target, E, opts=None, omega=None, status=None):
         import torch
+        self.handle = None
+        _f64(E, name="E")
         M = int(E.numel())
         P = n_target * (n_target + 1) // 2
         self.E = E
@@ -356,6 +414,8 @@ class Plan:
             (M, P), dtype=torch.float64, device=E.device)
         self.status = status if status is not None else torch.empty(
             (M,), dtype=torch.int32, device=E.device)
+        _f64(self.omega, M * P, "omega")
+        _i32(self.status, M, "status")
         self._syms = list(syms)
         arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
         o = opts if opts is not None else make_opts()
@@ -393,11 +453,16 @@ class Plan:
 def rm_convolve_gaussian(E, omega, fwhm, out=None):
     """Gaussian smoothing of omega [M, P] (CUDA float64) on the mesh E [M]."""
     import torch
+    if not isinstance(omega, torch.Tensor) or omega.dim() != 2:
+        raise RmError(RM_ERR_ARG, "omega must be a [M, P] tensor")
     M, P = int(omega.shape[0]), int(omega.shape[1])
+    pi = _f64(omega, M * P, "omega")
+    pE = _f64(E, M, "E")
     if out is None:
         out = torch.empty_like(omega)
-    _check(lib().rm_convolve_gaussian(_ptr(E), M, _ptr(omega), P,
-                                      float(fwhm), _ptr(out), _stream()))
+    po = _f64(out, M * P, "out")
+    _check(lib().rm_convolve_gaussian(pE, M, pi, P, float(fwhm), po,
+                                      _stream()))
     return out
 
 
@@ -410,9 +475,14 @@ def rm_effective_collision_strengths(E, omega, e_level, n_target, kT):
     if lev.size != n_target:
         raise RmError(RM_ERR_ARG, "e_level must hold n_target values")
     P = n_target * (n_target + 1) // 2
+    if not isinstance(omega, torch.Tensor) or omega.dim() != 2:
+        raise RmError(RM_ERR_ARG, "omega must be a [M, P] tensor")
+    M = int(omega.shape[0])
+    pom = _f64(omega, M * P, "omega")
+    pE = _f64(E, M, "E")
     ups = torch.empty((P, t.size), dtype=torch.float64, device=omega.device)
     _check(lib().rm_effective_collision_strengths(
-        _ptr(E), int(omega.shape[0]), _ptr(omega), int(n_target),
+        pE, M, pom, int(n_target),
         lev.ctypes.data, t.ctypes.data, int(t.size), _ptr(ups), _stream()))
     return ups
 
@@ -424,10 +494,13 @@ def rm_group_collision_strengths(omega, n_target, group, n_group):
     if g.size != n_target:
         raise RmError(RM_ERR_ARG, "group must hold n_target values")
     Pg = n_group * (n_group + 1) // 2
-    out = torch.empty((int(omega.shape[0]), Pg), dtype=torch.float64,
-                      device=omega.device)
+    if not isinstance(omega, torch.Tensor) or omega.dim() != 2:
+        raise RmError(RM_ERR_ARG, "omega must be a [M, P] tensor")
+    M = int(omega.shape[0])
+    pom = _f64(omega, M * (n_target * (n_target + 1) // 2), "omega")
+    out = torch.empty((M, Pg), dtype=torch.float64, device=omega.device)
     _check(lib().rm_group_collision_strengths(
-        _ptr(omega), int(omega.shape[0]), int(n_target), g.ctypes.data,
+        pom, M, int(n_target), g.ctypes.data,
         int(n_group), _ptr(out), _stream()))
     return out
 
@@ -443,16 +516,18 @@ def rm_load_dipoles(sym, d):
 def rm_photoionization(syms, E, e0, opts=None, sigma=None, status=None):
     """sigma [M] in Mb (CUDA float64) and status [M] at the energies E."""
     import torch
+    pE = _f64(E, name="E")
     M = int(E.numel())
     if sigma is None:
         sigma = torch.empty((M,), dtype=torch.float64, device=E.device)
     if status is None:
         status = torch.empty((M,), dtype=torch.int32, device=E.device)
+    psg = _f64(sigma, M, "sigma")
+    pst = _i32(status, M, "status")
     arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
     o = opts if opts is not None else make_opts()
-    _check(lib().rm_photoionization(arr, len(syms), _ptr(E), M, float(e0),
-                                    ctypes.byref(o), _ptr(sigma),
-                                    _ptr(status), _stream()))
+    _check(lib().rm_photoionization(arr, len(syms), pE, M, float(e0),
+                                    ctypes.byref(o), psg, pst, _stream()))
     return sigma, status
 
 

@@ -21,6 +21,17 @@ def omega_normwise_err(om_gpu, om_ref):
     return float((num / den).max()), num, den
 
 
+def omega_elementwise_err(om_gpu, om_ref, floor=1e-8):
+    """Max of |dOmega| / |Omega_ref| over every transition whose reference
+    is at least `floor` times the largest value of its energy's row."""
+    om_gpu = np.asarray(om_gpu)
+    om_ref = np.asarray(om_ref)
+    row = np.abs(om_ref).max(axis=1, keepdims=True)
+    big = (np.abs(om_ref) >= floor * row) & (row > 0)
+    rel = np.abs(om_gpu - om_ref) / np.maximum(np.abs(om_ref), 1e-300)
+    return float(np.where(big, rel, 0.0).max()) if om_ref.size else 0.0
+
+
 def oracle_channel_table(sym, E):
     """Oracle channel functions laid out like rm_channel_functions."""
     cd = oracle.channel_data(E, sym["e_thr"], sym["l"], sym["z"], sym["a"])

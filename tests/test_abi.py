@@ -168,3 +168,68 @@ def test_photo_rejects_invalid(L):
 def test_propagation_rejects_invalid(L):
     assert L.rm_set_propagation(None, ctypes.c_double(30.0), 10, 1, None,
                                 None) == native.RM_ERR_ARG
+
+
+class _Poison:
+    """A library stand-in that fails the test if any entry point is called:
+    the binding must reject bad tensors before it reaches the C ABI."""
+
+    def __getattr__(self, name):
+        raise AssertionError("library entry point %s reached" % name)
+
+
+def _bad_tensors():
+    import torch
+    good = torch.zeros(6, dtype=torch.float64)
+    return [
+        ("float32", good.float()),
+        ("int32", good.to(torch.int32)),
+        ("strided", torch.zeros(12, dtype=torch.float64)[::2]),
+        ("host", good),  # right dtype and size, but host memory
+    ]
+
+
+@pytest.mark.parametrize("kind", ["float32", "int32", "strided", "host"])
+def test_binding_rejects_bad_tensors_before_any_call(monkeypatch, kind):
+    """Every tensor the binding passes to the C ABI is checked for dtype,
+    contiguity, size and device first: a float32 or strided E would be read
+    as the wrong doubles, a host pointer handed to a kernel is a GPU page
+    fault.  Each rejection is an RmError(RM_ERR_ARG) raised before the
+    library is touched."""
+    import torch
+    bad = dict(_bad_tensors())[kind]
+    monkeypatch.setattr(native, "_lib", _Poison())
+    sym = native.Symmetry(None, 2, 3, 2)
+    calls = [
+        lambda: native.rm_sweep_energies([sym], 2, bad),
+        lambda: native.rm_kmatrix(sym, bad),
+        lambda: native.rm_rmatrix(sym, bad),
+        lambda: native.rm_channel_functions(sym, bad),
+        lambda: native.rm_photoionization([sym], bad, -0.5),
+        lambda: native.Plan([sym], 2, bad),
+    ]
+    for call in calls:
+        with pytest.raises(native.RmError) as ei:
+            call()
+        assert ei.value.code == native.RM_ERR_ARG
+    # caller-supplied outputs are checked too
+    E_ok_shape = torch.zeros(6, dtype=torch.float64)
+    with pytest.raises(native.RmError):
+        native.rm_collision_strengths(sym, bad, bad, E_ok_shape, 2, bad)
+    with pytest.raises(native.RmError):
+        native.rm_convolve_gaussian(E_ok_shape, bad.reshape(2, 3)
+                                    if bad.is_contiguous() else bad[:6].reshape(2, 3), 0.1)
+    sym.handle = None
+
+
+def test_binding_rejects_wrong_sizes():
+    """Size is checked before the device: an output with the wrong element
+    count is refused whatever memory it is in."""
+    import torch
+    with pytest.raises(native.RmError) as ei:
+        native._f64(torch.zeros((4, 2), dtype=torch.float64), 12, "omega")
+    assert "omega must hold 12" in str(ei.value)
+    with pytest.raises(native.RmError) as ei:
+        native._i32(torch.zeros(3, dtype=torch.int32), 4, "status")
+    assert "status must hold 4" in str(ei.value)
+    assert native._f64(None, 4, "R", optional=True) is None

@@ -4,20 +4,25 @@ forms of the pole sum: the pair-major GEMM over precomputed w_ik w_jk (the
 default) and the scaled-W kernels (RM_FLAG_NO_PAIR_PRODUCTS).
 
 Bar: Omega within 1e-4 normwise per energy (the stated tolerance for the
-mixed paths).  R is checked normwise against bounds that follow from the
-arithmetic: FP32 operands carry 24 bits, split BF16 about 16 bits, with FP32
-accumulation over N_H terms.
+mixed paths) at the configured near-pole window delta = 1e-3 Ry, with the
+FP32-operand band out to 1e-2 Ry (the defaults).  R is checked normwise
+against bounds that follow from the arithmetic: FP32 operands carry 24
+bits, split BF16 about 16 bits, with FP32 accumulation over N_H terms.
+The elementwise error (every transition at least 1e-8 of its row's
+largest) is logged, not asserted: weak transitions carry the absolute
+error of the strong ones.
 """
 import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import log, omega_normwise_err
+from gpu_helpers import log, omega_elementwise_err, omega_normwise_err
 from paper_1403_5524_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
 OMEGA_TOL_MIXED = 1e-4
+DELTA = 1e-3   # the configured near-pole window of the 200-channel case
 R_TOL = {1: 1e-5, 2: 1e-4}
 FORMS = [0, 0x2]   # pair-major GEMM, scaled-W kernels
 
@@ -56,26 +61,82 @@ def test_rmatrix_mixed_c2(env, prec, flags):
     assert err.max() < R_TOL[prec]
 
 
+def _tier_energies(sym, w):
+    """Mesh energies plus energies in every tier of the pole sum around a
+    pole: inside the FP64 window (2e-6), just outside it and across the
+    FP32-operand band (1.05e-3 ... 9e-3, both sides), and just beyond the
+    band (1.2e-2, 1.5e-2), where the far sum carries its largest terms."""
+    rng = np.random.default_rng(17)
+    ks = np.nonzero((sym.E_pole > 0.5) & (sym.E_pole < 19.5))[0]
+    pk = rng.choice(ks, 40, replace=False)
+    off = rng.uniform(1.0e-3, 5.0e-3, 40) * rng.choice([-1.0, 1.0], 40)
+    off[:8] = np.sign(off[:8]) * rng.uniform(1.0e-3, 1.1e-3, 8)
+    return np.concatenate([w.mesh[wl.sample_indices(w.mesh.size, 24, seed=9)],
+                           sym.E_pole[pk] + off,
+                           _near_pole_energies(sym, 4, 2e-6),
+                           _near_pole_energies(sym, 4, 9e-3),
+                           _near_pole_energies(sym, 4, -1.05e-3),
+                           _near_pole_energies(sym, 4, 1.2e-2),
+                           _near_pole_energies(sym, 4, -1.5e-2)])
+
+
+@pytest.fixture(scope="module")
+def tier_ref(env):
+    _, _, w, _ = env
+    s = w.syms[0]
+    E = _tier_energies(s, w)
+    return E, oracle.sweep(s.as_dict(), E)
+
+
 @pytest.mark.parametrize("flags", FORMS)
 @pytest.mark.parametrize("prec", [1, 2])
-def test_sweep_mixed_c2_sample(env, prec, flags):
+def test_sweep_mixed_c2_delta_1e3(env, tier_ref, prec, flags):
+    """The 200-channel case at delta = 1e-3 Ry (its configuration): 24 mesh
+    energies and 60 energies placed in every tier around poles, half of
+    them 1-5e-3 Ry from a pole."""
     torch, nat, w, h = env
-    s = w.syms[0]
-    # mesh energies, energies inside the FP64 window and energies just
-    # outside it (the largest terms the low-precision far sum carries)
-    E = np.concatenate([w.mesh[wl.sample_indices(w.mesh.size, 16, seed=9)],
-                        _near_pole_energies(s, 4, 2e-6),
-                        _near_pole_energies(s, 4, 1.2e-2),
-                        _near_pole_energies(s, 4, -1.5e-2)])
-    log("sweep mixed prec=%d flags=%d m=%d" % (prec, flags, E.size))
+    E, ref = tier_ref
+    log("sweep mixed prec=%d flags=%d m=%d delta=%g" % (prec, flags, E.size,
+                                                         DELTA))
     Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
     om, st = nat.rm_sweep_energies([h], 200, Et,
-                                   nat.make_opts(prec=prec, flags=flags))
-    ref = oracle.sweep(s.as_dict(), E)
-    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
-    log("mixed prec=%d flags=%d omega normwise err %.3e" % (prec, flags, err))
+                                   nat.make_opts(prec=prec, flags=flags,
+                                                 near_delta=DELTA))
+    om = om.cpu().numpy()
+    err, _, _ = omega_normwise_err(om, ref["omega"])
+    el = omega_elementwise_err(om, ref["omega"])
+    log("mixed prec=%d flags=%d omega normwise err %.3e (elementwise %.3e)"
+        % (prec, flags, err, el))
     assert err < OMEGA_TOL_MIXED
     assert np.array_equal(st.cpu().numpy(), ref["status"])
+
+
+def test_default_window_is_the_configured_one(env, tier_ref):
+    """A zero-initialised rm_opts selects delta = 1e-3 and the band edge
+    10 delta: bit-identical to asking for them."""
+    torch, nat, w, h = env
+    E, _ = tier_ref
+    Et = torch.as_tensor(E[:16], dtype=torch.float64, device="cuda:0")
+    a, _ = nat.rm_sweep_energies([h], 200, Et, nat.make_opts(prec=1))
+    b, _ = nat.rm_sweep_energies([h], 200, Et,
+                                 nat.make_opts(prec=1, near_delta=1e-3,
+                                               band_delta=1e-2))
+    assert torch.equal(a, b)
+
+
+def test_band_is_what_meets_the_tolerance(env, tier_ref):
+    """With the band switched off (band_delta = delta) the FP32-accumulated
+    far sum carries the poles 1-5e-3 Ry away and misses the tolerance that
+    the three-tier sum meets: the band is doing the work."""
+    torch, nat, w, h = env
+    E, ref = tier_ref
+    Et = torch.as_tensor(E, dtype=torch.float64, device="cuda:0")
+    om, _ = nat.rm_sweep_energies([h], 200, Et,
+                                  nat.make_opts(prec=1, near_delta=DELTA,
+                                                band_delta=DELTA))
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref["omega"])
+    log("fp32 without the band: omega normwise err %.3e" % err)
+    assert err > OMEGA_TOL_MIXED
 
 
 def test_mixed_matches_fp64_on_c1(env):

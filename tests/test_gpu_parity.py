@@ -231,20 +231,48 @@ def test_empty_mesh_is_noop(torch_dev, nat, c1):
     assert om.shape == (0, 36)
 
 
-def test_batched_symmetries_c3_sample(torch_dev, nat):
-    """All 40 symmetries of uneven size summed into 20 shared target levels,
-    on sampled energies of the 5e4-point mesh."""
+@pytest.fixture(scope="module")
+def c3(nat):
+    """The 40-symmetry case loaded once, with the oracle on 6 sampled
+    energies of its 5e4-point mesh."""
     w = wl.config3()
     hs = [nat.load_symmetry(s) for s in w.syms]
     idx = wl.sample_indices(w.mesh.size, 6, seed=5)
     E = w.mesh[idx]
+    ref, rst = oracle_sweep_multi(w.syms, E, w.n_target)
+    return w, hs, E, ref, rst
+
+
+def test_batched_symmetries_c3_sample(torch_dev, nat, c3):
+    """All 40 symmetries of uneven size summed into 20 shared target levels,
+    on sampled energies of the 5e4-point mesh."""
+    w, hs, E, ref, rst = c3
     log("sweep c3 m=%d syms=%d" % (E.size, len(hs)))
     om, st = nat.rm_sweep_energies(hs, w.n_target, _dev(torch_dev, E))
-    ref, rst = oracle_sweep_multi(w.syms, E, w.n_target)
     err, _, _ = omega_normwise_err(om.cpu().numpy(), ref)
     log("c3 omega normwise err %.3e" % err)
     assert err < OMEGA_TOL_FP64
     assert np.array_equal(st.cpu().numpy(), rst)
+
+
+def test_batched_symmetries_c3_fp32_plan(torch_dev, nat, c3):
+    """The 40-symmetry case in its configured arithmetic: FP32 MFMA pole
+    sums with the FP64 near tier, one captured plan (hipGraph replay) with
+    autotuned tiles; Omega within the mixed tolerance."""
+    torch, _ = torch_dev
+    w, hs, E, ref, rst = c3
+    Et = _dev(torch_dev, E)
+    plan = nat.Plan(hs, w.n_target, Et,
+                    nat.make_opts(prec=nat.RM_PREC_FP32,
+                                  flags=nat.RM_FLAG_AUTOTUNE))
+    om, st = plan.execute()
+    torch.cuda.synchronize()
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref)
+    log("c3 fp32 plan omega normwise err %.3e variants %s"
+        % (err, plan.info()[2][:8]))
+    assert err < 1e-4
+    assert np.array_equal(st.cpu().numpy(), rst)
+    plan.free()
 
 
 def test_large_symmetry_c4_sampled(torch_dev, nat):

@@ -102,3 +102,86 @@ def test_no_sectors_is_identity_and_sweep_runs():
     om = outer.sweep_propagated(sym, prop, np.array([0.5, 2.0, 5.0]))
     assert om.shape == (3, n * (n + 1) // 2)
     assert np.all(np.isfinite(om)) and np.all(om >= 0.0)
+
+
+def _c1_sym():
+    from paper_1403_5524_amd import workloads as wl
+    return wl.config1().syms[0].as_dict()
+
+
+# energies with closed channels (below 2 Ry) and with every channel open
+SWEEP_E = np.array([0.35, 1.1, 1.85, 3.3, 6.7, 9.4])
+
+
+def test_sweep_propagated_pure_coulomb_equals_sweep_at_a():
+    """beta = 0: the outer solutions are the Coulomb / Whittaker functions
+    themselves, so Omega after propagation to A and matching there equals
+    Omega matched at r = a, up to the second-order sector error."""
+    sym = _c1_sym()
+    n = sym["e_thr"].size
+    ref = oracle.sweep(sym, SWEEP_E)["omega"]
+    scale = np.abs(ref).max(axis=1)
+    errs = []
+    for n_sec in (200, 400):
+        prop = {"A": sym["a"] + 15.0, "n_sec": n_sec,
+                "beta": np.zeros((1, n, n))}
+        got = outer.sweep_propagated(sym, prop, SWEEP_E)
+        errs.append((np.abs(got - ref).max(axis=1) / scale).max())
+    assert errs[-1] < 2e-5
+    assert 3.0 < errs[0] / errs[1] < 5.0   # second order in the width
+
+
+def test_sweep_propagated_no_sectors_at_a_is_sweep():
+    """n_sec = 0 with A = a: nothing propagates and the matching radius is
+    a, so the result is oracle.sweep's to rounding."""
+    sym = _c1_sym()
+    n = sym["e_thr"].size
+    prop = {"A": sym["a"], "n_sec": 0, "beta": np.zeros((1, n, n))}
+    ref = oracle.sweep(sym, SWEEP_E)["omega"]
+    got = outer.sweep_propagated(sym, prop, SWEEP_E)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_sweep_propagated_is_the_per_energy_chain():
+    """beta != 0 with a target map: every energy's Omega row equals
+    k_matrix_propagated -> t_matrix -> collision_strengths, and the packed
+    row holds the flux of the open block: pairs within one level count both
+    orders, pairs across two levels one order (T is symmetric), so
+    sum Omega = (g/2)(sum_same |T_ij|^2 + sum_across |T_ij|^2 / 2)."""
+    rng = np.random.default_rng(7)
+    sym = dict(_c1_sym())
+    n = sym["e_thr"].size
+    sym["target"] = np.array([0, 1, 1, 2, 0, 3, 2, 3], dtype=np.int32)
+    sym["g"] = 3.0
+    prop = {"A": sym["a"] + 10.0, "n_sec": 40,
+            "beta": np.stack([_sym_matrix(rng, n, 1.0),
+                              _sym_matrix(rng, n, 4.0)])}
+    got = outer.sweep_propagated(sym, prop, SWEEP_E)
+    for m, E in enumerate(SWEEP_E):
+        K, P = outer.k_matrix_propagated(sym, prop, E)
+        if P.size == 0:
+            assert np.all(got[m] == 0.0)
+            continue
+        T = oracle.t_matrix(K)
+        row = oracle.collision_strengths(T, P, sym["target"], 4, sym["g"])
+        assert np.abs(got[m] - row).max() <= 1e-13 * np.abs(row).max()
+        t = sym["target"][P]
+        same = t[:, None] == t[None, :]
+        T2 = np.abs(T) ** 2
+        flux = 0.5 * sym["g"] * (T2[same].sum() + 0.5 * T2[~same].sum())
+        assert np.isclose(got[m].sum(), flux, rtol=1e-13)
+
+
+def test_sweep_propagated_catches_channel_data_at_a(monkeypatch):
+    """Planted mistake: channel functions taken at r = a instead of A.  The
+    pure-Coulomb pin above must then fail by far more than its bound."""
+    sym = _c1_sym()
+    n = sym["e_thr"].size
+    prop = {"A": sym["a"] + 15.0, "n_sec": 400, "beta": np.zeros((1, n, n))}
+    ref = oracle.sweep(sym, SWEEP_E)["omega"]
+    real = outer.channel_data
+    monkeypatch.setattr(outer, "channel_data",
+                        lambda E, e, l, z, r: real(E, e, l, z, sym["a"]))
+    got = outer.sweep_propagated(sym, prop, SWEEP_E)
+    err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+    assert err > 1e-2

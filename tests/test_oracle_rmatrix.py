@@ -307,3 +307,77 @@ def test_s_matrix_eigenvalues_are_exp_of_twice_the_eigenphases():
     for dd in (-1.2, 0.3, 1.5):
         S = oracle.s_matrix(np.array([[np.tan(dd)]]))
         assert abs(S[0, 0] - np.exp(2j * dd)) < 1e-12
+
+
+def _pole_sum_exact(E_pole, w, a, E):
+    """R(E) in exact rational arithmetic from the FP64 inputs (each double
+    is a rational), rounded once at the end: the reference the FP64 product
+    must reach to within its own rounding."""
+    from fractions import Fraction
+    n, nh = w.shape
+    Ef = Fraction(float(E))
+    inv2a = Fraction(1) / (2 * Fraction(float(a)))
+    d = [1 / (Fraction(float(ek)) - Ef) for ek in E_pole]
+    W = [[Fraction(float(w[i, k])) for k in range(nh)] for i in range(n)]
+    out = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            out[i, j] = float(inv2a * sum(W[i][k] * W[j][k] * d[k]
+                                          for k in range(nh)))
+    return out
+
+
+def _pole_sum_fsum(E_pole, w, a, E):
+    """R(E) term by term with math.fsum (one correctly rounded sum per
+    entry of the FP64 terms)."""
+    n = w.shape[0]
+    out = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            out[i, j] = math.fsum(float(w[i, k]) * float(w[j, k]) / (ek - E)
+                                  for k, ek in enumerate(E_pole)) / (2.0 * a)
+    return out
+
+
+@pytest.mark.parametrize("seed,n,nh", [(31, 1, 1), (32, 3, 17), (33, 4, 32)])
+def test_pole_sum_brute_force_tiny(seed, n, nh):
+    """Sec. 6, Eq. 1: the oracle's product R = X Y / (2a) against the pole
+    sum written out term by term, in exact rational arithmetic and with
+    math.fsum, on tiny systems (n <= 4, N_H <= 32, M <= 16) whose energies
+    include points 1e-6 Ry from a pole, where one term dominates the rest
+    by five orders of magnitude.  Normwise bound 1e-14."""
+    rng = np.random.default_rng(seed)
+    E_pole = np.sort(rng.uniform(-2.0, 30.0, nh))
+    w = rng.normal(0.0, 0.1, (n, nh))
+    a = 20.0
+    E = np.concatenate([rng.uniform(-1.0, 25.0, 12),
+                        E_pole[[0, nh // 2]] + 1e-6,
+                        E_pole[[nh - 1, nh // 3]] - 1e-6])[:16]
+    R = oracle.r_matrix(E_pole, w, a, E)
+    for m, e in enumerate(E):
+        exact = _pole_sum_exact(E_pole, w, a, e)
+        fs = _pole_sum_fsum(E_pole, w, a, e)
+        scale = np.abs(exact).max()
+        assert np.abs(fs - exact).max() <= 1e-15 * scale
+        assert np.abs(R[m] - exact).max() <= 1e-14 * scale
+
+
+def test_pole_sum_brute_force_catches_planted_mistakes():
+    """A dropped first term (an off-by-one in the pole loop), a flipped sign
+    of d_k and 1/a in place of 1/(2a) each miss the brute-force pole sum by
+    far more than the 1e-14 bound of the pin above."""
+    rng = np.random.default_rng(34)
+    n, nh, a = 3, 9, 20.0
+    E_pole = np.sort(rng.uniform(-2.0, 30.0, nh))
+    w = rng.normal(0.0, 0.1, (n, nh))
+    e = E_pole[4] + 1e-6
+    exact = _pole_sum_exact(E_pole, w, a, e)
+    scale = np.abs(exact).max()
+    d = 1.0 / (E_pole - e)
+    wrong = [
+        (w[:, 1:] * d[None, 1:]) @ w[:, 1:].T / (2 * a),          # dropped term
+        (w * -d[None, :]) @ w.T / (2 * a),                         # sign of d_k
+        (w * d[None, :]) @ w.T / a,                                # 1/a for 1/(2a)
+    ]
+    for Rw in wrong:
+        assert np.abs(Rw - exact).max() > 1e-10 * scale
