@@ -164,6 +164,30 @@ int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
                       const double *E, int64_t M, const rm_opts *opts,
                       double *omega, int32_t *status, void *stream);
 
+/* rm_sweep_energies without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * rm_sweep_energies.  Its workspace (the per-energy matching systems, the
+ * channel slots, the pole-sum work tables and counters) lives in one static
+ * device array of RM_NOALLOC_SCRATCH_BYTES, which every GPU the library
+ * runs on holds until the process ends; the mesh is swept in chunks of as
+ * many energies as that array holds (about 270 at 200 channels), so large
+ * symmetries run with fewer energies in flight than rm_sweep_energies.
+ * Differences: RM_FLAG_AUTOTUNE returns RM_ERR_ARG (timing allocates); the
+ * pair form of the pole sum is used only where its products are already
+ * resident (formed by an earlier allocating call), else the scaled-W
+ * kernels; symmetries whose single energy (or whose tables and counters)
+ * do not fit return RM_ERR_ARG.  The call synchronises `stream` once, after
+ * copying its tables into the array, then enqueues the sweep.  Every call
+ * on a GPU shares that GPU's array and leaves its contents behind: calls
+ * that overlap on one GPU (other streams or host threads) race and must be
+ * serialised by the caller. */
+#define RM_NOALLOC_SCRATCH_BYTES (256u << 20)
+int rm_sweep_energies_noalloc(const rm_sym_t *syms, int32_t n_sym,
+                              int32_t n_target, const double *E, int64_t M,
+                              const rm_opts *opts, double *omega,
+                              int32_t *status, void *stream);
+
 /* Captured sweep.  rm_plan_create validates like rm_sweep_energies, orders
  * the symmetries by cost, sizes the chunks and the workspace (owned by the
  * plan), builds the grouped pole-sum work tables (largest symmetries first),

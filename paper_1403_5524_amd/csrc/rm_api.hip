@@ -381,6 +381,7 @@ struct Plan {
   int *counters = nullptr;         // one per chunk (match kernel)
   int match_grid = 0;
   bool owns_async = false;         // workspace from hipMallocAsync
+  bool in_arena = false;           // tables and workspace in an Arena
   hipStream_t alloc_stream = nullptr;
   // graph
   hipGraph_t graph = nullptr;
@@ -409,6 +410,15 @@ static void plan_free_device(Plan &p) {
   p.exec = nullptr;
   p.graph = nullptr;
   p.cap_stream = nullptr;
+  if (p.in_arena) {  // nothing of the plan's device memory is its own
+    p.sets.clear();
+    p.d_syms = nullptr;
+    p.d_work_off = p.d_chan_off = nullptr;
+    p.work = nullptr;
+    p.chan = nullptr;
+    p.counters = nullptr;
+    return;
+  }
   for (auto &set : p.sets)
     for (int t = 0; t < 2; ++t)
       if (set.d_items[t]) (void)hipFree(set.d_items[t]);
@@ -717,11 +727,41 @@ static double workspace_budget(double base) {
   return std::max(base, std::min(0.4 * (double)free_b, 96.0e9));
 }
 
+// A fixed device buffer handed out front to back (256-byte aligned pieces).
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  template <class T>
+  bool take(T **out, size_t bytes) {
+    const size_t at = (used + 255) & ~(size_t)255;
+    if (at > cap || bytes > cap - at) return false;
+    *out = (T *)(base + at);
+    used = at + bytes;
+    return true;
+  }
+};
+
+// Variant of a symmetry for a sweep that may not allocate: the pair form
+// only where its products are already resident, no autotuning.
+static int pick_variant_noalloc(const Sym &s, const rm_opts &o) {
+  if (o.prec == RM_PREC_FP64) {
+    const bool pd = (o.flags & RM_FLAG_PAIR_PRODUCTS) && s.P64;
+    return pd ? PS_PD64 : PS_F64_T32_E16;
+  }
+  const bool have = o.prec == RM_PREC_BF16X3 ? s.Ph != nullptr : s.P32 != nullptr;
+  return (have && !(o.flags & RM_FLAG_NO_PAIR_PRODUCTS)) ? PS_PD
+                                                         : default_variant(o.prec);
+}
+
 // Build a plan: orders symmetries, allocates tables and workspace.
 // async: workspace from the stream-ordered allocator on st (eager calls).
+// arena (non-null): every table and the workspace come from it instead, the
+// tables are uploaded with copies on st, nothing is allocated, and the
+// chunk length is what the arena's remaining space holds.
 static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
                       const double *E, int64_t M, const rm_opts &o,
-                      hipStream_t st, bool async, double ws_budget) {
+                      hipStream_t st, bool async, double ws_budget,
+                      Arena *arena = nullptr) {
   p.o = o;
   p.n_target = n_target;
   p.M = M;
@@ -736,6 +776,10 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   p.device = v[0]->device;
   p.variant.resize(v.size());
   for (size_t q = 0; q < v.size(); ++q) {
+    if (arena) {
+      p.variant[q] = pick_variant_noalloc(*v[q], o);
+      continue;
+    }
     int rc = pick_variant(*const_cast<Sym *>(v[q]), o, E, M, st, &p.variant[q]);
     if (rc) return rc;
   }
@@ -753,48 +797,100 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   p.chan_estride = cacc;
   p.h_work_off = woff;
   for (const Sym *q : v) p.propagate = p.propagate || q->n_sec > 0;
-  int64_t C = o.chunk > 0 ? o.chunk
-                          : (int64_t)(ws_budget / (8.0 * wacc + 32.0 * cacc + 64.0));
-  C = std::max<int64_t>(1, std::min<int64_t>(C, 4096));
-  if (o.chunk <= 0) C = std::max<int64_t>(std::min<int64_t>(64, M), C);
+  const double per_energy = 8.0 * wacc + 32.0 * cacc;  // workspace + slots
+  int64_t C;
+  if (arena) {
+    // what the arena holds after the tables (bounded by the item tables of
+    // the largest chunk: at most one item per tile and energy, 16 bytes,
+    // plus a counter per chunk)
+    const double tables = (double)sd.size() * (sizeof(SymDev) + 16) + 65536.0;
+    const double room = (double)arena->cap - tables;
+    double tiles = 0.0;
+    {
+      std::vector<std::pair<int, int>> tl;
+      for (size_t q = 0; q < v.size(); ++q) {
+        ps_tiles(*v[q], p.variant[q], tl);
+        tiles += (double)tl.size();
+      }
+    }
+    // per energy: workspace, slots, and the pole-sum items of a full and a
+    // tail chunk (one per tile and energy group, at most one per energy),
+    // plus the per-chunk counters for M / C chunks
+    const double per = per_energy + 2.0 * tiles * sizeof(PsItem) + 512.0;
+    C = room > per ? (int64_t)(room / per) : 0;
+    if (o.chunk > 0) C = std::min<int64_t>(C, o.chunk);
+    if (C < 1)
+      return fail(RM_ERR_ARG, "one energy of these symmetries needs %.0f bytes "
+                  "of scratch, over the %zu-byte limit", per + tables, arena->cap);
+    C = std::min<int64_t>(C, 4096);
+  } else {
+    C = o.chunk > 0 ? o.chunk : (int64_t)(ws_budget / (per_energy + 64.0));
+    C = std::max<int64_t>(1, std::min<int64_t>(C, 4096));
+    if (o.chunk <= 0) C = std::max<int64_t>(std::min<int64_t>(64, M), C);
+  }
   C = std::min<int64_t>(C, std::max<int64_t>(M, 1));
   p.C = C;
   p.n_chunks = (int)((M + C - 1) / C);
   p.tail = M - (int64_t)(p.n_chunks - 1) * C;
-  hipError_t e = hipMalloc(&p.d_syms, sd.size() * sizeof(SymDev));
-  if (e == hipSuccess) e = hipMalloc(&p.d_work_off, woff.size() * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMalloc(&p.d_chan_off, coff.size() * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMemcpy(p.d_syms, sd.data(), sd.size() * sizeof(SymDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p.d_work_off, woff.data(), woff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p.d_chan_off, coff.data(), coff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  p.in_arena = arena != nullptr;
+  hipError_t e = hipSuccess;
+  // device memory for a table: from the arena or hipMalloc
+  auto get = [&](void **ptr, size_t bytes) -> hipError_t {
+    if (!arena) return hipMalloc(ptr, bytes);
+    return arena->take(ptr, bytes) ? hipSuccess : hipErrorOutOfMemory;
+  };
+  auto put = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+    return arena ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st)
+                 : hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  e = get((void **)&p.d_syms, sd.size() * sizeof(SymDev));
+  if (e == hipSuccess) e = get((void **)&p.d_work_off, woff.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = get((void **)&p.d_chan_off, coff.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = put(p.d_syms, sd.data(), sd.size() * sizeof(SymDev));
+  if (e == hipSuccess) e = put(p.d_work_off, woff.data(), woff.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = put(p.d_chan_off, coff.data(), coff.size() * sizeof(int64_t));
   std::vector<int> vars(p.variant.begin(), p.variant.end());
   std::sort(vars.begin(), vars.end());
   vars.erase(std::unique(vars.begin(), vars.end()), vars.end());
+  std::vector<std::vector<PsItem>> staged;  // host tables alive until synced
   for (int var : vars) {
     if (e != hipSuccess) break;
     Plan::ItemSet set;
     set.variant = var;
     for (int t = 0; t < 2; ++t) {
       const int64_t m = (t == 0) ? C : p.tail;
-      std::vector<PsItem> items;
+      staged.emplace_back();
+      std::vector<PsItem> &items = staged.back();
       build_items(p, var, m, items);
       set.n_items[t] = (int)items.size();
       if (items.empty()) continue;
-      e = hipMalloc(&set.d_items[t], items.size() * sizeof(PsItem));
+      e = get((void **)&set.d_items[t], items.size() * sizeof(PsItem));
       if (e == hipSuccess)
-        e = hipMemcpy(set.d_items[t], items.data(), items.size() * sizeof(PsItem), hipMemcpyHostToDevice);
+        e = put(set.d_items[t], items.data(), items.size() * sizeof(PsItem));
+      if (e != hipSuccess) break;
     }
     p.sets.push_back(set);
   }
+  // the host tables go out of scope here: wait for their copies
+  if (arena && e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess)
-    return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
+    return fail(e == hipErrorOutOfMemory ? (arena ? RM_ERR_ARG : RM_ERR_NOMEM)
+                                         : RM_ERR_HIP,
                 "plan tables: %s", hipGetErrorString(e));
   const size_t wbytes = (size_t)(C * wacc) * sizeof(double);
   const size_t cbytes = (size_t)(C * cacc) * sizeof(ChanSlot);
   const size_t kbytes = (size_t)std::max(1, p.n_chunks) * sizeof(int);
-  p.owns_async = async;
+  p.owns_async = async && !arena;
   p.alloc_stream = st;
-  if (async) {
+  if (arena) {
+    e = arena->take(&p.work, wbytes) && arena->take(&p.chan, cbytes) &&
+                arena->take(&p.counters, kbytes)
+            ? hipSuccess
+            : hipErrorOutOfMemory;
+    if (e != hipSuccess)
+      return fail(RM_ERR_ARG, "workspace of %zu bytes does not fit the "
+                  "%zu-byte scratch", wbytes + cbytes, arena->cap);
+  } else if (async) {
     e = hipMallocAsync((void **)&p.work, wbytes, st);
     if (e == hipSuccess) e = hipMallocAsync((void **)&p.chan, cbytes, st);
     if (e == hipSuccess) e = hipMallocAsync((void **)&p.counters, kbytes, st);
@@ -1136,6 +1232,73 @@ int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
   Plan p;
   rc = plan_build(p, syms, n_sym, n_target, E, M, o, st, true,
                   workspace_budget(16.0e9));
+  if (!rc) {
+    p.E = E;
+    p.omega = omega;
+    p.status = status;
+    rc = plan_enqueue(p, st);
+  }
+  plan_free_device(p);
+  return rc;
+}
+
+}  // extern "C"
+
+namespace rmx {
+
+// The workspace of rm_sweep_energies_noalloc: one static device array per
+// GPU.  In host code `scratch` names a host-side stand-in, never the device
+// memory: kernels and copies use the address hipGetSymbolAddress returns
+// for the current device, looked up once per device.
+static __device__ __align__(256) char scratch[RM_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_ptr;
+
+static int scratch_arena(Arena &a) {
+  int dev = 0;
+  RM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RM_ERR_HIP, "scratch address on device %d: %s", dev,
+                  hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, (char *)ptr).first;
+  }
+  a.base = it->second;
+  a.cap = RM_NOALLOC_SCRATCH_BYTES;
+  a.used = 0;
+  return RM_OK;
+}
+
+}  // namespace rmx
+
+extern "C" {
+
+int rm_sweep_energies_noalloc(const rm_sym_t *syms, int32_t n_sym,
+                              int32_t n_target, const double *E, int64_t M,
+                              const rm_opts *opts, double *omega,
+                              int32_t *status, void *stream) {
+  if (M < 0) return fail(RM_ERR_ARG, "M < 0");
+  rm_opts o;
+  int rc = check_opts(opts, &o);
+  if (rc) return rc;
+  if (o.flags & RM_FLAG_AUTOTUNE)
+    return fail(RM_ERR_ARG, "RM_FLAG_AUTOTUNE allocates: not available "
+                            "without allocation");
+  if (!syms || n_sym < 1 || n_target < 1) return validate_syms(syms, n_sym, n_target);
+  for (int q = 0; q < n_sym; ++q)
+    if (!syms[q]) return fail(RM_ERR_ARG, "null handle %d", q);
+  if (M > 0 && (!E || !omega)) return fail(RM_ERR_ARG, "null E or omega");
+  if ((rc = validate_syms(syms, n_sym, n_target))) return rc;
+  if (M == 0) return RM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Arena arena;
+  if ((rc = scratch_arena(arena))) return rc;
+  Plan p;
+  rc = plan_build(p, syms, n_sym, n_target, E, M, o, st, false, 0.0, &arena);
   if (!rc) {
     p.E = E;
     p.omega = omega;

@@ -26,6 +26,7 @@ RM_FLAG_NO_PAIR_PRODUCTS = 0x2
 RM_FLAG_PAIR_PRODUCTS = 0x4
 
 EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
+            "rm_sweep_energies_noalloc",
             "rm_kmatrix", "rm_collision_strengths", "rm_rmatrix",
             "rm_channel_functions", "rm_profile", "rm_profile_query",
             "rm_mlp_create", "rm_mlp_free", "rm_mlp_n_params",
@@ -87,6 +88,9 @@ def lib():
         L.rm_sym_info.argtypes = [vp, vp, vp, vp]
         L.rm_sweep_energies.argtypes = [vp, i32, i32, vp, i64,
                                         ctypes.POINTER(Opts), vp, vp, vp]
+        L.rm_sweep_energies_noalloc.argtypes = [vp, i32, i32, vp, i64,
+                                                ctypes.POINTER(Opts), vp, vp,
+                                                vp]
         L.rm_kmatrix.argtypes = [vp, vp, i64, ctypes.POINTER(Opts), vp, vp,
                                  vp, vp, vp]
         L.rm_collision_strengths.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp]
@@ -258,6 +262,22 @@ def rm_sweep_energies(syms, n_target, E, opts=None, omega=None, status=None):
     o = opts if opts is not None else make_opts()
     _check(lib().rm_sweep_energies(arr, len(syms), n_target, pE, M,
                                    ctypes.byref(o), po, ps, _stream()))
+    return omega, status
+
+
+def rm_sweep_energies_noalloc(syms, n_target, E, omega, status, opts=None):
+    """rm_sweep_energies with no device allocation inside the library: the
+    caller passes E [M], omega [M, P] and status [M] (CUDA tensors)."""
+    pE = _f64(E, name="E")
+    M = int(E.numel())
+    P = n_target * (n_target + 1) // 2
+    po = _f64(omega, M * P, "omega")
+    ps = _i32(status, M, "status")
+    arr = (ctypes.c_void_p * len(syms))(*[s.handle for s in syms])
+    o = opts if opts is not None else make_opts()
+    _check(lib().rm_sweep_energies_noalloc(arr, len(syms), n_target, pE, M,
+                                           ctypes.byref(o), po, ps,
+                                           _stream()))
     return omega, status
 
 
