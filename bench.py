@@ -482,9 +482,11 @@ def main():
     ap.add_argument("--M", type=int, default=100000)
     ap.add_argument("--err-sample", type=int, default=32)
     ap.add_argument("--cpu-sample", type=int, default=1024)
-    ap.add_argument("--also", default="bf16x3,fp32",
+    ap.add_argument("--also", default="bf16x3,fp32,fp32/s32",
                     help="comma-separated precisions also timed on the same "
-                         "workload (reported under other_precisions)")
+                         "workload (reported under other_precisions); a "
+                         "\"/s32\" suffix also factors the matching solve "
+                         "in FP32 with FP64 refinement")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
                     help="c2 is the headline workload; c3 (40 symmetries) "
@@ -565,13 +567,17 @@ def main():
             ref = r if ref is None else ref + r
     idx_dev = torch.as_tensor(idx, device=dev)
 
-    def run(prec, graph):
-        """Warm up, time `steps` sweeps at one precision, check Omega."""
-        opts = native.make_opts(prec=PREC_CODE[prec])
+    def run(name, graph):
+        """Warm up, time `steps` sweeps at one precision, check Omega.
+        `name` is a pole-sum precision, optionally with "/s32": the
+        matching solve factored in FP32 and refined in FP64."""
+        prec, _, solve = name.partition("/")
+        opts = native.make_opts(prec=PREC_CODE[prec],
+                                solve_fp32=1 if solve == "s32" else 0)
         for i in range(args.warmup):
             native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
             torch.cuda.synchronize()
-            note("%s warmup %d done" % (prec, i + 1))
+            note("%s warmup %d done" % (name, i + 1))
         native.rm_profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -581,7 +587,7 @@ def main():
         t1 = time.perf_counter()
         native.rm_profile(False)
         ms = (t1 - t0) * 1e3 / args.steps
-        note("%s: timed %d steps: %.2f ms/step" % (prec, args.steps, ms))
+        note("%s: timed %d steps: %.2f ms/step" % (name, args.steps, ms))
         stage = {k: native.rm_profile_query(k) for k in ("polesum", "match")}
         graph_ms = None
         if graph:
@@ -594,12 +600,12 @@ def main():
             torch.cuda.synchronize()
             graph_ms = (time.perf_counter() - g0) * 1e3 / args.steps
             plan.free()
-            note("%s: graph replays %.2f ms/step" % (prec, graph_ms))
+            note("%s: graph replays %.2f ms/step" % (name, graph_ms))
         got = omega[idx_dev].cpu().numpy()
         err, err_el = omega_errors(got, ref)
         st = status.cpu().numpy()
         note("%s: max rel err of Omega on %d sampled energies: %.3e "
-             "normwise, %.3e elementwise" % (prec, idx.size, err, err_el))
+             "normwise, %.3e elementwise" % (name, idx.size, err, err_el))
         kernels = {}
         for key, flops, peak, stg, tkey in (
                 ("polesum_%s" % prec, flops_step, PEAK[prec], "polesum",

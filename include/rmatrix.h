@@ -55,7 +55,18 @@ enum rm_status {
  *         each term is then that of a slightly moved pole with slightly
  *         changed amplitudes, not an independent error per matrix entry);
  *   far   the rest: the MFMA precision below with FP32 accumulation.
- * The matching solve is FP64 unless rm_opts.solve_fp32 is set. */
+ * The matching solve is FP64 unless rm_opts.solve_fp32 is set: then the
+ * system (D1 - R D2)[K; X] = R[:, P] diag(a s'_P) - [diag(s_P); 0] of each
+ * energy is rounded to FP32, LU-factored with partial pivoting and solved in
+ * FP32, and the solution refined in FP64 (residual from R in FP64, each
+ * correction solved with the FP32 factors) until a correction is below
+ * 2^-50 max|[K; X]|, or the corrections stop contracting at a residual with
+ * max|r| <= 4 sqrt(n) 2^-53 ||D1 - R D2||_inf max|[K; X]| (the backward-
+ * error test of LAPACK's dsgesv), within refine_iters corrections;
+ * otherwise (cond u_32 near 1: at 200 channels, energies within about 1e-6
+ * Ry of a pole) that energy gets RM_E_REFINE_NOCONV and is solved again
+ * with the FP64 factorisation, as dsgesv falls back.  The T step stays
+ * FP64. */
 enum rm_precision {
   RM_PREC_FP64 = 0,    /* FP64 MFMA over every pole                          */
   RM_PREC_FP32 = 1,    /* FP32 MFMA, FP32 accumulation, far poles only       */
@@ -70,7 +81,9 @@ enum rm_precision {
 #define RM_E_CF_NOCONV      0x04  /* a channel-function iteration hit its cap*/
 #define RM_E_NONFINITE      0x08  /* non-finite value in K or T             */
 #define RM_E_ON_THRESHOLD   0x10  /* E equals a channel threshold exactly   */
-#define RM_E_REFINE_NOCONV  0x20  /* reserved                               */
+#define RM_E_REFINE_NOCONV  0x20  /* FP32 solve: refinement did not reach
+                                     the FP64 test; the energy was solved
+                                     again in FP64 (below)                 */
 
 typedef struct rm_sym *rm_sym_t;  /* one symmetry, device-resident, opaque */
 
@@ -105,9 +118,10 @@ typedef struct {
 typedef struct {
   int32_t prec;          /* rm_precision                                   */
   double near_delta;     /* Ry, mixed precisions only; 0 -> 1e-3           */
-  int32_t solve_fp32;    /* must be 0: the matching solve is FP64 (a
-                            nonzero value returns RM_ERR_ARG)              */
-  int32_t refine_iters;  /* reserved, must be >= 0                         */
+  int32_t solve_fp32;    /* 0: the matching solve in FP64; 1: factored in
+                            FP32 and refined in FP64 (below)               */
+  int32_t refine_iters;  /* FP32 solve: at most this many FP64 corrections
+                            (0 -> 8, at most 100)                          */
   int32_t chunk;         /* energies per internal chunk; 0 -> automatic    */
   uint32_t flags;        /* RM_FLAG_* bits                                 */
   double band_delta;     /* Ry, mixed precisions only: the outer edge of the

@@ -44,6 +44,31 @@ constexpr int WPB = 4;   // wavefronts per workgroup
 constexpr int UNR = 4;   // independent elements per lane per batch
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Element types of the wavefront linear algebra: FP64 (the default path) and
+// FP32 (the factorisation of the FP32 solve, refined in FP64).  The 16x16x4
+// MFMAs of both read A[i][k] and B[k][j] at i = j = lane % 16, k = lane / 16;
+// their 16x16 results differ in layout: FP64 row kq + 4r, FP32 row 4kq + r
+// of register r (kq = lane / 16).
+template <class T>
+struct Mx;
+template <>
+struct Mx<double> {
+  typedef d4 acc;
+  __device__ static inline acc mfma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int kq, int r) { return kq + 4 * r; }
+};
+template <>
+struct Mx<float> {
+  typedef f4 acc;
+  __device__ static inline acc mfma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int kq, int r) { return 4 * kq + r; }
+};
 
 // Per-wavefront LDS: the diagonal block of the current two panels, its
 // inverse, and the row moves of their interchanges.
@@ -74,12 +99,17 @@ __device__ inline double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ inline float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // Wavefront argmax of a = |v| (ties -> smaller index), carrying v.
-__device__ inline void wave_argmax(double &a, double &v, int &idx) {
+template <class T>
+__device__ inline void wave_argmax(T &a, T &v, int &idx) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    const double oa = __shfl_xor(a, off);
-    const double ov = __shfl_xor(v, off);
+    const T oa = __shfl_xor(a, off);
+    const T ov = __shfl_xor(v, off);
     const int oi = __shfl_xor(idx, off);
     if (oa > a || (oa == a && oi < idx)) {
       a = oa;
@@ -102,8 +132,9 @@ __device__ inline int wave_or(int v) {
 //   MODE 2: C = A B
 // The wavefront walks 32 x 32 output tiles (2 x 2 MFMA blocks sharing their
 // A and B fragments) in k-steps of 16.
+template <class T>
 struct Frag {
-  double a[4][2], b[4][2];
+  T a[4][2], b[4][2];
 };
 
 // Operand storage flags of wave_gemm.
@@ -111,9 +142,9 @@ constexpr int G_TA = 1;     // A[i][k] stored at A[k * lda + i]
 constexpr int G_TB = 2;     // B[k][j] stored at B[j * ldb + k]
 constexpr int G_LOWER = 4;  // only the tiles of C that meet its lower triangle
 
-template <int FL>
-__device__ inline void frag_load(Frag &f, const double *A, int lda,
-                                 const double *B, int ldb, int rows, int cols,
+template <int FL, class T>
+__device__ inline void frag_load(Frag<T> &f, const T *A, int lda,
+                                 const T *B, int ldb, int rows, int cols,
                                  int kd, int rb, int cb, int k0) {
   const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
@@ -123,24 +154,25 @@ __device__ inline void frag_load(Frag &f, const double *A, int lda,
     const int k = k0 + 4 * s + kq;
     const bool kv = k < kd;
     if (FL & G_TA) {
-      f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)k * lda + ra0] : 0.0;
-      f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)k * lda + ra1] : 0.0;
+      f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)k * lda + ra0] : T(0);
+      f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)k * lda + ra1] : T(0);
     } else {
-      f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)ra0 * lda + k] : 0.0;
-      f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)ra1 * lda + k] : 0.0;
+      f.a[s][0] = (kv && ra0 < rows) ? A[(int64_t)ra0 * lda + k] : T(0);
+      f.a[s][1] = (kv && ra1 < rows) ? A[(int64_t)ra1 * lda + k] : T(0);
     }
     if (FL & G_TB) {
-      f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)c0 * ldb + k] : 0.0;
-      f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)c1 * ldb + k] : 0.0;
+      f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)c0 * ldb + k] : T(0);
+      f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)c1 * ldb + k] : T(0);
     } else {
-      f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)k * ldb + c0] : 0.0;
-      f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)k * ldb + c1] : 0.0;
+      f.b[s][0] = (kv && c0 < cols) ? B[(int64_t)k * ldb + c0] : T(0);
+      f.b[s][1] = (kv && c1 < cols) ? B[(int64_t)k * ldb + c1] : T(0);
     }
   }
 }
 
-// FP64 16x16x4 result layout: D[i][j] at j = lane % 16, i = lane / 16 + 4 r.
-__device__ inline void ctile_load(double (&c)[2][2][4], const double *C,
+// C tile in the result layout of the type's 16x16x4 MFMA (Mx<T>::row).
+template <class T>
+__device__ inline void ctile_load(T (&c)[2][2][4], const T *C,
                                   int ldc, int rows, int cols, int rb, int cb) {
   const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
@@ -150,8 +182,8 @@ __device__ inline void ctile_load(double (&c)[2][2][4], const double *C,
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = rb + 16 * x + kq + 4 * r, j = cb + 16 * y + col;
-        c[x][y][r] = (i < rows && j < cols) ? C[(int64_t)i * ldc + j] : 0.0;
+        const int i = rb + 16 * x + Mx<T>::row(kq, r), j = cb + 16 * y + col;
+        c[x][y][r] = (i < rows && j < cols) ? C[(int64_t)i * ldc + j] : T(0);
       }
 }
 
@@ -165,28 +197,29 @@ __device__ inline int gemm_next_tile(int t, int nct, int ntile) {
   return t;
 }
 
-template <int MODE, int FL = 0>
-__device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
-                          const double *B, int ldb, int rows, int cols,
+template <int MODE, int FL = 0, class T = double>
+__device__ void wave_gemm(T *C, int ldc, const T *A, int lda,
+                          const T *B, int ldb, int rows, int cols,
                           int kd) {
+  typedef typename Mx<T>::acc acc_t;
   const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
   const int nct = (cols + 31) >> 5;
   const int ntile = ((rows + 31) >> 5) * nct;
   const int nk = max(1, (kd + 15) >> 4);
   if (ntile > 0) {
-    Frag cur, nxt;
-    double cv[2][2][4], cn[2][2][4];
+    Frag<T> cur, nxt;
+    T cv[2][2][4], cn[2][2][4];
     frag_load<FL>(cur, A, lda, B, ldb, rows, cols, kd, 0, 0, 0);
     if (MODE == 0) ctile_load(cv, C, ldc, rows, cols, 0, 0);
     for (int t = 0; t < ntile;) {
       const int tn = gemm_next_tile<FL>(t, nct, ntile);
       const int rb = (t / nct) * 32, cb = (t % nct) * 32;
-      d4 acc[2][2];
+      acc_t acc[2][2];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < 2; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
       for (int kc = 0; kc < nk; ++kc) {
         // prefetch: the next k-step of this tile, else the next tile (whose
         // A, B and C do not overlap this tile's C)
@@ -203,8 +236,7 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
           for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y)
-              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                  cur.a[s][x], cur.b[s][y], acc[x][y], 0, 0, 0);
+              acc[x][y] = Mx<T>::mfma(cur.a[s][x], cur.b[s][y], acc[x][y]);
         cur = nxt;
       }
 #pragma unroll
@@ -213,11 +245,11 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
         for (int y = 0; y < 2; ++y)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = rb + 16 * x + kq + 4 * r, j = cb + 16 * y + col;
+            const int i = rb + 16 * x + Mx<T>::row(kq, r), j = cb + 16 * y + col;
             if (i >= rows || j >= cols) continue;
-            double v = acc[x][y][r];
+            T v = acc[x][y][r];
             if (MODE == 0) v = cv[x][y][r] - v;
-            if (MODE == 1 && i == j) v += 1.0;
+            if (MODE == 1 && i == j) v += T(1);
             C[(int64_t)i * ldc + j] = v;
           }
       if (MODE == 0) {
@@ -241,21 +273,22 @@ __device__ void wave_gemm(double *C, int ldc, const double *A, int lda,
 // interchanges swap the row segments [sw0, j0 + jb) (the panel and the L
 // columns of an earlier panel of the same block); pivots -> W.piv[po + .].
 // Returns 1 if a pivot was zero or not a number.
-__device__ int wave_panel(double *A, int na, int ld, int j0, int jb, int sw0,
+template <class T>
+__device__ int wave_panel(T *A, int na, int ld, int j0, int jb, int sw0,
                           int po, WaveLds &W) {
   const int lane = lane_id();
   int flag = 0;
 #pragma unroll 1
   for (int jj = 0; jj < jb; ++jj) {
     const int col = j0 + jj;
-    double ba = -1.0, bv = 0.0;
+    T ba = T(-1), bv = T(0);
     int bi = na;
     for (int r0 = col + lane; r0 < na; r0 += UNR * WT) {
-      double v[UNR];
+      T v[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int r = r0 + u * WT;
-        v[u] = r < na ? A[(int64_t)r * ld + col] : 0.0;
+        v[u] = r < na ? A[(int64_t)r * ld + col] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
@@ -269,20 +302,20 @@ __device__ int wave_panel(double *A, int na, int ld, int j0, int jb, int sw0,
     }
     wave_argmax(ba, bv, bi);
     int pr = bi;
-    double pv = bv;
+    T pv = bv;
     if (pr >= na) {  // every candidate is NaN
       pr = col;
-      pv = __builtin_nan("");
+      pv = (T)__builtin_nan("");
     }
     if (lane == 0) W.piv[po + jj] = pr;
     // swap the segments [sw0, j0 + jb) of rows col and pr; lane q keeps the
     // new pivot row's element of panel column j0 + q
     const int sw = lane + sw0 - j0;  // this lane's column, relative to j0
-    double yv = 0.0;
+    T yv = T(0);
     if (sw < jb) {
-      double *x = A + (int64_t)col * ld + j0 + sw;
-      double *y = A + (int64_t)pr * ld + j0 + sw;
-      const double xv = *x;
+      T *x = A + (int64_t)col * ld + j0 + sw;
+      T *y = A + (int64_t)pr * ld + j0 + sw;
+      const T xv = *x;
       yv = *y;
       if (pr != col) {
         *x = yv;
@@ -290,27 +323,27 @@ __device__ int wave_panel(double *A, int na, int ld, int j0, int jb, int sw0,
       }
     }
     // the lane that swapped panel column j0 + q holds its pivot-row value
-    const double prow = __shfl(yv, min(lane + j0 - sw0, WT - 1));
+    const T prow = __shfl(yv, min(lane + j0 - sw0, WT - 1));
     wave_sync();
-    if (!(fabs(pv) > 0.0)) flag = 1;
-    const double inv = 1.0 / pv;
-    double pc[NB];
+    if (!(fabs(pv) > T(0))) flag = 1;
+    const T inv = T(1) / pv;
+    T pc[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) pc[q] = read_lane(prow, q);
     // eliminate below the pivot, two rows per lane per batch
     for (int r0 = col + 1 + lane; r0 < na; r0 += 2 * WT) {
       const int r1 = r0 + WT;
-      double *p0 = A + (int64_t)r0 * ld + j0;
-      double *p1 = A + (int64_t)r1 * ld + j0;
+      T *p0 = A + (int64_t)r0 * ld + j0;
+      T *p1 = A + (int64_t)r1 * ld + j0;
       const bool h1 = r1 < na;
-      double x0[NB], x1[NB];
+      T x0[NB], x1[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const bool in = q >= jj && q < jb;
-        x0[q] = in ? p0[q] : 0.0;
-        x1[q] = (in && h1) ? p1[q] : 0.0;
+        x0[q] = in ? p0[q] : T(0);
+        x1[q] = (in && h1) ? p1[q] : T(0);
       }
-      double l0 = 0.0, l1 = 0.0;
+      T l0 = T(0), l1 = T(0);
 #pragma unroll
       for (int q = 0; q < NB; ++q)
         if (q == jj) {
@@ -320,8 +353,8 @@ __device__ int wave_panel(double *A, int na, int ld, int j0, int jb, int sw0,
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         if (q < jj || q >= jb) continue;
-        const double v0 = q == jj ? l0 : fma(-l0, pc[q], x0[q]);
-        const double v1 = q == jj ? l1 : fma(-l1, pc[q], x1[q]);
+        const T v0 = q == jj ? l0 : fma(-l0, pc[q], x0[q]);
+        const T v1 = q == jj ? l1 : fma(-l1, pc[q], x1[q]);
         p0[q] = v0;
         if (h1) p1[q] = v1;
       }
@@ -338,21 +371,34 @@ __device__ int wave_panel(double *A, int na, int ld, int j0, int jb, int sw0,
 // trip.  Interchanges swap rows of the panel only.
 constexpr int PR_T = 4;  // panel rows per lane
 typedef double d16 __attribute__((ext_vector_type(16)));
+typedef float fv16 __attribute__((ext_vector_type(16)));
+template <class T>
+struct V16;
+template <>
+struct V16<double> {
+  typedef d16 t;
+};
+template <>
+struct V16<float> {
+  typedef fv16 t;
+};
 
 // x0..x3 are four 16-wide row vectors (not an array, which would be placed
 // in scratch memory); PR_EACH applies M to each with its slot index.
 #define PR_EACH(M) M(0, x0) M(1, x1) M(2, x2) M(3, x3)
 
-__device__ int wave_panel_regs(double *A, int na, int ld, int j0, int jb,
+template <class T>
+__device__ int wave_panel_regs(T *A, int na, int ld, int j0, int jb,
                                int po, WaveLds &W) {
   static_assert(NB == 16, "row vectors hold one 16-column panel");
+  typedef typename V16<T>::t vec;
   const int lane = lane_id();
-  d16 x0, x1, x2, x3;
+  vec x0, x1, x2, x3;
 #define PR_LOAD(t, xv)                                                    \
   {                                                                       \
     const int r = j0 + lane + WT * t;                                     \
     _Pragma("unroll") for (int q = 0; q < NB; ++q) xv[q] =                \
-        (r < na && q < jb) ? A[(int64_t)r * ld + j0 + q] : 0.0;           \
+        (r < na && q < jb) ? A[(int64_t)r * ld + j0 + q] : T(0);          \
   }
   PR_EACH(PR_LOAD)
 #undef PR_LOAD
@@ -361,12 +407,12 @@ __device__ int wave_panel_regs(double *A, int na, int ld, int j0, int jb,
   for (int jj = 0; jj < NB; ++jj) {
     if (jj < jb) {  // uniform; the loop is unrolled so jj is a constant
       const int col = j0 + jj;
-      double ba = -1.0, bv = 0.0;
+      T ba = T(-1), bv = T(0);
       int bi = na;
 #define PR_ARGMAX(t, xv)                                                  \
   {                                                                       \
     const int r = j0 + lane + WT * t;                                     \
-    const double v = xv[jj];                                              \
+    const T v = xv[jj];                                                   \
     if (r >= col && r < na && fabs(v) > ba) {                             \
       ba = fabs(v);                                                       \
       bv = v;                                                             \
@@ -383,12 +429,12 @@ __device__ int wave_panel_regs(double *A, int na, int ld, int j0, int jb,
       const int d = pr - j0;
       const int lp = __builtin_amdgcn_readfirstlane(d & (WT - 1)), tp = d >> 6;
       const bool swap = pr != col, on_p = lane == lp, on_c = lane == jj;
-      d16 pc;
+      vec pc;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const double s = tp == 0 ? x0[q] : tp == 1 ? x1[q] : tp == 2 ? x2[q] : x3[q];
-        const double vp = read_lane(s, lp);      // pivot row
-        const double vc = read_lane(x0[q], jj);  // row col (lane jj, slot 0)
+        const T s = tp == 0 ? x0[q] : tp == 1 ? x1[q] : tp == 2 ? x2[q] : x3[q];
+        const T vp = read_lane(s, lp);      // pivot row
+        const T vc = read_lane((T)x0[q], jj);  // row col (lane jj, slot 0)
         pc[q] = vp;
         // branch-free: the pivot row's slot takes row col, lane jj's slot 0
         // takes the pivot row
@@ -398,14 +444,14 @@ __device__ int wave_panel_regs(double *A, int na, int ld, int j0, int jb,
         x2[q] = (wp && tp == 2) ? vc : x2[q];
         x3[q] = (wp && tp == 3) ? vc : x3[q];
       }
-      const double pv = bad ? __builtin_nan("") : pc[jj];
-      if (!(fabs(pv) > 0.0)) flag = 1;
-      const double inv = 1.0 / pv;
+      const T pv = bad ? (T)__builtin_nan("") : (T)pc[jj];
+      if (!(fabs(pv) > T(0))) flag = 1;
+      const T inv = T(1) / pv;
 #define PR_ELIM(t, xv)                                                    \
   {                                                                       \
     const int r = j0 + lane + WT * t;                                     \
     if (r > col && r < na) {                                              \
-      const double l = xv[jj] * inv;                                      \
+      const T l = xv[jj] * inv;                                           \
       xv[jj] = l;                                                         \
       _Pragma("unroll") for (int q = jj + 1; q < NB; ++q) xv[q] =         \
           fma(-l, pc[q], xv[q]);                                          \
@@ -430,16 +476,17 @@ __device__ int wave_panel_regs(double *A, int na, int ld, int j0, int jb,
 
 // Apply the row moves in W (block positions j0 .. j0+cnt-1) to columns
 // [c0, c1) only, with batched loads before stores.
-__device__ void wave_apply_moves(double *A, int ld, int j0, int cnt, int c0,
+template <class T>
+__device__ void wave_apply_moves(T *A, int ld, int j0, int cnt, int c0,
                                  int c1, const WaveLds &W) {
   const int lane = lane_id();
   const int nout = W.nout;
   for (int c = c0 + lane; c < c1; c += WT) {
-    double xv[NB], yv[NB];
+    T xv[NB], yv[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      xv[q] = q < cnt ? A[(int64_t)W.srcp[q] * ld + c] : 0.0;
-      yv[q] = q < nout ? A[(int64_t)W.osrc[q] * ld + c] : 0.0;
+      xv[q] = q < cnt ? A[(int64_t)W.srcp[q] * ld + c] : T(0);
+      yv[q] = q < nout ? A[(int64_t)W.osrc[q] * ld + c] : T(0);
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -500,8 +547,8 @@ __device__ void wave_tile_invert(WaveLds &W, int kind) {
 // Stage the block's diagonal part of A (rows and columns [j0, j0 + jb)) into
 // W.T with identity padding to NT: its unit lower triangle (lower) or its
 // upper triangle with the diagonal.
-template <int NT>
-__device__ void wave_tile_stage(const double *A, int ld, int j0, int jb,
+template <int NT, class T>
+__device__ void wave_tile_stage(const T *A, int ld, int j0, int jb,
                                 WaveLds &W, int kind) {
   const int lane = lane_id();
   for (int q = lane; q < NT * NT; q += WT) {
@@ -510,7 +557,7 @@ __device__ void wave_tile_stage(const double *A, int ld, int j0, int jb,
     const bool in = kind == TILE_UNIT_LOWER ? j < i
                     : kind == TILE_UPPER    ? j >= i
                                             : j <= i;
-    if (i < jb && j < jb && in) v = A[(int64_t)(j0 + i) * ld + j0 + j];
+    if (i < jb && j < jb && in) v = (double)A[(int64_t)(j0 + i) * ld + j0 + j];
     W.T[i][j] = v;
   }
   wave_sync();
@@ -553,19 +600,20 @@ __device__ void wave_build_moves(WaveLds &W, int j0, int cnt, int po = 0) {
 // rows osrc[m] (m < nout) in the same pass; only rows q < jb are written.
 // 16 x 16 FP64 MFMA blocks over NT/4 k-steps; every load of a batch is
 // issued before any store, so sources and destinations may coincide.
-template <int NT, bool TRANS = false>
-__device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
+template <int NT, bool TRANS = false, class T = double>
+__device__ void wave_tile_apply(T *A, int ld, int j0, int jb, int c0,
                                 int c1, const WaveLds &W, bool moves) {
   constexpr int NS = NT / 4, NRB = NT / 16, CB = NT == 16 ? 4 : 2;
+  typedef typename Mx<T>::acc acc_t;
   const int lane = lane_id();
   const int col = lane & 15, kq = lane >> 4;
-  double ainv[NRB][NS];  // Ti, or its transpose
+  T ainv[NRB][NS];  // Ti, or its transpose
 #pragma unroll
   for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      ainv[rb][s] = TRANS ? W.Ti[4 * s + kq][rb * 16 + col]
-                          : W.Ti[rb * 16 + col][4 * s + kq];
+      ainv[rb][s] = (T)(TRANS ? W.Ti[4 * s + kq][rb * 16 + col]
+                              : W.Ti[rb * 16 + col][4 * s + kq]);
   int srow[NS], orow[NS], drow[NS];
   bool sv[NS], ov[NS];
   const int nout = moves ? W.nout : 0;
@@ -579,28 +627,27 @@ __device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
     drow[s] = ov[s] ? W.opos[q] : 0;
   }
   for (int cb = c0; cb < c1; cb += 16 * CB) {
-    double b[CB][NS], y[CB][NS];
+    T b[CB][NS], y[CB][NS];
 #pragma unroll
     for (int u = 0; u < CB; ++u) {
       const int c = cb + 16 * u + col;
       const bool cv = c < c1;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        b[u][s] = (cv && sv[s]) ? A[(int64_t)srow[s] * ld + c] : 0.0;
-        y[u][s] = (cv && ov[s]) ? A[(int64_t)orow[s] * ld + c] : 0.0;
+        b[u][s] = (cv && sv[s]) ? A[(int64_t)srow[s] * ld + c] : T(0);
+        y[u][s] = (cv && ov[s]) ? A[(int64_t)orow[s] * ld + c] : T(0);
       }
     }
 #pragma unroll
     for (int u = 0; u < CB; ++u) {
-      d4 acc[NRB];
+      acc_t acc[NRB];
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) acc[rb] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int rb = 0; rb < NRB; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb)
-          acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ainv[rb][s], b[u][s],
-                                                         acc[rb], 0, 0, 0);
+          acc[rb] = Mx<T>::mfma(ainv[rb][s], b[u][s], acc[rb]);
       const int c = cb + 16 * u + col;
       if (c < c1) {
 #pragma unroll
@@ -610,7 +657,7 @@ __device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
         for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int q = rb * 16 + kq + 4 * r;  // FP64 result row
+            const int q = rb * 16 + Mx<T>::row(kq, r);  // result row
             if (q < jb) A[(int64_t)(j0 + q) * ld + c] = acc[rb][r];
           }
       }
@@ -626,8 +673,14 @@ __device__ void wave_tile_apply(double *A, int ld, int j0, int jb, int c0,
 // first before it is factored), then the block's interchanges and L11^-1
 // applied to the columns on its right and one rank-32 trailing update, so
 // the trailing matrix crosses HBM once per 32 columns.  Returns nonzero if
-// a pivot was zero or not a number.
-__device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
+// a pivot was zero or not a number.  piv (nullable) receives the pivot row
+// of every column, block by block, for later solves with the factors
+// (wave_lu_resolve).
+// (TAG only makes a separate copy of the routine for a caller in another
+// kernel, so that the two kernels' register allocations stay independent.)
+template <class T, int TAG = 0>
+__device__ int wave_lu_solve(T *A, int na, int ld, int nrhs, WaveLds &W,
+                             int *piv = nullptr) {
   const int ntot = na + nrhs;
   int flag = 0;
   for (int j0 = 0; j0 < na; j0 += NB2) {
@@ -657,6 +710,7 @@ __device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
       }
     }
     // the block's interchanges and L11^-1 on every column to its right
+    if (piv && lane_id() < jb) piv[j0 + lane_id()] = W.piv[lane_id()];
     wave_build_moves(W, j0, jb);
     wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UNIT_LOWER);
     wave_tile_invert<NB2>(W, TILE_UNIT_LOWER);
@@ -677,6 +731,110 @@ __device__ int wave_lu_solve(double *A, int na, int ld, int nrhs, WaveLds &W) {
                    nrhs, jb);
   }
   return flag;
+}
+
+// Solve A X = B again with the factors wave_lu_solve left in columns
+// [0, na) and its pivots `piv`, for new right-hand sides in columns
+// [na, na + nrhs); on return those columns hold X.  Same block order as the
+// factorisation: per 32-column block its interchanges and L11^-1 on the
+// right-hand sides, then the rank-32 update of the rows below (the L
+// columns of a block were never permuted by later blocks, so they match the
+// right-hand sides at that point), then back substitution with U.
+template <class T>
+__device__ void wave_lu_resolve(T *A, int na, int ld, int nrhs,
+                                const int *piv, WaveLds &W) {
+  const int lane = lane_id();
+  const int ntot = na + nrhs;
+  for (int j0 = 0; j0 < na; j0 += NB2) {
+    const int jb = min(NB2, na - j0);
+    if (lane < jb) W.piv[lane] = piv[j0 + lane];
+    wave_sync();
+    wave_build_moves(W, j0, jb);
+    wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UNIT_LOWER);
+    wave_tile_invert<NB2>(W, TILE_UNIT_LOWER);
+    wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, true);
+    const int r0 = j0 + jb;
+    if (r0 < na)
+      wave_gemm<0>(A + (int64_t)r0 * ld + na, ld, A + (int64_t)r0 * ld + j0,
+                   ld, A + (int64_t)j0 * ld + na, ld, na - r0, nrhs, jb);
+  }
+  for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
+    const int jb = min(NB2, na - j0);
+    wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UPPER);
+    wave_tile_invert<NB2>(W, TILE_UPPER);
+    wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
+    if (j0 > 0)
+      wave_gemm<0>(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0,
+                   nrhs, jb);
+  }
+}
+
+// Residual of the matching system in FP64 for iterative refinement.  With R
+// (n x n, leading dimension ld) and the current solution Z (n x no, ld),
+//   B - M Z = R (D2 Z + E) - [diag(s); 0] - D1 Z,   E_kj = a s'_j [k == j],
+// from the channel slots (d1, d2, s, a s'), so neither M nor B is kept.  R W
+// runs as 16x16x4 FP64 MFMAs over 32 x 32 output tiles with W formed in the
+// fragment loads; the residual goes to `out` (FP32, leading dimension ldo).
+// Returns max |r| (wavefront-uniform).
+__device__ double wave_residual(const double *Rm, int ld, const double *Z,
+                                const ChanSlot *ch, int n, int no,
+                                float *out, int ldo) {
+  const int lane = lane_id();
+  const int col = lane & 15, kq = lane >> 4;
+  const int nct = (no + 31) >> 5, ntile = ((n + 31) >> 5) * nct;
+  double rmax = 0.0;
+  for (int t = 0; t < ntile; ++t) {
+    const int rb = (t / nct) * 32, cb = (t % nct) * 32;
+    d4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      double a[4][2], b[4][2];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = k0 + 4 * s4 + kq;
+        const bool kv = k < n;
+        const double d2 = kv ? ch[k].d2 : 0.0;
+        const double asp = kv ? ch[k].asp : 0.0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          const int i = rb + 16 * x + col;
+          a[s4][x] = (kv && i < n) ? Rm[(int64_t)i * ld + k] : 0.0;
+          const int j = cb + 16 * x + col;
+          const double z = (kv && j < no) ? Z[(int64_t)k * ld + j] : 0.0;
+          b[s4][x] = (kv && j < no) ? fma(d2, z, k == j ? asp : 0.0) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                a[s4][x], b[s4][y], acc[x][y], 0, 0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rb + 16 * x + kq + 4 * r, j = cb + 16 * y + col;
+          if (i >= n || j >= no) continue;
+          const double z = Z[(int64_t)i * ld + j];
+          double v = acc[x][y][r] - ch[i].d1 * z;
+          if (i == j) v -= ch[i].s;
+          rmax = fmax(rmax, fabs(v));
+          out[(int64_t)i * ldo + j] = (float)v;
+        }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+  wave_sync();
+  return rmax;
 }
 
 // Copy a rows x cols block (row-major source ld sl, destination ld dl) with
@@ -1080,7 +1238,150 @@ __device__ inline int count_open(const SymDev &S, double Ee) {
   return lo;
 }
 
+// The matching solve with an FP32 factorisation refined in FP64: [M | B]
+// rounded to FP32 in K's place (n x 2n floats), factored and solved there;
+// the solution Z in FP64 in Aug's right half, then per iteration the FP64
+// residual (wave_residual, from R kept in Aug's left half) solved with the
+// FP32 factors and added to Z.  Converged when a correction is below the
+// rounding of Z (max|dZ| <= 2^-50 max|Z|), or when the corrections stop
+// contracting (max|dZ| over half the previous one) at a residual that passes
+// the backward-error test of LAPACK's mixed-precision dsgesv, max|r| <=
+// 4 sqrt(n) u ||M||_inf max|Z| (u = 2^-53): the floor that the system's
+// conditioning sets in FP64.  Otherwise, after refine_iters corrections,
+// the energy is flagged RM_E_REFINE_NOCONV and solved again with the FP64
+// factorisation.  Returns RM_E_* bits.
+__device__ int wave_solve_fp32(const MatchLaunch &L, const SymDev &S,
+                               double *Aug, double *Kb, const ChanSlot *ch,
+                               int no, WaveLds &W) {
+  const int lane = lane_id();
+  const int n = S.n, ld = 2 * n, ld32 = 2 * n;
+  float *A32 = (float *)Kb;
+  int *piv = (int *)(Aug + (int64_t)3 * n * n + 2 * n);
+  int bits = 0;
+  const int nsq = n * n;
+  for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+    double r[UNR], d2[UNR], asp[UNR], d1[UNR], sv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      const bool in = q < nsq;
+      const int i = q / n, j = q % n;
+      r[u] = in ? Aug[(int64_t)i * ld + j] : 0.0;
+      d2[u] = in ? ch[j].d2 : 0.0;
+      asp[u] = (in && j < no) ? ch[j].asp : 0.0;
+      d1[u] = (in && i == j) ? ch[i].d1 : 0.0;
+      sv[u] = (in && i == j) ? ch[i].s : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q >= nsq) continue;
+      const int i = q / n, j = q % n;
+      A32[(int64_t)i * ld32 + j] = (float)(d1[u] - r[u] * d2[u]);
+      if (j < no) A32[(int64_t)i * ld32 + n + j] = (float)(r[u] * asp[u] - sv[u]);
+    }
+  }
+  // ||M||_inf from the FP64 entries (row sums of |d1 - R d2|)
+  double anrm = 0.0;
+  for (int i = lane; i < n; i += WT) {
+    double rs = 0.0;
+    for (int j = 0; j < n; ++j)
+      rs += fabs((i == j ? ch[i].d1 : 0.0) - Aug[(int64_t)i * ld + j] * ch[j].d2);
+    anrm = fmax(anrm, rs);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) anrm = fmax(anrm, __shfl_xor(anrm, off));
+  wave_sync();
+  if (wave_lu_solve(A32, n, ld32, no, W, piv)) bits |= RM_E_SINGULAR;
+  // Z in FP64
+  const int nz = n * no;
+  double zmax = 0.0;
+  for (int q = lane; q < nz; q += WT) {
+    const int i = q / no, j = q % no;
+    const double z = (double)A32[(int64_t)i * ld32 + n + j];
+    Aug[(int64_t)i * ld + n + j] = z;
+    zmax = fmax(zmax, fabs(z));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) zmax = fmax(zmax, __shfl_xor(zmax, off));
+  wave_sync();
+  const double tol = 4.0 * sqrt((double)n) * 0x1p-53 * anrm;
+  bool conv = false;
+  double dprev = 1e300;
+  double rmax = wave_residual(Aug, ld, Aug + n, ch, n, no, A32 + n, ld32);
+  for (int it = 0; it < L.refine_iters; ++it) {
+    if (rmax == 0.0) {
+      conv = true;
+      break;
+    }
+    if (!(rmax < 1e300)) break;  // not finite
+    wave_lu_resolve(A32, n, ld32, no, piv, W);
+    double dmax = 0.0;
+    zmax = 0.0;
+    for (int q = lane; q < nz; q += WT) {
+      const int i = q / no, j = q % no;
+      const double dz = (double)A32[(int64_t)i * ld32 + n + j];
+      const double z = Aug[(int64_t)i * ld + n + j] + dz;
+      Aug[(int64_t)i * ld + n + j] = z;
+      zmax = fmax(zmax, fabs(z));
+      dmax = fmax(dmax, fabs(dz));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      zmax = fmax(zmax, __shfl_xor(zmax, off));
+      dmax = fmax(dmax, __shfl_xor(dmax, off));
+    }
+    wave_sync();
+    // the correction is below the rounding of Z itself
+    if (dmax <= 0x1p-50 * zmax) {
+      conv = true;
+      break;
+    }
+    rmax = wave_residual(Aug, ld, Aug + n, ch, n, no, A32 + n, ld32);
+    // corrections no longer contract: the FP64 floor of this system, if the
+    // residual passes the backward-error test there
+    if (dmax > 0.5 * dprev) {
+      conv = rmax <= tol * zmax;
+      break;
+    }
+    dprev = dmax;
+  }
+  if (!conv) {
+    // as LAPACK's dsgesv does: the FP32 factors cannot refine this system
+    // (cond(M) u_32 near 1, e.g. within ~1e-6 Ry of a pole at 200
+    // channels), so solve it again with the FP64 factorisation from R,
+    // still in Aug's left half
+    bits |= RM_E_REFINE_NOCONV;
+    for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+      double r[UNR], d2[UNR], asp[UNR], d1[UNR], sv[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        const bool in = q < nsq;
+        const int i = q / n, j = q % n;
+        r[u] = in ? Aug[(int64_t)i * ld + j] : 0.0;
+        d2[u] = in ? ch[j].d2 : 0.0;
+        asp[u] = (in && j < no) ? ch[j].asp : 0.0;
+        d1[u] = (in && i == j) ? ch[i].d1 : 0.0;
+        sv[u] = (in && i == j) ? ch[i].s : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + u * WT;
+        if (q >= nsq) continue;
+        const int i = q / n, j = q % n;
+        Aug[(int64_t)i * ld + j] = d1[u] - r[u] * d2[u];
+        if (j < no) Aug[(int64_t)i * ld + n + j] = r[u] * asp[u] - sv[u];
+      }
+    }
+    wave_sync();
+    if (wave_lu_solve<double, 1>(Aug, n, ld, no, W)) bits |= RM_E_SINGULAR;
+  }
+  return bits;
+}
+
 // One symmetry at one energy, one wavefront.  Returns RM_E_* bits.
+template <bool F32>
 __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
   const SymDev &S = L.syms[s];
   const int lane = lane_id();
@@ -1102,7 +1403,11 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
   }
   int bits = 0;
   const bool k_given = (L.K_in != nullptr) && s == 0;
-  if (!k_given) {
+  if (!k_given && F32) {
+    bits |= wave_channel_functions(S, Ee, ch);
+    wave_sync();
+    bits |= wave_solve_fp32(L, S, Aug, Kb, ch, no, W);
+  } else if (!k_given) {
     bits |= wave_channel_functions(S, Ee, ch);
     wave_sync();
     // [D1 - R D2 | R[:, P] diag(a s'_P) - diag(s_P)], R already in place
@@ -1131,6 +1436,8 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     }
     wave_sync();
     if (wave_lu_solve(Aug, n, ld, no, W)) bits |= RM_E_SINGULAR;
+  }
+  if (!k_given) {
     // K = sym(Z[0:no, 0:no]) -> Kb (ld n)
     const int nk = no * no;
     for (int q0 = lane; q0 < nk; q0 += UNR * WT) {
@@ -1256,6 +1563,7 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
 }
 
 #ifndef RM_MATCH_DEVICE_ONLY
+template <bool F32>
 __global__ __launch_bounds__(WT *WPB) void match_kernel(MatchLaunch L) {
   __shared__ WaveLds lds[WPB];
   const int lane = lane_id();
@@ -1270,7 +1578,7 @@ __global__ __launch_bounds__(WT *WPB) void match_kernel(MatchLaunch L) {
     }
     if (e >= L.m) break;
     int stat = 0;
-    for (int s = 0; s < L.n_sym; ++s) stat |= match_one(L, s, e, lds[wv]);
+    for (int s = 0; s < L.n_sym; ++s) stat |= match_one<F32>(L, s, e, lds[wv]);
     if (lane == 0 && L.status && stat) atomicOr(&L.status[e], stat);
     if (!L.counter) break;
   }
@@ -1280,7 +1588,10 @@ hipError_t launch_match(const MatchLaunch &L, hipStream_t st) {
   if (L.m <= 0) return hipSuccess;
   const int waves = L.counter ? std::max(1, std::min(L.grid * WPB, L.m)) : L.m;
   const unsigned blocks = (unsigned)((waves + WPB - 1) / WPB);
-  hipLaunchKernelGGL(match_kernel, dim3(blocks), dim3(WT * WPB), 0, st, L);
+  if (L.solve_fp32)
+    hipLaunchKernelGGL(match_kernel<true>, dim3(blocks), dim3(WT * WPB), 0, st, L);
+  else
+    hipLaunchKernelGGL(match_kernel<false>, dim3(blocks), dim3(WT * WPB), 0, st, L);
   return hipGetLastError();
 }
 

@@ -256,9 +256,9 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
     return fail(RM_ERR_ARG, "unknown flags 0x%x", d.flags);
   if ((d.flags & RM_FLAG_NO_PAIR_PRODUCTS) && (d.flags & RM_FLAG_PAIR_PRODUCTS))
     return fail(RM_ERR_ARG, "RM_FLAG_NO_PAIR_PRODUCTS and RM_FLAG_PAIR_PRODUCTS together");
-  if (d.solve_fp32 != 0)
-    return fail(RM_ERR_ARG, "solve_fp32 is not available: the matching "
-                            "solve runs in FP64");
+  if (d.solve_fp32 != 0 && d.solve_fp32 != 1)
+    return fail(RM_ERR_ARG, "solve_fp32 must be 0 or 1");
+  if (d.refine_iters > 100) return fail(RM_ERR_ARG, "refine_iters > 100");
   *out = d;
   return RM_OK;
 }
@@ -352,8 +352,9 @@ static int free_sym(Sym *s);
 // the whole sweep is a fixed sequence of launches: per chunk one grouped
 // pole-sum launch per tile variant and one persistent matching launch.
 
-// [Aug n x 2n | K n x n | g n | v n]: g and v serve photoionization
-static int64_t work_doubles(int n) { return (int64_t)3 * n * n + 2 * n; }
+// [Aug n x 2n | K n x n | g n | v n | pivots n]: g and v serve
+// photoionization, the pivots (as int) the FP32 solve's refinement
+static int64_t work_doubles(int n) { return (int64_t)3 * n * n + 3 * n; }
 
 struct Plan {
   int device = -1;
@@ -973,6 +974,8 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.e0 = p.e0;
     L.counter = p.counters + c;
     L.grid = p.match_grid;
+    L.solve_fp32 = p.o.solve_fp32;
+    L.refine_iters = p.o.refine_iters;
     if (p.propagate) {
       StageTimer tp(7, st);
       RM_HIP(launch_propagate(L, st));

@@ -181,7 +181,7 @@ struct MatchLaunch {
   // accumulated over the symmetries (nullable)
   double *sigma;
   double e0;
-  double *work;               // [M | B] (n x 2n) then K (n x n) per symmetry
+  double *work;               // [M | B] (n x 2n), K (n x n), 2n, n pivots
   int64_t work_estride;
   const int64_t *work_off;    // device [n_sym]
   ChanSlot *chan;
@@ -197,6 +197,8 @@ struct MatchLaunch {
   int do_t;
   int *counter;               // nullable
   int grid;
+  int solve_fp32;             // FP32 factorisation refined in FP64
+  int refine_iters;           // at most this many corrections
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
 // R(a) -> R(A) for the symmetries with outer-region sectors (same launch
