@@ -27,6 +27,7 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
                                    level groups (statistical averaging)
 * ``photo.photoionization``       photoionization cross sections from the
                                    same solve and bound-free dipole vectors
+* ``photo.photoionization_damped`` the same with radiatively damped poles
 * ``outer.sweep_propagated``      Omega with the R-matrix propagated beyond
                                    r = a through long-range multipole coupling
 * ``inner.inner_region``          poles and surface amplitudes from the full
@@ -45,7 +46,7 @@ from .rmatrix import (r_matrix, channel_data, k_matrix, k_matrix_elimination,
 from .postproc import (gaussian_convolve, effective_collision_strengths,
                        trapezoid_weights, group_collision_strengths)
 from .photo import (dipole_pole_sum, matching_solution, dipole_strength,
-                    photoionization, SIGMA_CONST)
+                    photoionization, photoionization_damped, SIGMA_CONST)
 from . import outer
 from . import inner
 
@@ -58,5 +59,6 @@ __all__ = [
     "gaussian_convolve", "effective_collision_strengths", "trapezoid_weights",
     "group_collision_strengths",
     "dipole_pole_sum", "matching_solution", "dipole_strength",
-    "photoionization", "SIGMA_CONST", "outer", "inner",
+    "photoionization", "photoionization_damped", "SIGMA_CONST", "outer",
+    "inner",
 ]

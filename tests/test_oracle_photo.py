@@ -185,3 +185,113 @@ def test_cross_section_constant():
     s = oracle.photoionization([sym], [d], E, -0.5)[0]
     s2 = oracle.photoionization([sym], [d], E, -1.5)[0]
     assert abs(s2 / s - 4.0 / 3.0) < 1e-12   # proportional to E - e0
+
+
+# ---- radiation damping -----------------------------------------------------
+
+def _damped_case(seed=51, n=4, nh=60):
+    from paper_1403_5524_amd import workloads as wl
+    rng = np.random.default_rng(seed)
+    sym = wl.random_symmetry(rng, n, nh, -2.0, 30.0).as_dict()
+    d = rng.normal(0.0, 1.0, nh)
+    G = 10.0 ** rng.uniform(-5, -2, nh)
+    return sym, d, G
+
+
+def test_damped_with_zero_widths_is_the_undamped_cross_section():
+    """Gamma = 0: the driven-solution flux equals the K-matrix route
+    (1/pi) M (1 + K^2)^-1 M^T, which is pinned independently above (square
+    well overlap, coupled well, incoming-wave sum)."""
+    sym, d, _ = _damped_case()
+    E = np.array([0.3, 1.2, 1.9, 2.7, 5.5, 11.0, 17.3])
+    ref = oracle.photoionization([sym], [d], E, -0.8)
+    got = oracle.photoionization_damped([sym], [d], [np.zeros(d.size)], E, -0.8)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _flux_balance(sym, d, G, E):
+    """(Im sum_k conj(A_k) d_k, sum_f |alpha_f|^2, sum_k Gamma_k/2 |A_k|^2)."""
+    from oracle import photo
+    a = sym["a"]
+    cd = oracle.channel_data(np.array([E]), sym["e_thr"], sym["l"], sym["z"], a)
+    cd1 = {k: v[0] for k, v in cd.items()}
+    R, g = photo.damped_pole_sums(sym["E_pole"], sym["w"], d, G, a, E)
+    x, P, d2 = photo.driven_solution(R, g, a, cd1)
+    A = photo.inner_amplitudes(sym["E_pole"], sym["w"], d, G, a, x, d2, E)
+    return (float(np.imag(np.sum(np.conj(A) * d))),
+            float(np.sum(np.abs(x[P]) ** 2)),
+            float(np.sum(0.5 * G * np.abs(A) ** 2)))
+
+
+@pytest.mark.parametrize("E", [0.7, 1.6, 4.4, 12.9])
+def test_damped_flux_balance(E):
+    """The driven solution of (E - H + i sum Gamma_k/2 |k><k|) psi = D Psi_0:
+    the imaginary part of <psi|D Psi_0> (from the inner-region amplitudes
+    A_k) is the flux out through the open channels (from the matching) plus
+    the radiative loss sum_k (Gamma_k/2)|A_k|^2; with Gamma = 0 it is the
+    optical theorem.  Checked with widths up to 1e-2 Ry, at energies with
+    and without closed channels."""
+    sym, d, G = _damped_case()
+    for widths in (G, np.zeros_like(G)):
+        lhs, flux, loss = _flux_balance(sym, d, widths, E)
+        assert abs(lhs - (flux + loss)) <= 1e-10 * abs(lhs)
+        assert flux > 0.0 and loss >= 0.0
+
+
+def test_damping_lowers_a_narrow_resonance_and_spares_the_background():
+    """One weakly coupled pole (autoionisation width ~1e-4 Ry) among broad
+    ones: as its radiative width grows from 0 to 1e-3 Ry the cross section at
+    the resonance falls monotonically (below half at 1e-3 Ry), while 0.2 Ry
+    away it changes by less than (Gamma / 0.2 Ry)^2 = 2.5e-5 relative."""
+    sym, d, _ = _damped_case(seed=53)
+    Ep = sym["E_pole"].copy()
+    k = int(np.argmin(np.abs(Ep - 6.0)))
+    sym["w"][:, k] *= 0.05
+    d = d.copy()
+    d[k] = 5.0
+    # the resonance position: the maximum of the undamped cross section
+    # near the pole (its shift from E_k is small for a weak coupling)
+    Es = Ep[k] + np.linspace(-2e-3, 2e-3, 800)   # E_k itself not on the grid
+    s0 = oracle.photoionization([sym], [d], Es, -0.8)
+    Er = Es[np.argmax(s0)]
+    peaks, far = [], []
+    for gr in (0.0, 1e-5, 1e-4, 1e-3):
+        G = np.zeros(Ep.size)
+        G[k] = gr
+        peaks.append(oracle.photoionization_damped([sym], [d], [G], [Er], -0.8)[0])
+        far.append(oracle.photoionization_damped([sym], [d], [G], [Er + 0.2], -0.8)[0])
+    assert all(p1 < p0 for p0, p1 in zip(peaks, peaks[1:]))
+    assert peaks[-1] < 0.5 * peaks[0]
+    assert max(abs(f - far[0]) for f in far) <= 2.5e-5 * far[0]
+
+
+def test_damping_planted_mistakes_break_the_flux_balance():
+    """A width entering with the wrong sign (E_k + i Gamma/2), the damping
+    left out of the dipole sum g, or the outgoing wave taken as c - i s
+    each break the flux balance by far more than its 1e-10 bound (at an
+    energy 0.1 Ry from the nearest pole, where the widths act weakly)."""
+    from oracle import photo
+    sym, d, G = _damped_case()
+    E = 4.4
+    a = sym["a"]
+    cd = oracle.channel_data(np.array([E]), sym["e_thr"], sym["l"], sym["z"], a)
+    cd1 = {k: v[0] for k, v in cd.items()}
+
+    def balance(R, g, Gm, conj_wave=False):
+        d1, d2 = photo.outgoing_channel_values(a, cd1)
+        if conj_wave:
+            d1, d2 = np.conj(d1), np.conj(d2)
+        x = np.linalg.solve(np.diag(d1) - R * d2[None, :], -g)
+        P = np.nonzero(cd1["open"])[0]
+        A = photo.inner_amplitudes(sym["E_pole"], sym["w"], d, Gm, a, x, d2, E)
+        lhs = np.imag(np.sum(np.conj(A) * d))
+        rhs = np.sum(np.abs(x[P]) ** 2) + np.sum(0.5 * G * np.abs(A) ** 2)
+        return abs(lhs - rhs) / abs(lhs)
+
+    R, g = photo.damped_pole_sums(sym["E_pole"], sym["w"], d, G, a, E)
+    assert balance(R, g, G) < 1e-10
+    Rm, gm = photo.damped_pole_sums(sym["E_pole"], sym["w"], d, -G, a, E)
+    assert balance(Rm, gm, -G) > 1e-8
+    _, g0 = photo.damped_pole_sums(sym["E_pole"], sym["w"], d, 0 * G, a, E)
+    assert balance(R, g0, G) > 1e-8
+    assert balance(R, g, G, conj_wave=True) > 1e-3
