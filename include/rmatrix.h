@@ -146,6 +146,9 @@ typedef struct {
  * two may not be combined (RM_ERR_ARG). */
 #define RM_FLAG_NO_PAIR_PRODUCTS 0x2u
 #define RM_FLAG_PAIR_PRODUCTS 0x4u
+/* rm_opts.flags, rm_photoionization only: radiation damping (below); every
+ * other entry point returns RM_ERR_ARG for it. */
+#define RM_FLAG_RADIATION_DAMPING 0x8u
 
 /* Load one symmetry (Sec. 3: the poles and amplitudes produced by the
  * inner-region diagonalisation; Sec. 6 Eq. 2: W is the shared operand of
@@ -357,6 +360,27 @@ int rm_set_propagation(rm_sym_t sym, double A, int32_t n_sec, int32_t lmax,
  * synchronising `stream`).  Errors: RM_ERR_ARG, RM_ERR_STATE, RM_ERR_NOMEM,
  * RM_ERR_HIP. */
 int rm_load_dipoles(rm_sym_t sym, const double *d, void *stream);
+
+/* rm_load_widths: attach the radiative widths Gamma_k (host [n_poles], finite,
+ * >= 0, Ry, input pole order) of the inner-region states to a loaded
+ * symmetry, for the damped photoionization (replaces earlier widths after
+ * synchronising `stream`).  Errors: RM_ERR_ARG, RM_ERR_STATE, RM_ERR_NOMEM,
+ * RM_ERR_HIP.
+ *
+ * Radiation damping (the damped photoionization module of Sec. 3, Tables
+ * 1-2; the paper gives no formula), read as the optical potential
+ * -i sum_k (Gamma_k/2)|psi_k><psi_k|: the poles move to E_k - i Gamma_k/2,
+ * so R and g become complex, and sigma is the flux into the open channels
+ * of the driven solution of (E - H_eff) psi = D Psi_0 with outgoing waves:
+ *   (diag(d1) - R_c diag(d2)) [alpha; beta] = -g_c,
+ *   d1 = c + i s, d2 = a (c' + i s') (open), (e, a e') (closed),
+ *   sigma(E) += (4 pi^2 alpha a0^2 / 3) (E - e0) (1/pi) sum_open |alpha_f|^2,
+ * which equals the undamped sigma when every Gamma_k = 0.  Selected by
+ * RM_FLAG_RADIATION_DAMPING in rm_photoionization's opts; it needs the FP64
+ * pole sum and solve (prec = RM_PREC_FP64, solve_fp32 = 0, no autotuning or
+ * pair products: RM_ERR_ARG otherwise) and widths on every symmetry.  The
+ * complex system is solved as its real 2n x 2n form. */
+int rm_load_widths(rm_sym_t sym, const double *gamma, void *stream);
 
 /* rm_photoionization: sigma (device [M], overwritten) at the M energies E
  * (device, total energy of the final state on the thresholds' scale) for

@@ -1562,8 +1562,89 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
   return wave_or(bits);
 }
 
+// Radiation-damped photoionization, one symmetry at one energy.  With the
+// pole energies E_k - i Gamma_k/2 the pole sums are complex, R_c = R_re +
+// i R_im and g_c = g_re + i g_im (the pole-sum kernels' parts 1 and 2), and
+// the driven solution of (E - H_eff) psi = D Psi_0 with outgoing waves
+// outside satisfies
+//     (diag(d1) - R_c diag(d2)) x = -g_c,
+// d1 = c + i s, d2 = a (c' + i s') on open channels (u = (c + i s) alpha)
+// and the closed function (e, a e') on closed ones; its flux into the open
+// channels is sum_f |alpha_f|^2 (c s' - s c' = 1), and sigma +=
+// (4 pi alpha a0^2 / 3) omega sum_f |alpha_f|^2.  The complex system is
+// solved as the real 2n x 2n system [[A_r, -A_i], [A_i, A_r]] [x_r; x_i] =
+// [-g_re; -g_im] by the wavefront LU.  Returns RM_E_* bits.
+__device__ int match_one_damped(const MatchLaunch &L, int s, int e,
+                                WaveLds &W) {
+  const SymDev &S = L.syms[s];
+  const int lane = lane_id();
+  const int n = S.n, n2 = 2 * n, ld = 2 * n + 2;
+  const double Ee = L.E[e];
+  double *Sys = L.work + (int64_t)e * L.work_estride + L.work_off[s];
+  const double *Rre = Sys + (int64_t)n2 * ld;
+  const double *Rim = Rre + (int64_t)n * n;
+  const double *gre = Rim + (int64_t)n * n;
+  const double *gim = gre + n;
+  ChanSlot *ch = L.chan + (int64_t)e * L.chan_estride + L.chan_off[s];
+  const int no = count_open(S, Ee);
+  if (no == 0) return RM_E_NO_OPEN;
+  int bits = wave_channel_functions(S, Ee, ch);
+  wave_sync();
+  const int nsq = n * n;
+  for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+    double rr[UNR], ri[UNR], d2[UNR], asp[UNR], d1[UNR], sv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      const bool in = q < nsq;
+      const int i = q / n, j = q % n;
+      rr[u] = in ? Rre[q] : 0.0;
+      ri[u] = in ? Rim[q] : 0.0;
+      d2[u] = in ? ch[j].d2 : 0.0;
+      asp[u] = in ? ch[j].asp : 0.0;
+      d1[u] = (in && i == j) ? ch[i].d1 : 0.0;
+      sv[u] = (in && i == j) ? ch[i].s : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q >= nsq) continue;
+      const int i = q / n, j = q % n;
+      const double ar = d1[u] - (rr[u] * d2[u] - ri[u] * asp[u]);
+      const double ai = sv[u] - (rr[u] * asp[u] + ri[u] * d2[u]);
+      Sys[(int64_t)i * ld + j] = ar;
+      Sys[(int64_t)i * ld + n + j] = -ai;
+      Sys[(int64_t)(n + i) * ld + j] = ai;
+      Sys[(int64_t)(n + i) * ld + n + j] = ar;
+    }
+  }
+  for (int i = lane; i < n; i += WT) {
+    Sys[(int64_t)i * ld + n2] = -gre[i];
+    Sys[(int64_t)(n + i) * ld + n2] = -gim[i];
+  }
+  wave_sync();
+  if (wave_lu_solve<double, 2>(Sys, n2, ld, 1, W)) bits |= RM_E_SINGULAR;
+  double s2 = 0.0;
+  for (int f = lane; f < no; f += WT) {
+    const double xr = Sys[(int64_t)f * ld + n2];
+    const double xi = Sys[(int64_t)(n + f) * ld + n2];
+    s2 = fma(xr, xr, fma(xi, xi, s2));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s2 += __shfl_xor(s2, o);
+  const double c = 4.0 * M_PI * 7.2973525693e-3 * 28.00285205 / 3.0;
+  const double add = c * (Ee - L.e0) * s2;
+  if (!isfinite(add)) bits |= RM_E_NONFINITE;
+  if (lane == 0) L.sigma[e] += add;
+  wave_sync();
+  return wave_or(bits);
+}
+
 #ifndef RM_MATCH_DEVICE_ONLY
-template <bool F32>
+// MODE 0: FP64 solve; 1: FP32 solve refined in FP64; 2: damped
+// photoionization.  Separate instantiations keep each kernel's registers
+// its own.
+template <int MODE>
 __global__ __launch_bounds__(WT *WPB) void match_kernel(MatchLaunch L) {
   __shared__ WaveLds lds[WPB];
   const int lane = lane_id();
@@ -1578,7 +1659,12 @@ __global__ __launch_bounds__(WT *WPB) void match_kernel(MatchLaunch L) {
     }
     if (e >= L.m) break;
     int stat = 0;
-    for (int s = 0; s < L.n_sym; ++s) stat |= match_one<F32>(L, s, e, lds[wv]);
+    for (int s = 0; s < L.n_sym; ++s) {
+      if constexpr (MODE == 2)
+        stat |= match_one_damped(L, s, e, lds[wv]);
+      else
+        stat |= match_one<MODE == 1>(L, s, e, lds[wv]);
+    }
     if (lane == 0 && L.status && stat) atomicOr(&L.status[e], stat);
     if (!L.counter) break;
   }
@@ -1588,10 +1674,12 @@ hipError_t launch_match(const MatchLaunch &L, hipStream_t st) {
   if (L.m <= 0) return hipSuccess;
   const int waves = L.counter ? std::max(1, std::min(L.grid * WPB, L.m)) : L.m;
   const unsigned blocks = (unsigned)((waves + WPB - 1) / WPB);
-  if (L.solve_fp32)
-    hipLaunchKernelGGL(match_kernel<true>, dim3(blocks), dim3(WT * WPB), 0, st, L);
+  if (L.damped)
+    hipLaunchKernelGGL(match_kernel<2>, dim3(blocks), dim3(WT * WPB), 0, st, L);
+  else if (L.solve_fp32)
+    hipLaunchKernelGGL(match_kernel<1>, dim3(blocks), dim3(WT * WPB), 0, st, L);
   else
-    hipLaunchKernelGGL(match_kernel<false>, dim3(blocks), dim3(WT * WPB), 0, st, L);
+    hipLaunchKernelGGL(match_kernel<0>, dim3(blocks), dim3(WT * WPB), 0, st, L);
   return hipGetLastError();
 }
 

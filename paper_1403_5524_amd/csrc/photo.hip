@@ -19,7 +19,7 @@ constexpr int DP_KC = 16;  // poles per stage
 
 __global__ __launch_bounds__(256) void dip_polesum_kernel(
     SymDev S, const double *__restrict__ E, int m, double *__restrict__ out,
-    int64_t estride, int64_t off) {
+    int64_t estride, int64_t off, int part) {
   __shared__ double D[DP_KC][DP_BE];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -43,7 +43,17 @@ __global__ __launch_bounds__(256) void dip_polesum_kernel(
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + sk + 4 * u;
-      dv[u] = ev ? S.dip[k] / (S.E_pole[k] - Ee) : 0.0;
+      // part 0: d_k / (E_k - E); 1, 2: real and imaginary part of
+      // d_k / (E_k - i Gamma_k/2 - E)
+      const double x = S.E_pole[k] - Ee;
+      double v;
+      if (part == 0) {
+        v = S.dip[k] / x;
+      } else {
+        const double h = 0.5 * S.gam[k];
+        v = S.dip[k] * (part == 1 ? x : h) / fma(x, x, h * h);
+      }
+      dv[u] = ev ? v : 0.0;
     }
     // A[i][k] = w_ik for i = i0 + col, k = k0 + 4 s + kq
     double a[4];
@@ -77,11 +87,11 @@ __global__ __launch_bounds__(256) void dip_polesum_kernel(
 
 hipError_t launch_dip_polesum(const SymDev &S, const double *E, int m,
                               double *out, int64_t estride, int64_t off,
-                              hipStream_t st) {
+                              hipStream_t st, int part) {
   if (m <= 0) return hipSuccess;
   const dim3 grid((unsigned)((S.n + 63) / 64), (unsigned)((m + DP_BE - 1) / DP_BE));
   hipLaunchKernelGGL(dip_polesum_kernel, grid, dim3(256), 0, st, S, E, m, out,
-                     estride, off);
+                     estride, off, part);
   return hipGetLastError();
 }
 

@@ -38,7 +38,21 @@ struct F64Smem {  // two stages: one feeds the MFMAs while the next fills
 // holds any element that is kept (row and column below n, row <= column on
 // a diagonal tile); the others are never formed.  Diagonal tiles are
 // exactly the masks without block (1, 0).
-template <int MASK>
+// Pole weight of part PART (see PsLaunch::part) for pole energy ep, width
+// gm and energy e: 1/(ep - e), or the real / imaginary part of
+// 1/(ep - i gm/2 - e) = (x + i h)/(x^2 + h^2), x = ep - e, h = gm/2.
+template <int PART>
+__device__ inline double ps_weight(double ep, double gm, double e) {
+  const double x = ep - e;
+  if constexpr (PART == 0) {
+    return 1.0 / x;
+  } else {
+    const double h = 0.5 * gm;
+    return (PART == 1 ? x : h) / fma(x, x, h * h);
+  }
+}
+
+template <int MASK, int PART>
 __device__ void ps_f64_item_m(const SymDev &S, int I, int J, int grp,
                               const double *__restrict__ E, int m,
                               double *__restrict__ Rbase, int64_t estride,
@@ -86,6 +100,11 @@ __device__ void ps_f64_item_m(const SymDev &S, int I, int J, int grp,
     rb1 = *(const double2 *)(wb + 2);
   }
   double ep0 = S.E_pole[dk[0]], ep1 = S.E_pole[dk[1]];
+  double gm0 = 0.0, gm1 = 0.0;
+  if constexpr (PART != 0) {
+    gm0 = S.gam[dk[0]];
+    gm1 = S.gam[dk[1]];
+  }
   // stage chunk c (held in registers) into LDS buffer c % 2
   auto stage = [&](int buf) {
     *(double2 *)&sm.As[buf][ld_k][ld_c] = ra0;
@@ -94,8 +113,8 @@ __device__ void ps_f64_item_m(const SymDev &S, int I, int J, int grp,
       *(double2 *)&sm.Bs[buf][ld_k][ld_c] = rb0;
       *(double2 *)&sm.Bs[buf][ld_k][ld_c + 2] = rb1;
     }
-    sm.Ds[buf][de[0]][dk[0]] = ev[0] ? 1.0 / (ep0 - Eloc[0]) : 0.0;
-    sm.Ds[buf][de[1]][dk[1]] = ev[1] ? 1.0 / (ep1 - Eloc[1]) : 0.0;
+    sm.Ds[buf][de[0]][dk[0]] = ev[0] ? ps_weight<PART>(ep0, gm0, Eloc[0]) : 0.0;
+    sm.Ds[buf][de[1]][dk[1]] = ev[1] ? ps_weight<PART>(ep1, gm1, Eloc[1]) : 0.0;
   };
   // load chunk starting at pole kn into registers
   auto fetch = [&](int kn) {
@@ -108,6 +127,10 @@ __device__ void ps_f64_item_m(const SymDev &S, int I, int J, int grp,
     }
     ep0 = S.E_pole[kn + dk[0]];
     ep1 = S.E_pole[kn + dk[1]];
+    if constexpr (PART != 0) {
+      gm0 = S.gam[kn + dk[0]];
+      gm1 = S.gam[kn + dk[1]];
+    }
   };
   stage(0);
   if (PS_KC < S.nh_pad) fetch(PS_KC);
@@ -177,6 +200,7 @@ __device__ void ps_f64_item_m(const SymDev &S, int I, int J, int grp,
   }
 }
 
+template <int PART>
 __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
                             const double *__restrict__ E, int m,
                             double *__restrict__ Rbase, int64_t estride,
@@ -184,19 +208,20 @@ __device__ void ps_f64_item(const SymDev &S, int I, int J, int grp,
   // the last tile may reach at most 16 rows past n (n_pad = 32 ceil(n/32))
   if (I == J) {
     if (S.n - I * PS_T <= 16)
-      ps_f64_item_m<1>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+      ps_f64_item_m<1, PART>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
     else
-      ps_f64_item_m<1 | 2 | 8>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+      ps_f64_item_m<1 | 2 | 8, PART>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
   } else {
     if (S.n - J * PS_T <= 16)
-      ps_f64_item_m<1 | 4>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+      ps_f64_item_m<1 | 4, PART>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
     else
-      ps_f64_item_m<15>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
+      ps_f64_item_m<15, PART>(S, I, J, grp, E, m, Rbase, estride, ld, sm);
   }
 }
 
 // two workgroups per CU (41 KB of LDS and at most 256 registers per lane
 // each), so one's barrier and staging overlap the other's MFMAs
+template <int PART>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void polesum_f64_kernel(PsLaunch L) {
   __shared__ F64Smem sm;
@@ -217,7 +242,7 @@ void polesum_f64_kernel(PsLaunch L) {
     if (it >= L.n_items) break;
     const PsItem item = L.items[it];
     const SymDev &S = L.syms[item.sym];
-    ps_f64_item(S, item.x, item.y, item.grp, L.E, L.m,
+    ps_f64_item<PART>(S, item.x, item.y, item.grp, L.E, L.m,
                 L.out.out + L.out.off[item.sym], L.out.estride,
                 L.out.ld_mult * S.n, sm);
     if (!L.counter) break;
@@ -266,7 +291,12 @@ hipError_t launch_polesum(const PsLaunch &L, int variant, hipStream_t st) {
     grid = (unsigned)std::max(1, std::min(L.grid, L.n_items));
   else
     grid = (unsigned)(8 * ((L.n_items + 7) / 8));
-  hipLaunchKernelGGL(polesum_f64_kernel, dim3(grid), dim3(256), 0, st, L);
+  if (L.part == 1)
+    hipLaunchKernelGGL(polesum_f64_kernel<1>, dim3(grid), dim3(256), 0, st, L);
+  else if (L.part == 2)
+    hipLaunchKernelGGL(polesum_f64_kernel<2>, dim3(grid), dim3(256), 0, st, L);
+  else
+    hipLaunchKernelGGL(polesum_f64_kernel<0>, dim3(grid), dim3(256), 0, st, L);
   return hipGetLastError();
 }
 

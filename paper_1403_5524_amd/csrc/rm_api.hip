@@ -232,7 +232,7 @@ static int check_device(const Sym *s) {
   return RM_OK;
 }
 
-static int check_opts(const rm_opts *o, rm_opts *out) {
+static int check_opts(const rm_opts *o, rm_opts *out, bool photo = false) {
   rm_opts d{};
   if (o) d = *o;
   if (d.prec < RM_PREC_FP64 || d.prec > RM_PREC_BF16X3)
@@ -252,7 +252,17 @@ static int check_opts(const rm_opts *o, rm_opts *out) {
   if (d.refine_iters < 0) return fail(RM_ERR_ARG, "refine_iters < 0");
   if (d.refine_iters == 0) d.refine_iters = 8;
   if (d.chunk < 0) return fail(RM_ERR_ARG, "chunk < 0");
-  if (d.flags & ~(RM_FLAG_AUTOTUNE | RM_FLAG_NO_PAIR_PRODUCTS | RM_FLAG_PAIR_PRODUCTS))
+  if ((d.flags & RM_FLAG_RADIATION_DAMPING) && !photo)
+    return fail(RM_ERR_ARG, "RM_FLAG_RADIATION_DAMPING applies to "
+                            "rm_photoionization only");
+  if (d.flags & RM_FLAG_RADIATION_DAMPING) {
+    if (d.prec != RM_PREC_FP64 || d.solve_fp32 ||
+        (d.flags & (RM_FLAG_AUTOTUNE | RM_FLAG_PAIR_PRODUCTS)))
+      return fail(RM_ERR_ARG, "the damped photoionization runs the FP64 "
+                              "scaled-W pole sum and the FP64 solve only");
+  }
+  if (d.flags & ~(RM_FLAG_AUTOTUNE | RM_FLAG_NO_PAIR_PRODUCTS | RM_FLAG_PAIR_PRODUCTS |
+                  RM_FLAG_RADIATION_DAMPING))
     return fail(RM_ERR_ARG, "unknown flags 0x%x", d.flags);
   if ((d.flags & RM_FLAG_NO_PAIR_PRODUCTS) && (d.flags & RM_FLAG_PAIR_PRODUCTS))
     return fail(RM_ERR_ARG, "RM_FLAG_NO_PAIR_PRODUCTS and RM_FLAG_PAIR_PRODUCTS together");
@@ -355,6 +365,12 @@ static int free_sym(Sym *s);
 // [Aug n x 2n | K n x n | g n | v n | pivots n]: g and v serve
 // photoionization, the pivots (as int) the FP32 solve's refinement
 static int64_t work_doubles(int n) { return (int64_t)3 * n * n + 3 * n; }
+// damped photoionization: [2n x 2n real driven system, leading dimension
+// 2n + 2 | R_re n x n | R_im n x n | g_re n | g_im n]
+static int64_t sys_doubles_damped(int n) { return (int64_t)2 * n * (2 * n + 2); }
+static int64_t work_doubles_damped(int n) {
+  return sys_doubles_damped(n) + (int64_t)2 * n * n + 2 * n;
+}
 
 struct Plan {
   int device = -1;
@@ -397,6 +413,9 @@ struct Plan {
   double e0 = 0.0;
   std::vector<int64_t> h_work_off;  // host copy of the workspace offsets
   bool propagate = false;           // some symmetry has outer sectors
+  // damped photoionization: per-symmetry offsets of R_re and R_im
+  bool damped = false;
+  int64_t *d_rre_off = nullptr, *d_rim_off = nullptr;
   // rm_kmatrix-style extras (single symmetry)
   double *K_out = nullptr;
   int32_t *n_open_out = nullptr;
@@ -424,11 +443,13 @@ static void plan_free_device(Plan &p) {
     for (int t = 0; t < 2; ++t)
       if (set.d_items[t]) (void)hipFree(set.d_items[t]);
   p.sets.clear();
-  void *tabs[] = {p.d_syms, p.d_work_off, p.d_chan_off};
+  void *tabs[] = {p.d_syms, p.d_work_off, p.d_chan_off, p.d_rre_off,
+                  p.d_rim_off};
   for (void *q : tabs)
     if (q) (void)hipFree(q);
   p.d_syms = nullptr;
   p.d_work_off = p.d_chan_off = nullptr;
+  p.d_rre_off = p.d_rim_off = nullptr;
   void *ws[] = {p.work, p.chan, p.counters};
   for (void *q : ws) {
     if (!q) continue;
@@ -776,7 +797,12 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   p.syms = v;
   p.device = v[0]->device;
   p.variant.resize(v.size());
+  p.damped = (o.flags & RM_FLAG_RADIATION_DAMPING) != 0;
   for (size_t q = 0; q < v.size(); ++q) {
+    if (p.damped) {  // the FP64 scaled-W kernel has the damped weights
+      p.variant[q] = PS_F64_T32_E16;
+      continue;
+    }
     if (arena) {
       p.variant[q] = pick_variant_noalloc(*v[q], o);
       continue;
@@ -791,7 +817,7 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
     sd.push_back(s->dev());
     woff.push_back(wacc);
     coff.push_back(cacc);
-    wacc += work_doubles(s->n);
+    wacc += p.damped ? work_doubles_damped(s->n) : work_doubles(s->n);
     cacc += s->n;
   }
   p.work_estride = wacc;
@@ -850,6 +876,17 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   if (e == hipSuccess) e = put(p.d_syms, sd.data(), sd.size() * sizeof(SymDev));
   if (e == hipSuccess) e = put(p.d_work_off, woff.data(), woff.size() * sizeof(int64_t));
   if (e == hipSuccess) e = put(p.d_chan_off, coff.data(), coff.size() * sizeof(int64_t));
+  if (p.damped && !arena) {
+    std::vector<int64_t> re(v.size()), im(v.size());
+    for (size_t q = 0; q < v.size(); ++q) {
+      re[q] = woff[q] + sys_doubles_damped(v[q]->n);
+      im[q] = re[q] + (int64_t)v[q]->n * v[q]->n;
+    }
+    if (e == hipSuccess) e = get((void **)&p.d_rre_off, re.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = get((void **)&p.d_rim_off, im.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = put(p.d_rre_off, re.data(), re.size() * sizeof(int64_t));
+    if (e == hipSuccess) e = put(p.d_rim_off, im.data(), im.size() * sizeof(int64_t));
+  }
   std::vector<int> vars(p.variant.begin(), p.variant.end());
   std::sort(vars.begin(), vars.end());
   vars.erase(std::unique(vars.begin(), vars.end()), vars.end());
@@ -933,9 +970,27 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
         L.prec = p.o.prec;
         L.delta = p.o.near_delta;
         L.band = p.o.band_delta;
+        if (p.damped) {
+          // real and imaginary parts of R with damped pole energies
+          L.out = PsOut{p.work, p.work_estride, p.d_rre_off, 1};
+          L.part = 1;
+          RM_HIP(launch_polesum(L, set.variant, st));
+          L.out = PsOut{p.work, p.work_estride, p.d_rim_off, 1};
+          L.part = 2;
+        }
         RM_HIP(launch_polesum(L, set.variant, st));
       }
-      if (p.sigma) {
+      if (p.sigma && p.damped) {
+        for (size_t q = 0; q < p.syms.size(); ++q) {
+          const Sym &s = *p.syms[q];
+          const int64_t go = p.h_work_off[q] + sys_doubles_damped(s.n) +
+                             (int64_t)2 * s.n * s.n;
+          RM_HIP(launch_dip_polesum(s.dev(), p.E + c0, (int)m, p.work,
+                                    p.work_estride, go, st, 1));
+          RM_HIP(launch_dip_polesum(s.dev(), p.E + c0, (int)m, p.work,
+                                    p.work_estride, go + s.n, st, 2));
+        }
+      } else if (p.sigma) {
         // dipole pole sums after each symmetry's K block
         for (size_t q = 0; q < p.syms.size(); ++q) {
           const Sym &s = *p.syms[q];
@@ -976,6 +1031,7 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.grid = p.match_grid;
     L.solve_fp32 = p.o.solve_fp32;
     L.refine_iters = p.o.refine_iters;
+    L.damped = p.damped ? 1 : 0;
     if (p.propagate) {
       StageTimer tp(7, st);
       RM_HIP(launch_propagate(L, st));
@@ -1011,7 +1067,7 @@ static int free_sym(Sym *s) {
   void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
                   s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT,
                   s->pair_ij, s->Ph, s->Pl, s->P32, s->P64, s->dip,
-                  s->prop_O, s->prop_eps};
+                  s->prop_O, s->prop_eps, s->gam};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete[] s->h_e_thr;
@@ -1471,20 +1527,42 @@ int rm_load_dipoles(rm_sym_t sym, const double *d, void *stream) {
   return RM_OK;
 }
 
+int rm_load_widths(rm_sym_t sym, const double *gamma, void *stream) {
+  if (!sym || !gamma) return fail(RM_ERR_ARG, "null handle or widths");
+  int rc = check_device(sym);
+  if (rc) return rc;
+  std::vector<double> h((size_t)sym->nh_pad, 0.0);
+  for (int k = 0; k < sym->nh; ++k) {
+    if (!std::isfinite(gamma[k]) || gamma[k] < 0.0)
+      return fail(RM_ERR_ARG, "width %d not finite and >= 0", k);
+    h[k] = gamma[k];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  RM_HIP(hipStreamSynchronize(st));  // queued kernels may read the old ones
+  if (!sym->gam) RM_HIP(hipMalloc((void **)&sym->gam, h.size() * sizeof(double)));
+  RM_HIP(hipMemcpy(sym->gam, h.data(), h.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+  return RM_OK;
+}
+
 int rm_photoionization(const rm_sym_t *syms, int32_t n_sym, const double *E,
                        int64_t M, double e0, const rm_opts *opts,
                        double *sigma, int32_t *status, void *stream) {
   if (M < 0) return fail(RM_ERR_ARG, "M < 0");
   if (!std::isfinite(e0)) return fail(RM_ERR_ARG, "e0 not finite");
   rm_opts o;
-  int rc = check_opts(opts, &o);
+  int rc = check_opts(opts, &o, true);
   if (rc) return rc;
   if (!syms || n_sym < 1) return fail(RM_ERR_ARG, "no symmetries");
+  const bool damped = (o.flags & RM_FLAG_RADIATION_DAMPING) != 0;
   int n_tgt = 1;
   for (int q = 0; q < n_sym; ++q) {
     if (!syms[q]) return fail(RM_ERR_ARG, "null handle %d", q);
     if (!syms[q]->dip)
       return fail(RM_ERR_ARG, "symmetry %d has no dipoles (rm_load_dipoles)", q);
+    if (damped && !syms[q]->gam)
+      return fail(RM_ERR_ARG, "symmetry %d has no radiative widths "
+                  "(rm_load_widths)", q);
     if (syms[q]->n_sec > 0)
       return fail(RM_ERR_ARG, "symmetry %d has an outer-region propagation: "
                   "photoionization matches at r = a", q);

@@ -40,6 +40,7 @@ struct SymDev {
   const float *P32;           // [np_pad][nh_pad] FP32 w_ik w_jk
   const double *P64;          // [np_pad][nh_pad] FP64 w_ik w_jk
   const double *dip;          // [nh_pad] bound-free dipoles, or null
+  const double *gam;          // [nh_pad] radiative widths Gamma_k, or null
   // outer-region propagation from a to A (n_sec = 0: none): sector s
   // rotates the reduced R-matrix by O_s (X <- O_s^T X O_s) and then steps
   // it across width h_sec with eigenvalues eps_s; O_{n_sec} returns to the
@@ -78,6 +79,7 @@ struct Sym {
   float *P32;
   double *P64;
   double *dip = nullptr;  // [nh_pad] dipoles with the initial state (owned)
+  double *gam = nullptr;  // [nh_pad] radiative widths of the poles (owned)
   int n_sec = 0;          // outer-region sectors (0: match at r = a)
   double A = 0.0, h_sec = 0.0;
   double *prop_O = nullptr, *prop_eps = nullptr;  // owned
@@ -92,7 +94,7 @@ struct Sym {
     d.e_thr = e_thr; d.l = l; d.perm = perm; d.tgt = tgt;
     d.ntu = ntu; d.ut = ut; d.G = G; d.GT = GT;
     d.np = np; d.np_pad = np_pad; d.pair_ij = pair_ij;
-    d.Ph = Ph; d.Pl = Pl; d.P32 = P32; d.P64 = P64; d.dip = dip;
+    d.Ph = Ph; d.Pl = Pl; d.P32 = P32; d.P64 = P64; d.dip = dip; d.gam = gam;
     d.n_sec = n_sec; d.A = A; d.h_sec = h_sec;
     d.r_match = n_sec > 0 ? A : a;
     d.prop_O = prop_O; d.prop_eps = prop_eps;
@@ -157,6 +159,9 @@ struct PsLaunch {
   int prec;
   double delta;         // near tier: FP64 operands
   double band;          // band tier (>= delta): FP32 operands, FP64 sum
+  // FP64 scaled-W variant only: 0 the weights 1/(E_k - E); 1 and 2 the
+  // real and imaginary parts of 1/(E_k - i Gamma_k/2 - E) (damped poles)
+  int part;
 };
 hipError_t launch_polesum(const PsLaunch &L, int variant, hipStream_t st);
 hipError_t launch_polesum_pd(const PsLaunch &L, hipStream_t st);
@@ -199,6 +204,10 @@ struct MatchLaunch {
   int grid;
   int solve_fp32;             // FP32 factorisation refined in FP64
   int refine_iters;           // at most this many corrections
+  // radiation-damped photoionization: per symmetry the workspace holds the
+  // 2n x 2n real form of the complex driven system (leading dimension
+  // 2n + 2), then R_re, R_im (n x n each) and g_re, g_im (n each)
+  int damped;
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
 // R(a) -> R(A) for the symmetries with outer-region sectors (same launch
@@ -208,9 +217,11 @@ hipError_t launch_propagate(const MatchLaunch &L, hipStream_t st);
 // Dipole pole sum g_i(E) = (1/sqrt2) sum_k w_ik d_k / (E_k - E) of one
 // symmetry (sorted channel order) at the m energies E, written to
 // out + e*estride + off + i.
+// part as for PsLaunch: 0 undamped, 1 and 2 the real and imaginary parts
+// with damped pole energies E_k - i Gamma_k/2.
 hipError_t launch_dip_polesum(const SymDev &S, const double *E, int m,
                               double *out, int64_t estride, int64_t off,
-                              hipStream_t st);
+                              hipStream_t st, int part = 0);
 
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v,

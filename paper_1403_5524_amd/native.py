@@ -24,6 +24,7 @@ RM_E_REFINE_NOCONV = 0x20
 RM_FLAG_AUTOTUNE = 0x1
 RM_FLAG_NO_PAIR_PRODUCTS = 0x2
 RM_FLAG_PAIR_PRODUCTS = 0x4
+RM_FLAG_RADIATION_DAMPING = 0x8
 
 EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_sweep_energies_noalloc",
@@ -34,6 +35,7 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
             "rm_plan_create", "rm_plan_execute", "rm_plan_info",
             "rm_plan_free", "rm_set_propagation", "rm_load_dipoles",
+            "rm_load_widths",
             "rm_photoionization",
             "rm_convolve_gaussian",
             "rm_effective_collision_strengths",
@@ -116,6 +118,7 @@ def lib():
         L.rm_plan_free.argtypes = [vp]
         L.rm_set_propagation.argtypes = [vp, f64, i32, i32, vp, vp]
         L.rm_load_dipoles.argtypes = [vp, vp, vp]
+        L.rm_load_widths.argtypes = [vp, vp, vp]
         L.rm_photoionization.argtypes = [vp, i32, vp, i64, f64,
                                          ctypes.POINTER(Opts), vp, vp, vp]
         L.rm_convolve_gaussian.argtypes = [vp, i64, vp, i64, f64, vp, vp]
@@ -531,6 +534,15 @@ def rm_load_dipoles(sym, d):
     if d.size != sym.n_poles:
         raise RmError(RM_ERR_ARG, "d must hold n_poles values")
     _check(lib().rm_load_dipoles(sym.handle, d.ctypes.data, _stream()))
+
+
+def rm_load_widths(sym, gamma):
+    """Attach the radiative widths Gamma_k [n_poles] (host, >= 0) to a
+    loaded symmetry for the damped photoionization."""
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    if g.size != sym.n_poles:
+        raise RmError(RM_ERR_ARG, "gamma must hold n_poles values")
+    _check(lib().rm_load_widths(sym.handle, g.ctypes.data, _stream()))
 
 
 def rm_photoionization(syms, E, e0, opts=None, sigma=None, status=None):

@@ -165,6 +165,14 @@ def photo_b2(M=409600):
     return w, dip, -0.8
 
 
+def radiative_widths(n_poles, seed, lo=1e-6, hi=1e-3):
+    """Radiative widths Gamma_k of the inner-region states for the damped
+    photoionization: log-uniform in [lo, hi] Ry (inner-shell radiative
+    widths run from micro- to milli-Rydberg), numpy PCG64 with the seed."""
+    rng = np.random.default_rng(seed)
+    return 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), size=n_poles)
+
+
 def photo_ca2(M=6000):
     """Stand-in for the Ca II photoionization run (Sec. 3, Table 2: 513
     target states, 1815 coupled channels, Hamiltonian dimension 23,073,

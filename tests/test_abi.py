@@ -80,10 +80,21 @@ def test_sweep_rejects_invalid(L):
                             | native.RM_FLAG_PAIR_PRODUCTS)
     assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(both), None,
                                None, None) == native.RM_ERR_ARG
-    unknown = native.make_opts(flags=0x8)
+    unknown = native.make_opts(flags=0x10)
     assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(unknown), None,
                                None, None) == native.RM_ERR_ARG
     assert b"flags" in L.rm_last_error()
+    damp = native.make_opts(flags=native.RM_FLAG_RADIATION_DAMPING)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(damp), None,
+                               None, None) == native.RM_ERR_ARG
+    assert b"rm_photoionization only" in L.rm_last_error()
+    band = native.make_opts(prec=1, near_delta=1e-2, band_delta=1e-3)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(band), None,
+                               None, None) == native.RM_ERR_ARG
+    assert b"band_delta" in L.rm_last_error()
+    s32 = native.make_opts(solve_fp32=2)
+    assert L.rm_sweep_energies(arr, 1, 1, None, 0, ctypes.byref(s32), None,
+                               None, None) == native.RM_ERR_ARG
 
 
 def test_null_handles_rejected(L):
@@ -163,6 +174,16 @@ def test_photo_rejects_invalid(L):
                                 None) == native.RM_ERR_ARG
     assert b"e0" in L.rm_last_error()
     assert L.rm_load_dipoles(None, dummy, None) == native.RM_ERR_ARG
+    assert L.rm_load_widths(None, dummy, None) == native.RM_ERR_ARG
+    # damping needs the FP64 pole sum and solve
+    for bad in (native.make_opts(prec=1,
+                                 flags=native.RM_FLAG_RADIATION_DAMPING),
+                native.make_opts(solve_fp32=1,
+                                 flags=native.RM_FLAG_RADIATION_DAMPING)):
+        assert L.rm_photoionization(arr, 1, dummy, 4, f64(-1.0),
+                                    ctypes.byref(bad), dummy, None,
+                                    None) == native.RM_ERR_ARG
+        assert b"damped" in L.rm_last_error()
 
 
 def test_propagation_rejects_invalid(L):
