@@ -327,6 +327,15 @@ __device__ void pd_item(const SymDev &S, int pb, int grp,
   // epilogue: the near and band tiers, scale, store both triangles.
   // 16x16 FP32 MFMA result: D[i][j] at lane j + 16 (i / 4), register i % 4.
   const double scale = 1.0 / (2.0 * S.a);
+  // this lane's 16 pairs (rows of its accumulators) and their channels
+  int gij[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = row0 + wave * 64 + a * 16 + 4 * kq + r;
+      gij[a][r] = p < S.np ? S.pair_ij[p] : -1;
+    }
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
     const int el = b * 16 + col;
@@ -336,29 +345,40 @@ __device__ void pd_item(const SymDev &S, int pb, int grp,
     const f2 ee = sm.Ee2[el];
     const int klo = sm.klo[el], khi = sm.khi[el];
     double *Re = Rbase + (int64_t)e * estride;
+    // the near and band tiers of this energy: one weight per pole, applied
+    // to all 16 pairs
+    double cor[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cor[a][r] = 0.0;
+    for (int k = klo; k < khi; ++k) {
+      const double ek = S.E_pole[k];
+      const float df = pd_diff(pd_split(ek), ee);
+      if (!(fabsf(df) < band32)) continue;  // D's test: in the GEMM
+      // near tier: FP64 operands; band tier: FP32-rounded operands
+      const bool nr = fabsf(df) < delta32;
+      const double t = nr ? 1.0 / (ek - Ee) : (double)__builtin_amdgcn_rcpf(df);
+      const double *wk = S.Wt + (int64_t)k * S.n_pad;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ij = max(gij[a][r], 0);
+          const double wi = wk[ij >> 16], wj = wk[ij & 0xffff];
+          const double x = nr ? wi : (double)(float)wi;
+          const double y = nr ? wj : (double)(float)wj;
+          cor[a][r] = fma(x * y, t, cor[a][r]);
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int p = row0 + wave * 64 + a * 16 + 4 * kq + r;
-        if (p >= S.np) continue;
-        const int ij = S.pair_ij[p];
+        const int ij = gij[a][r];
+        if (ij < 0) continue;
         const int gi = ij >> 16, gj = ij & 0xffff;
-        double v = (double)acc[a][b][r];
-        for (int k = klo; k < khi; ++k) {
-          const double ek = S.E_pole[k];
-          const f2 ek2 = pd_split(ek);
-          if (!pd_near(ek2, ee, band32)) continue;  // D's test: in the GEMM
-          const double wi = S.Wt[(int64_t)k * S.n_pad + gi];
-          const double wj = S.Wt[(int64_t)k * S.n_pad + gj];
-          if (pd_near(ek2, ee, delta32)) {
-            v += wi * wj / (ek - Ee);
-          } else {
-            const double d32 = (double)__builtin_amdgcn_rcpf(pd_diff(ek2, ee));
-            v += (double)(float)wi * (double)(float)wj * d32;
-          }
-        }
-        v *= scale;
+        const double v = ((double)acc[a][b][r] + cor[a][r]) * scale;
         Re[(int64_t)gi * ld + gj] = v;
         if (gi != gj) Re[(int64_t)gj * ld + gi] = v;
       }
