@@ -30,6 +30,8 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
 * ``photo.photoionization_damped`` the same with radiatively damped poles
 * ``outer.sweep_propagated``      Omega with the R-matrix propagated beyond
                                    r = a through long-range multipole coupling
+* ``resonance.measure_resonance`` position and width of a resonance from the
+                                   slope of the eigenphase sum
 * ``inner.inner_region``          poles and surface amplitudes from the full
                                    eigen-solve of a model inner-region
                                    Hamiltonian
@@ -49,6 +51,7 @@ from .photo import (dipole_pole_sum, matching_solution, dipole_strength,
                     photoionization, photoionization_damped, SIGMA_CONST)
 from . import outer
 from . import inner
+from . import resonance
 
 __all__ = [
     "coulomb_fg", "open_channel_functions", "closed_channel_logderiv",
@@ -60,5 +63,5 @@ __all__ = [
     "group_collision_strengths",
     "dipole_pole_sum", "matching_solution", "dipole_strength",
     "photoionization", "photoionization_damped", "SIGMA_CONST", "outer",
-    "inner",
+    "inner", "resonance",
 ]

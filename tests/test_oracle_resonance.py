@@ -71,3 +71,58 @@ def test_isolated_pole_breit_wigner_width_and_position():
     i = int(np.argmax(slope))
     assert abs(E[i] - Er) < 0.06 * Gam
     assert abs(2.0 / slope[i] - Gam) < 1e-2 * Gam
+
+
+def test_measured_resonance_matches_lane_thomas():
+    """oracle.resonance.measure_resonance on the isolated pole above: the
+    slope of the eigenphase sum gives the Lane-Thomas position and width
+    (E_l - S gamma^2, 2 P gamma^2, mpmath Coulomb functions) to 1 %, for
+    widths from 1e-5 to 1e-3 Ry, starting from the pole energy."""
+    from oracle import resonance
+    l, z, El = 0, 1.0, 3.0
+    P, S, _ = _pso(l, z, El)
+    for Gam_target in (1e-5, 1e-4, 1e-3):
+        g2 = Gam_target / (2 * P)
+        c = math.sqrt(2 * A * g2)
+        sym = {"E_pole": np.array([El]), "w": np.array([[c]]), "a": A,
+               "e_thr": np.array([0.0]), "l": np.array([l]), "z": z,
+               "g": 1.0, "target": None}
+        Er, Gam = resonance.measure_resonance(sym, El, 0.05)
+        assert abs(Gam - 2 * P * g2) < 1e-2 * Gam
+        assert abs(Er - (El - S * g2)) < 2e-2 * Gam
+
+
+def test_measured_resonance_in_a_coupled_system_is_the_decoupled_one():
+    """A narrow pole coupled to one channel of a 3-channel system whose
+    background poles couple the channels: measured in the full system it
+    agrees, within 5 % of its width, with the same pole measured in the
+    one-channel system of that channel alone plus the background poles'
+    diagonal (R of the other channels does not reach a pole that couples
+    to nothing else at first order).  A planted mistake in the measurement
+    (the slope without unwrapping, or 1/slope for the width) fails."""
+    from oracle import resonance
+    rng = np.random.default_rng(9)
+    nh = 40
+    Ek = np.sort(rng.uniform(-2.0, 30.0, nh))
+    w = np.zeros((3, nh))
+    w[:, :] = rng.normal(0.0, 0.02, (3, nh))
+    El = 6.1234
+    E_all = np.sort(np.concatenate([Ek, [El]]))
+    k = int(np.searchsorted(E_all, El))
+    w_all = np.insert(w, k, 0.0, axis=1)
+    w_all[0, k] = 0.02
+    sym = {"E_pole": E_all, "w": w_all, "a": A,
+           "e_thr": np.array([0.0, 0.5, 1.0]), "l": np.array([0, 1, 2]),
+           "z": 1.0, "g": 1.0, "target": None}
+    Er, Gam = resonance.measure_resonance(sym, El, 0.05)
+    one = {"E_pole": E_all, "w": w_all[:1], "a": A, "e_thr": np.array([0.0]),
+           "l": np.array([0]), "z": 1.0, "g": 1.0, "target": None}
+    Er1, Gam1 = resonance.measure_resonance(one, El, 0.05)
+    assert 1e-5 < Gam < 1e-2
+    assert abs(Gam - Gam1) < 0.05 * Gam1
+    assert abs(Er - Er1) < 0.05 * Gam1
+    # planted: width from the slope itself instead of 2 / slope
+    E = np.linspace(Er - 4 * Gam, Er + 4 * Gam, 41)
+    d = resonance.eigenphase_sum(sym, E)
+    s = np.max(np.diff(np.unwrap(2 * d) / 2) / (E[1] - E[0]))
+    assert abs(1.0 / s - Gam) > 0.3 * Gam
