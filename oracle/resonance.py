@@ -65,8 +65,9 @@ def measure_resonance(sym, E_guess, span, n=40, levels=14, refine=2):
 
     Grids of n points centred on E_guess shrink by 4 per level from
     +- span until the eigenphase sum rises by more than pi/2 across the
-    grid: the resonance is then inside and resolved (below that, a rise of
-    pi between two grid points is invisible modulo pi).  Its slope peak
+    grid with its steepest point in the central half: the resonance is then
+    inside and resolved (below that, a rise of pi between two grid points is
+    invisible modulo pi; off centre, it belongs to a wider neighbour).  Its slope peak
     gives (E_r, 2 / slope), refined on grids of +- 4 Gamma around it.  n is
     even, so a grid centred on a pole energy never evaluates on it.  Returns
     NaNs if no level shows the rise."""
@@ -78,8 +79,10 @@ def measure_resonance(sym, E_guess, span, n=40, levels=14, refine=2):
         if not np.all(np.isfinite(d)):
             return float("nan"), float("nan")
         du = np.unwrap(2.0 * d) / 2.0
-        if du[-1] - du[0] > 0.5 * np.pi:
-            Er, smax = _peak_slope(E, d)
+        Er, smax = _peak_slope(E, d)
+        # a rise of over pi/2 whose steepest point is in the central half:
+        # the resonance at E_guess, not a wider neighbour at the edge
+        if du[-1] - du[0] > 0.5 * np.pi and abs(Er - E_guess) < 0.5 * half:
             G = _width(smax, E[1] - E[0])
             for _ in range(refine):
                 E = np.linspace(Er - 4.0 * G, Er + 4.0 * G, n)
@@ -88,3 +91,32 @@ def measure_resonance(sym, E_guess, span, n=40, levels=14, refine=2):
             return float(Er), float(G)
         half /= 4.0
     return float("nan"), float("nan")
+
+
+def _measure_one(args):
+    sym, Er, span = args
+    return measure_resonance(sym, Er, span)
+
+
+def measure_list(sym, nominal, span_factor=30.0, workers=1):
+    """Measure every resonance of a nominal (E, width) list: each scan
+    starts at E over +- span_factor * width.  workers > 1 spreads the
+    resonances over that many processes (one BLAS thread each)."""
+    jobs = [(sym, float(E), span_factor * float(G)) for E, G in nominal]
+    if workers <= 1:
+        return [_measure_one(j) for j in jobs]
+    import multiprocessing as mp
+    import os
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                          "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            return pool.map(_measure_one, jobs)
+    finally:
+        for k, v in env.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v

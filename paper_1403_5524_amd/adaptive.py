@@ -223,81 +223,117 @@ def integrated_error(test, fine, rel_floor=1e-6):
     return float(rel.max()), float(rel.mean())
 
 
-def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
-                   lo=0.0, hi=20.0, M_fine=1000000, M_adapt=100000,
-                   nw=4096, steps=1500, log=print, label="curvature"):
-    """Train on train_seeds, evaluate uniform / heuristic / learned meshes of
-    M_adapt points on test_seed against the M_fine uniform fine mesh.
+def train_set(seeds, n=200, n_poles=8000, n_narrow=50, lo=0.0, hi=20.0,
+              dE_fine=2e-5, nw=4096, sub=1.0, log=print):
+    """Features and curvature labels of the training systems.
 
-    label "curvature" (default): the network learns log10 of each window's
-    largest second difference of sum Omega (relative to the median window)
-    and the density follows its square root (a peak of width G and height
-    A has curvature ~ A/G^2, so the density grows as 1/G: what resolving it
-    takes); "variation": it learns the window's total variation (relative
-    to the mean) and the density follows it."""
+    Each seed's system (the test system's kind) is swept with the plain
+    FP64 method on the fine spacing dE_fine, but only over a sub-window of
+    `sub` Ry placed by the seed inside the open region, so that hundreds of
+    systems cost what a few full sweeps would; the labels are those of the
+    windows of the [lo, hi] grid that lie wholly inside it."""
     import torch
     from . import workloads as wl
     dev = torch.device("cuda:0")
+    h = (hi - lo) / nw
     feats, labels = [], []
-    for s in train_seeds:
-        sym, truth, spec = wl.narrow_resonance_system(
+    for s in seeds:
+        sym, _, _ = wl.narrow_resonance_system(
             s, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
-            mesh_hi=hi, M_fine=M_fine)
-        h = native.load_symmetry(sym)
-        E = torch.as_tensor(wl.uniform_mesh(lo, hi, M_fine), device=dev)
-        j = sweep_integrals([h], n, E, lo, hi, nw=nw)
-        feats.append(window_features(sym, lo, hi, nw))
-        if label == "curvature":   # a few sharp peaks dominate its mean
-            labels.append(labels_from_variation(j.curvature, "median"))
-        else:
-            labels.append(labels_from_variation(j.variation))
-        log("labels: min %.2f median %.2f max %.2f, %d not finite"
-            % (labels[-1].min(), np.median(labels[-1]), labels[-1].max(),
-               int((~np.isfinite(labels[-1])).sum())))
-        h.free()
-        log("train system %d swept (%d energies)" % (s, M_fine))
-    X = np.concatenate(feats)
-    y = np.concatenate(labels)
+            mesh_hi=hi, M_fine=int(round((hi - lo) / dE_fine)))
+        rng = np.random.default_rng(s + 7)
+        a0 = rng.uniform(max(lo, 2.2), hi - sub)
+        w0, w1 = int(math.ceil((a0 - lo) / h)), int(math.floor((a0 + sub - lo) / h))
+        b0, b1 = lo + w0 * h, lo + w1 * h
+        M = int(round((b1 - b0) / dE_fine))
+        E = torch.as_tensor(b0 + (np.arange(M) + 0.5) * ((b1 - b0) / M),
+                            device=dev)
+        hd = native.load_symmetry(sym)
+        j = sweep_integrals([hd], n, E, b0, b1, nw=w1 - w0)
+        hd.free()
+        f = window_features(sym, lo, hi, nw)[w0:w1]
+        feats.append(f)
+        labels.append(labels_from_variation(j.curvature, "median"))
+    log("training set: %d systems, %d windows" % (len(seeds),
+                                                  sum(x.shape[0] for x in feats)))
+    return np.concatenate(feats), np.concatenate(labels)
+
+
+def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
+                   lo=0.0, hi=20.0, M_fine=1000000, M_adapt=100000,
+                   nw=4096, steps=1500, log=print, truth_fn=None,
+                   train_sub=1.0, couple=0.5):
+    """Train on train_seeds (sub-window sweeps, train_set), then compare
+    meshes of M_adapt points on test_seed against the M_fine uniform fine
+    mesh: uniform, the non-learned coupling heuristic, the learned density
+    alone, and the learned density mixed with the heuristic (weight
+    `couple` on the heuristic; both normalised to unit mass first).
+
+    The network learns log10 of each window's largest second difference
+    of sum Omega relative to the median window; the density follows its
+    square root (a peak of width G and height A has curvature ~ A/G^2, so
+    the density grows as 1/G: what resolving it takes).
+
+    truth_fn(sym, nominal) -> [(E_r, Gamma)] measures the test system's
+    resonances near the injected poles (nominal: the generator's
+    (E_pole, proxy width) list); without it the nominal list is used."""
+    import torch
+    from . import workloads as wl
+    dev = torch.device("cuda:0")
+    X, y = train_set(train_seeds, n=n, n_poles=n_poles, n_narrow=n_narrow,
+                     lo=lo, hi=hi, dE_fine=(hi - lo) / M_fine, nw=nw,
+                     sub=train_sub, log=log)
     norm = Normaliser(X)
     mlp, hist = train_mlp(norm(X), y, steps=steps, log=log)
 
-    sym, truth, spec = wl.narrow_resonance_system(
+    sym, nominal, spec = wl.narrow_resonance_system(
         test_seed, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
         mesh_hi=hi, M_fine=M_fine)
+    truth = np.asarray(truth_fn(sym, nominal) if truth_fn else nominal)
     h = native.load_symmetry(sym)
     Ej = torch.as_tensor(wl.uniform_mesh(lo, hi, M_fine), device=dev)
     fine = sweep_integrals([h], n, Ej, lo, hi, nw=nw)
     Xt = torch.as_tensor(norm(window_features(sym, lo, hi, nw)), device=dev)
     pred = mlp.forward(Xt)
+    heur = torch.as_tensor(heuristic_density(sym, lo, hi, nw), device=dev)
+    learned = torch.pow(10.0, 0.5 * pred.float())
+    mix = ((1.0 - couple) * learned / learned.sum()
+           + couple * heur / heur.sum()).contiguous()
     meshes = {
         "uniform": torch.as_tensor(wl.uniform_mesh(lo, hi, M_adapt), device=dev),
-        "heuristic": native.rm_mesh_from_density(
-            torch.as_tensor(heuristic_density(sym, lo, hi, nw), device=dev),
-            lo, hi, 0.3, M_adapt),
-        "learned": mesh_from_log_density(
-            pred, lo, hi, M_adapt, alpha=0.5 if label == "curvature" else 1.0),
+        "heuristic": native.rm_mesh_from_density(heur, lo, hi, 0.3, M_adapt),
+        "learned": native.rm_mesh_from_density(learned.contiguous(), lo, hi,
+                                               0.3, M_adapt),
+        "learned+coupling": native.rm_mesh_from_density(mix, lo, hi, 0.3,
+                                                        M_adapt),
     }
     min_w = 2.0 * (hi - lo) / M_fine
+    ok = np.isfinite(truth).all(axis=1)
     out = {"train_loss": hist, "fine_points": M_fine, "points": M_adapt,
-           "label": label}
+           "train_systems": len(train_seeds), "train_windows": int(X.shape[0]),
+           "test_seed": test_seed,
+           "truth": "measured" if truth_fn else "nominal",
+           "truth_resonances": int(ok.sum()),
+           "truth_width_range": [float(truth[ok, 1].min()),
+                                 float(truth[ok, 1].max())] if ok.any() else None}
     for name, E in meshes.items():
         r = sweep_integrals([h], n, E, lo, hi)
         mx, mean = integrated_error(r, fine)
-        miss, tot = missed_resonances(E.cpu().numpy(), truth, min_w)
+        miss, tot = missed_resonances(E.cpu().numpy(), truth[ok], min_w)
         out[name] = {"int_err_max": mx, "int_err_mean": mean,
                      "missed": miss, "resonances": tot}
-        log("%-9s int err max %.3e mean %.3e missed %d/%d"
+        log("%-16s int err max %.3e mean %.3e missed %d/%d"
             % (name, mx, mean, miss, tot))
     h.free()
     mlp.free()
     return out
 
 
-if __name__ == "__main__":   # full-size experiment on the GPU
+if __name__ == "__main__":   # training on the full seed range (GPU)
     import json
     import sys
-    label = sys.argv[1] if len(sys.argv) > 1 else "curvature"
-    res = run_experiment(train_seeds=list(range(1000, 1004)), test_seed=3000,
-                         label=label)
+    last = int(sys.argv[1]) if len(sys.argv) > 1 else 1255
+    res = run_experiment(train_seeds=list(range(1000, last + 1)),
+                         test_seed=3000)
     json.dump(res, sys.stdout)
     print()
