@@ -25,6 +25,9 @@ through multipole coupling (rm_set_propagation) under "outer_propagation".
 An inner-region leg times the full eigen-solve that supplies poles and
 amplitudes (rm_inner_region, 8 channels x 512 sine functions, D = 4096) under
 "inner_region", with the oracle's solve of the same model as its CPU baseline.
+A learned-mesh leg trains the network on narrow-resonance systems and judges
+its 1e5-point adaptive mesh against a 1e6-point uniform sweep under
+"learned_mesh".
 """
 import argparse
 import json
@@ -435,6 +438,26 @@ def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
     return out
 
 
+def c5_leg(n_train, workers, log):
+    """The learned adaptive mesh at full size: trained on seeds 1000 ..
+    1000 + n_train - 1 of the narrow-resonance generator (200 channels,
+    8000 + 50 poles; one 1 Ry sub-window of the 2e-5 Ry fine spacing per
+    seed), judged on seed 3000 against its 1e6-point uniform FP64 sweep on
+    [0, 20] Ry, 1e5 adaptive points; truth resonances measured by the
+    oracle from the slope of the eigenphase sum."""
+    from oracle import resonance
+    from paper_1403_5524_amd import adaptive
+
+    def truth(sym, nominal):
+        return resonance.measure_list(sym.as_dict(), nominal, workers=workers)
+    t0 = time.perf_counter()
+    res = adaptive.run_experiment(train_seeds=list(range(1000, 1000 + n_train)),
+                                  test_seed=3000, truth_fn=truth, log=log)
+    res["seconds"] = time.perf_counter() - t0
+    res.pop("train_loss", None)
+    return res
+
+
 def table3_leg(native, torch, oracle, workloads):
     """The FP64 pole sum (rm_rmatrix) on the ten shapes of the paper's
     Table 3: enough energies per shape to fill the GPU (4096, fewer for the
@@ -507,6 +530,9 @@ def main():
     ap.add_argument("--photo-ca-M", type=int, default=2048,
                     help="energies of the photoionization leg on the Ca II "
                          "shape (1815 channels, 6000 energies); 0 skips it")
+    ap.add_argument("--c5-train", type=int, default=32,
+                    help="training seeds of the learned-mesh leg (full-size "
+                         "1e6-point judge, 1e5 adaptive points); 0 skips it")
     ap.add_argument("--photo-M", type=int, default=8192,
                     help="energies of the photoionization leg (B II shape); "
                          "0 skips it")
@@ -681,6 +707,10 @@ def main():
         photo_ca = photo_leg(native, torch, oracle, workloads, 1, 0,
                              args.photo_ca_M, shape="ca2", n_check=2)
     table3 = table3_leg(native, torch, oracle, workloads) if args.table3 else None
+    c5 = None
+    if args.c5_train > 0:
+        c5 = c5_leg(args.c5_train, max(1, min(16, (os.cpu_count() or 2) - 1)),
+                    note)
     inner_res = None
     if args.inner_N > 0:
         inner_res = inner_leg(native, oracle, workloads, max(1, min(args.steps, 2)),
@@ -729,6 +759,7 @@ def main():
         "photoionization_ca2": photo_ca,
         "outer_propagation": outer_res,
         "inner_region": inner_res,
+        "learned_mesh": c5,
         "table3": table3,
     }
     if cpu_rec is not None:

@@ -159,12 +159,17 @@ def heuristic_density(sym, lo, hi, nw):
 
 
 class Normaliser:
+    """Per-feature standardisation from the training set; a feature that is
+    (nearly) constant there is only centred, and every standardised value
+    is clipped to +-8, so that a test window outside the training range
+    cannot drive the network far from what it was trained on."""
+
     def __init__(self, X):
         self.mu = X.mean(axis=0)
-        self.sd = X.std(axis=0) + 1e-6
+        self.sd = np.maximum(X.std(axis=0), 1e-2)
 
     def __call__(self, X):
-        return ((X - self.mu) / self.sd).astype(np.float32)
+        return np.clip((X - self.mu) / self.sd, -8.0, 8.0).astype(np.float32)
 
 
 def train_mlp(X, y, width=256, n_layers=4, steps=1500, batch=1024, lr=1e-3,
@@ -223,15 +228,39 @@ def integrated_error(test, fine, rel_floor=1e-6):
     return float(rel.max()), float(rel.mean())
 
 
+def relative_curvature(handle, n, E, nwin):
+    """Per window of a uniform mesh E (device, nwin equal windows), the
+    largest second difference of any single transition's Omega relative to
+    that transition's largest value over the mesh: the trapezoid rule's
+    error for the worst-sampled transition, not only for the strong ones
+    that dominate the sum."""
+    import torch
+    om, _ = native.rm_sweep_energies([handle], n, E)
+    scale = om.abs().amax(dim=0).clamp_min(1e-300)
+    d2 = (om[2:] - 2.0 * om[1:-1] + om[:-2]).abs() / scale
+    del om
+    per_e = d2.amax(dim=1)            # worst transition at each energy
+    del d2
+    M = int(E.numel())
+    wi = (torch.arange(1, M - 1, device=E.device) * nwin) // M
+    out = np.zeros(nwin)
+    v = per_e.cpu().numpy()
+    w = wi.cpu().numpy()
+    ok = np.isfinite(v)
+    np.maximum.at(out, w[ok], v[ok])
+    return out
+
+
 def train_set(seeds, n=200, n_poles=8000, n_narrow=50, lo=0.0, hi=20.0,
-              dE_fine=2e-5, nw=4096, sub=1.0, log=print):
+              dE_fine=2e-5, nw=4096, sub=1.0, log=print, label="sum"):
     """Features and curvature labels of the training systems.
 
     Each seed's system (the test system's kind) is swept with the plain
     FP64 method on the fine spacing dE_fine, but only over a sub-window of
-    `sub` Ry placed by the seed inside the open region, so that hundreds of
-    systems cost what a few full sweeps would; the labels are those of the
-    windows of the [lo, hi] grid that lie wholly inside it."""
+    `sub` Ry placed by the seed anywhere in [lo, hi] (thresholds and their
+    Rydberg series included), so that hundreds of systems cost what a few
+    full sweeps would; the labels are those of the windows of the [lo, hi]
+    grid that lie wholly inside it."""
     import torch
     from . import workloads as wl
     dev = torch.device("cuda:0")
@@ -242,37 +271,64 @@ def train_set(seeds, n=200, n_poles=8000, n_narrow=50, lo=0.0, hi=20.0,
             s, n=n, n_poles=n_poles, n_narrow=n_narrow, mesh_lo=lo,
             mesh_hi=hi, M_fine=int(round((hi - lo) / dE_fine)))
         rng = np.random.default_rng(s + 7)
-        a0 = rng.uniform(max(lo, 2.2), hi - sub)
+        a0 = rng.uniform(lo, hi - sub)
         w0, w1 = int(math.ceil((a0 - lo) / h)), int(math.floor((a0 + sub - lo) / h))
         b0, b1 = lo + w0 * h, lo + w1 * h
         M = int(round((b1 - b0) / dE_fine))
         E = torch.as_tensor(b0 + (np.arange(M) + 0.5) * ((b1 - b0) / M),
                             device=dev)
         hd = native.load_symmetry(sym)
-        j = sweep_integrals([hd], n, E, b0, b1, nw=w1 - w0)
+        if label == "relative":
+            lab = relative_curvature(hd, n, E, w1 - w0)
+        else:
+            j = sweep_integrals([hd], n, E, b0, b1, nw=w1 - w0)
+            lab = j.curvature
         hd.free()
         f = window_features(sym, lo, hi, nw)[w0:w1]
         feats.append(f)
-        labels.append(labels_from_variation(j.curvature, "median"))
+        labels.append(labels_from_variation(lab, "median"))
+        if len(feats) % 16 == 0:
+            log("training systems swept: %d of %d" % (len(feats), len(seeds)))
     log("training set: %d systems, %d windows" % (len(seeds),
                                                   sum(x.shape[0] for x in feats)))
     return np.concatenate(feats), np.concatenate(labels)
 
 
+def keep_off_poles(E, sym, gap=1e-9):
+    """Move the points of an adaptive mesh (device, ascending) that sit
+    within `gap` of a pole or threshold of sym to 2 gap from it (the
+    uniform meshes are drawn to keep that distance; an adaptive one must
+    keep it too, or the pole sum divides by ~0)."""
+    import torch
+    e = E.cpu().numpy()
+    for x in (np.asarray(sym.E_pole), np.sort(np.asarray(sym.e_thr))):
+        k = np.clip(np.searchsorted(x, e), 1, x.size - 1)
+        near = np.where(np.abs(e - x[k]) < np.abs(e - x[k - 1]), x[k], x[k - 1])
+        bad = np.abs(e - near) < gap
+        e[bad] = near[bad] + np.where(e[bad] >= near[bad], 2 * gap, -2 * gap)
+    return torch.as_tensor(np.sort(e), device=E.device)
+
+
 def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
                    lo=0.0, hi=20.0, M_fine=1000000, M_adapt=100000,
                    nw=4096, steps=1500, log=print, truth_fn=None,
-                   train_sub=1.0, couple=0.5):
+                   train_sub=1.0, couple=0.25, floor=0.7, alpha=0.35,
+                   label="sum"):
     """Train on train_seeds (sub-window sweeps, train_set), then compare
     meshes of M_adapt points on test_seed against the M_fine uniform fine
     mesh: uniform, the non-learned coupling heuristic, the learned density
     alone, and the learned density mixed with the heuristic (weight
-    `couple` on the heuristic; both normalised to unit mass first).
+    `couple` on the heuristic; both normalised to unit mass first), each
+    with a uniform share `floor` of the points.
 
     The network learns log10 of each window's largest second difference
-    of sum Omega relative to the median window; the density follows its
-    square root (a peak of width G and height A has curvature ~ A/G^2, so
-    the density grows as 1/G: what resolving it takes).
+    of sum Omega relative to the median window; the density follows
+    10^(alpha * prediction): alpha = 1/2 would follow the square root of
+    the curvature (a peak of width G and height A has curvature ~ A/G^2, so
+    the density grows as 1/G); the default 0.35, with the uniform share 0.7
+    and the coupling weight 0.25, was chosen on the 32-channel case of the
+    GPU test, where it resolves every resonance without raising the
+    largest integration error above the uniform mesh's.
 
     truth_fn(sym, nominal) -> [(E_r, Gamma)] measures the test system's
     resonances near the injected poles (nominal: the generator's
@@ -282,7 +338,7 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
     dev = torch.device("cuda:0")
     X, y = train_set(train_seeds, n=n, n_poles=n_poles, n_narrow=n_narrow,
                      lo=lo, hi=hi, dE_fine=(hi - lo) / M_fine, nw=nw,
-                     sub=train_sub, log=log)
+                     sub=train_sub, log=log, label=label)
     norm = Normaliser(X)
     mlp, hist = train_mlp(norm(X), y, steps=steps, log=log)
 
@@ -296,22 +352,25 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
     Xt = torch.as_tensor(norm(window_features(sym, lo, hi, nw)), device=dev)
     pred = mlp.forward(Xt)
     heur = torch.as_tensor(heuristic_density(sym, lo, hi, nw), device=dev)
-    learned = torch.pow(10.0, 0.5 * pred.float())
+    learned = torch.pow(10.0, alpha * pred.float())
     mix = ((1.0 - couple) * learned / learned.sum()
            + couple * heur / heur.sum()).contiguous()
     meshes = {
         "uniform": torch.as_tensor(wl.uniform_mesh(lo, hi, M_adapt), device=dev),
-        "heuristic": native.rm_mesh_from_density(heur, lo, hi, 0.3, M_adapt),
+        "heuristic": native.rm_mesh_from_density(heur, lo, hi, floor, M_adapt),
         "learned": native.rm_mesh_from_density(learned.contiguous(), lo, hi,
-                                               0.3, M_adapt),
-        "learned+coupling": native.rm_mesh_from_density(mix, lo, hi, 0.3,
+                                               floor, M_adapt),
+        "learned+coupling": native.rm_mesh_from_density(mix, lo, hi, floor,
                                                         M_adapt),
     }
+    for k in ("heuristic", "learned", "learned+coupling"):
+        meshes[k] = keep_off_poles(meshes[k], sym)
     min_w = 2.0 * (hi - lo) / M_fine
     ok = np.isfinite(truth).all(axis=1)
     out = {"train_loss": hist, "fine_points": M_fine, "points": M_adapt,
            "train_systems": len(train_seeds), "train_windows": int(X.shape[0]),
            "test_seed": test_seed,
+           "density": {"alpha": alpha, "floor": floor, "couple": couple},
            "truth": "measured" if truth_fn else "nominal",
            "truth_resonances": int(ok.sum()),
            "truth_width_range": [float(truth[ok, 1].min()),
@@ -334,6 +393,7 @@ if __name__ == "__main__":   # training on the full seed range (GPU)
     import sys
     last = int(sys.argv[1]) if len(sys.argv) > 1 else 1255
     res = run_experiment(train_seeds=list(range(1000, last + 1)),
-                         test_seed=3000)
+                         test_seed=3000,
+                         log=lambda m: print(m, file=sys.stderr, flush=True))
     json.dump(res, sys.stdout)
     print()
