@@ -723,12 +723,16 @@ __device__ int wave_lu_solve(T *A, int na, int ld, int nrhs, WaveLds &W,
   // back substitution U X = B' on the right-hand sides, 32 rows at a time
   for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, na - j0);
+    const int r1 = j0 + jb;
+    // left-looking: this block's rows take the solved rows below at once
+    // (X_b -= U[b, >b] X[>b]), so the right-hand sides above are not
+    // rewritten once per block
+    if (r1 < na)
+      wave_gemm<0>(A + (int64_t)j0 * ld + na, ld, A + (int64_t)j0 * ld + r1,
+                   ld, A + (int64_t)r1 * ld + na, ld, jb, nrhs, na - r1);
     wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UPPER);
     wave_tile_invert<NB2>(W, TILE_UPPER);
     wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
-    if (j0 > 0)
-      wave_gemm<0>(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0,
-                   nrhs, jb);
   }
   return flag;
 }
@@ -760,12 +764,16 @@ __device__ void wave_lu_resolve(T *A, int na, int ld, int nrhs,
   }
   for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, na - j0);
+    const int r1 = j0 + jb;
+    // left-looking: this block's rows take the solved rows below at once
+    // (X_b -= U[b, >b] X[>b]), so the right-hand sides above are not
+    // rewritten once per block
+    if (r1 < na)
+      wave_gemm<0>(A + (int64_t)j0 * ld + na, ld, A + (int64_t)j0 * ld + r1,
+                   ld, A + (int64_t)r1 * ld + na, ld, jb, nrhs, na - r1);
     wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UPPER);
     wave_tile_invert<NB2>(W, TILE_UPPER);
     wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
-    if (j0 > 0)
-      wave_gemm<0>(A + na, ld, A + j0, ld, A + (int64_t)j0 * ld + na, ld, j0,
-                   nrhs, jb);
   }
 }
 
@@ -1044,12 +1052,15 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
   // Y = L^-T Z, blocks from the bottom
   for (int j0 = ((no - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, no - j0);
+    const int r1 = j0 + jb;
+    // left-looking, as the LU's back substitution: Z_b -= L[>b, b]^T Y[>b]
+    if (r1 < no)
+      wave_gemm<0, G_TA>(Aug + (int64_t)j0 * ld + no, ld,
+                         Aug + (int64_t)r1 * ld + j0, ld,
+                         Aug + (int64_t)r1 * ld + no, ld, jb, no, no - r1);
     wave_tile_stage<NB2>(Aug, ld, j0, jb, W, TILE_LOWER);
     wave_tile_invert<NB2>(W, TILE_LOWER);
     wave_tile_apply<NB2, true>(Aug, ld, j0, jb, no, 2 * no, W, false);
-    if (j0 > 0)
-      wave_gemm<0, G_TA>(Aug + no, ld, Aug + (int64_t)j0 * ld, ld,
-                         Aug + (int64_t)j0 * ld + no, ld, j0, no, jb);
   }
   return flag;
 }
