@@ -266,6 +266,124 @@ __device__ void wave_gemm(T *C, int ldc, const T *A, int lda,
   wave_sync();
 }
 
+// Wide form: output tiles of (16 BM) x (16 BN), so each A row panel is read
+// once per 16 BN columns and each B column panel once per 16 BM rows (the
+// 32 x 32 tiles above read both twice as often).  MODE 0 loads C into the
+// accumulators and subtracts A B through them (no separate C registers;
+// the next tile's C is prefetched), MODE 1 starts from the identity, MODE 2
+// from zero.  With G_LOWER only tiles whose first column is on or left of
+// their last row are formed.
+template <int MODE, int FL, int BM, int BN, class T = double>
+__device__ void wave_gemm_wide(T *C, int ldc, const T *A, int lda,
+                               const T *B, int ldb, int rows, int cols,
+                               int kd) {
+  typedef typename Mx<T>::acc acc_t;
+  constexpr int TH = 16 * BM, TW = 16 * BN;
+  const int lane = lane_id();
+  const int col = lane & 15, kq = lane >> 4;
+  const int nct = (cols + TW - 1) / TW;
+  const int ntile = ((rows + TH - 1) / TH) * nct;
+  const int nk = max(1, (kd + 15) >> 4);
+  auto skip = [&](int t) {
+    return (FL & G_LOWER) && (t % nct) * TW > (t / nct) * TH + TH - 1;
+  };
+  auto next = [&](int t) {
+    ++t;
+    while (t < ntile && skip(t)) ++t;
+    return t;
+  };
+  // fragments of k-step k0 for the tile at (rb, cb)
+  auto fload = [&](T (&a)[4][BM], T (&b)[4][BN], int rb, int cb, int k0) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int k = k0 + 4 * s4 + kq;
+      const bool kv = k < kd;
+#pragma unroll
+      for (int x = 0; x < BM; ++x) {
+        const int i = rb + 16 * x + col;
+        a[s4][x] = (kv && i < rows)
+                       ? ((FL & G_TA) ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k])
+                       : T(0);
+      }
+#pragma unroll
+      for (int y = 0; y < BN; ++y) {
+        const int j = cb + 16 * y + col;
+        b[s4][y] = (kv && j < cols)
+                       ? ((FL & G_TB) ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j])
+                       : T(0);
+      }
+    }
+  };
+  auto cload = [&](T (&c)[BM][BN][4], int rb, int cb) {
+#pragma unroll
+    for (int x = 0; x < BM; ++x)
+#pragma unroll
+      for (int y = 0; y < BN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rb + 16 * x + Mx<T>::row(kq, r), j = cb + 16 * y + col;
+          c[x][y][r] = (i < rows && j < cols) ? C[(int64_t)i * ldc + j] : T(0);
+        }
+  };
+  int t = skip(0) ? next(0) : 0;
+  if (t < ntile) {
+    T ca[4][BM], cbf[4][BN], na[4][BM], nb[4][BN];
+    T cc[BM][BN][4];
+    fload(ca, cbf, (t / nct) * TH, (t % nct) * TW, 0);
+    while (t < ntile) {
+      const int tn = next(t);
+      const int rb = (t / nct) * TH, cb = (t % nct) * TW;
+      if (MODE == 0) cload(cc, rb, cb);
+      acc_t acc[BM][BN];
+#pragma unroll
+      for (int x = 0; x < BM; ++x)
+#pragma unroll
+        for (int y = 0; y < BN; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            T v = T(0);
+            if (MODE == 0) v = cc[x][y][r];
+            if (MODE == 1)
+              v = (rb + 16 * x + Mx<T>::row(kq, r) == cb + 16 * y + col) ? T(1) : T(0);
+            acc[x][y][r] = v;
+          }
+      for (int kc = 0; kc < nk; ++kc) {
+        if (kc + 1 < nk) {
+          fload(na, nb, rb, cb, (kc + 1) * 16);
+        } else if (tn < ntile) {
+          fload(na, nb, (tn / nct) * TH, (tn % nct) * TW, 0);
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int x = 0; x < BM; ++x)
+#pragma unroll
+            for (int y = 0; y < BN; ++y)
+              acc[x][y] = Mx<T>::mfma(MODE == 0 ? -ca[s4][x] : ca[s4][x],
+                                      cbf[s4][y], acc[x][y]);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+          for (int x = 0; x < BM; ++x) ca[s4][x] = na[s4][x];
+#pragma unroll
+          for (int y = 0; y < BN; ++y) cbf[s4][y] = nb[s4][y];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < BM; ++x)
+#pragma unroll
+        for (int y = 0; y < BN; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = rb + 16 * x + Mx<T>::row(kq, r), j = cb + 16 * y + col;
+            if (i < rows && j < cols) C[(int64_t)i * ldc + j] = acc[x][y][r];
+          }
+      t = tn;
+    }
+  }
+  wave_sync();
+}
+
 // ---------------------------------------------------------------------------
 // LU with partial pivoting.
 
@@ -717,8 +835,10 @@ __device__ int wave_lu_solve(T *A, int na, int ld, int nrhs, WaveLds &W,
     wave_tile_apply<NB2>(A, ld, j0, jb, j0 + jb, ntot, W, true);
     const int r0 = j0 + jb;
     if (r0 < na)
-      wave_gemm<0>(A + (int64_t)r0 * ld + r0, ld, A + (int64_t)r0 * ld + j0,
-                   ld, A + (int64_t)j0 * ld + r0, ld, na - r0, ntot - r0, jb);
+      wave_gemm_wide<0, 0, 2, 4>(A + (int64_t)r0 * ld + r0, ld,
+                                 A + (int64_t)r0 * ld + j0, ld,
+                                 A + (int64_t)j0 * ld + r0, ld, na - r0,
+                                 ntot - r0, jb);
   }
   // back substitution U X = B' on the right-hand sides, 32 rows at a time
   for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
@@ -728,8 +848,10 @@ __device__ int wave_lu_solve(T *A, int na, int ld, int nrhs, WaveLds &W,
     // (X_b -= U[b, >b] X[>b]), so the right-hand sides above are not
     // rewritten once per block
     if (r1 < na)
-      wave_gemm<0>(A + (int64_t)j0 * ld + na, ld, A + (int64_t)j0 * ld + r1,
-                   ld, A + (int64_t)r1 * ld + na, ld, jb, nrhs, na - r1);
+      wave_gemm_wide<0, 0, 2, 4>(A + (int64_t)j0 * ld + na, ld,
+                                 A + (int64_t)j0 * ld + r1, ld,
+                                 A + (int64_t)r1 * ld + na, ld, jb, nrhs,
+                                 na - r1);
     wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UPPER);
     wave_tile_invert<NB2>(W, TILE_UPPER);
     wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
@@ -759,8 +881,10 @@ __device__ void wave_lu_resolve(T *A, int na, int ld, int nrhs,
     wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, true);
     const int r0 = j0 + jb;
     if (r0 < na)
-      wave_gemm<0>(A + (int64_t)r0 * ld + na, ld, A + (int64_t)r0 * ld + j0,
-                   ld, A + (int64_t)j0 * ld + na, ld, na - r0, nrhs, jb);
+      wave_gemm_wide<0, 0, 2, 4>(A + (int64_t)r0 * ld + na, ld,
+                                 A + (int64_t)r0 * ld + j0, ld,
+                                 A + (int64_t)j0 * ld + na, ld, na - r0, nrhs,
+                                 jb);
   }
   for (int j0 = ((na - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, na - j0);
@@ -769,8 +893,10 @@ __device__ void wave_lu_resolve(T *A, int na, int ld, int nrhs,
     // (X_b -= U[b, >b] X[>b]), so the right-hand sides above are not
     // rewritten once per block
     if (r1 < na)
-      wave_gemm<0>(A + (int64_t)j0 * ld + na, ld, A + (int64_t)j0 * ld + r1,
-                   ld, A + (int64_t)r1 * ld + na, ld, jb, nrhs, na - r1);
+      wave_gemm_wide<0, 0, 2, 4>(A + (int64_t)j0 * ld + na, ld,
+                                 A + (int64_t)j0 * ld + r1, ld,
+                                 A + (int64_t)r1 * ld + na, ld, jb, nrhs,
+                                 na - r1);
     wave_tile_stage<NB2>(A, ld, j0, jb, W, TILE_UPPER);
     wave_tile_invert<NB2>(W, TILE_UPPER);
     wave_tile_apply<NB2>(A, ld, j0, jb, na, ntot, W, false);
@@ -1023,7 +1149,7 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
                           WaveLds &W, bool want_t, double *pv) {
   int flag = 0;
   // lower triangle of 1 + K^2, and K as the right-hand side
-  wave_gemm<1, G_LOWER>(Aug, ld, Kb, lk, Kb, lk, no, no, no);
+  wave_gemm_wide<1, G_LOWER, 2, 4>(Aug, ld, Kb, lk, Kb, lk, no, no, no);
   if (want_t) wave_copy(Aug + no, ld, Kb, lk, no, no);
   wave_sync();
   // right-looking blocked Cholesky with the forward substitution Z = L^-1 K
@@ -1036,28 +1162,30 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
     if (pv) wave_photo_forward(Aug, ld, j0, jb, no, W, pv);
     if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, 2 * no, W, false);
     if (r0 < no) {
-      wave_gemm<0, G_TB | G_LOWER>(Aug + (int64_t)r0 * ld + r0, ld,
-                                    Aug + (int64_t)r0 * ld + j0, ld,
-                                    Aug + (int64_t)r0 * ld + j0, ld, no - r0,
-                                    no - r0, jb);
+      wave_gemm_wide<0, G_TB | G_LOWER, 2, 4>(
+          Aug + (int64_t)r0 * ld + r0, ld, Aug + (int64_t)r0 * ld + j0, ld,
+          Aug + (int64_t)r0 * ld + j0, ld, no - r0, no - r0, jb);
       if (want_t)
-        wave_gemm<0>(Aug + (int64_t)r0 * ld + no, ld,
-                     Aug + (int64_t)r0 * ld + j0, ld,
-                     Aug + (int64_t)j0 * ld + no, ld, no - r0, no, jb);
+        wave_gemm_wide<0, 0, 2, 4>(Aug + (int64_t)r0 * ld + no, ld,
+                                   Aug + (int64_t)r0 * ld + j0, ld,
+                                   Aug + (int64_t)j0 * ld + no, ld, no - r0,
+                                   no, jb);
     }
   }
   if (!want_t) return flag;
   // Q = Z^T Z in K's place: symmetric, so only its lower triangle
-  wave_gemm<2, G_TA | G_LOWER>(Kb, lk, Aug + no, ld, Aug + no, ld, no, no, no);
+  wave_gemm_wide<2, G_TA | G_LOWER, 2, 4>(Kb, lk, Aug + no, ld, Aug + no, ld,
+                                          no, no, no);
   // Y = L^-T Z, blocks from the bottom
   for (int j0 = ((no - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
     const int jb = min(NB2, no - j0);
     const int r1 = j0 + jb;
     // left-looking, as the LU's back substitution: Z_b -= L[>b, b]^T Y[>b]
     if (r1 < no)
-      wave_gemm<0, G_TA>(Aug + (int64_t)j0 * ld + no, ld,
-                         Aug + (int64_t)r1 * ld + j0, ld,
-                         Aug + (int64_t)r1 * ld + no, ld, jb, no, no - r1);
+      wave_gemm_wide<0, G_TA, 2, 4>(Aug + (int64_t)j0 * ld + no, ld,
+                                    Aug + (int64_t)r1 * ld + j0, ld,
+                                    Aug + (int64_t)r1 * ld + no, ld, jb, no,
+                                    no - r1);
     wave_tile_stage<NB2>(Aug, ld, j0, jb, W, TILE_LOWER);
     wave_tile_invert<NB2>(W, TILE_LOWER);
     wave_tile_apply<NB2, true>(Aug, ld, j0, jb, no, 2 * no, W, false);
