@@ -49,14 +49,14 @@ PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # A figure applies only while its kernel source is the one measured.
 PMC_TRAFFIC = {
     "match_kernel": {"src": "paper_1403_5524_amd/csrc/match.hip",
-                     "sha256_16": "9bfacccc636ba97c",
-                     "bytes_per_energy": 23.26e6 + 9.49e6},
+                     "sha256_16": "6a670543afa0e68d",
+                     "bytes_per_energy": 21.65e6 + 8.147e6},
     "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
-                     "sha256_16": "922a8f7e26f5c975",
-                     "bytes_per_energy": 0.191e6 + 0.320e6},
+                     "sha256_16": "63e41f950c81571c",
+                     "bytes_per_energy": 0.1926e6 + 0.3227e6},
     "polesum_bf16x3": {"src": "paper_1403_5524_amd/csrc/polesum_pd.hip",
-                       "sha256_16": "964e1c800446329d",
-                       "bytes_per_energy": 0.338e6 + 0.822e6},
+                       "sha256_16": "045eb073247d461b",
+                       "bytes_per_energy": 0.3176e6 + 0.6998e6},
 }
 
 
@@ -240,40 +240,51 @@ PHOTO_SHAPES = {
 
 
 def photo_leg(native, torch, oracle, workloads, steps, warmup, count,
-              shape="b2", n_check=4):
+              shape="b2", n_check=4, damped=False):
     """Photoionization on the B II (Table 1: 400 channels, 409,600 energies)
     or Ca II (Table 2: 1815 channels, 6,000 energies) shape of the paper:
     `count` energies spread evenly over the mesh, timed like the headline;
-    sigma checked against the oracle on `n_check` of them."""
+    sigma checked against the oracle on `n_check` of them.  damped: with
+    radiative widths (workloads.radiative_widths, seed 65) on the poles."""
     gen, paper_rate, paper_hw = PHOTO_SHAPES[shape]
     w, d, e0 = getattr(workloads, gen)()
     stride = max(1, w.mesh.size // count)
     Em = w.mesh[::stride][:count]
     h = native.load_symmetry(w.syms[0])
     native.rm_load_dipoles(h, d)
+    opts = None
+    if damped:
+        G = workloads.radiative_widths(w.syms[0].n_poles, 65)
+        native.rm_load_widths(h, G)
+        opts = native.make_opts(flags=native.RM_FLAG_RADIATION_DAMPING)
     E = torch.as_tensor(Em, dtype=torch.float64, device="cuda:0")
     sig = torch.empty_like(E)
     st = torch.empty(E.shape, dtype=torch.int32, device=E.device)
     for _ in range(warmup):
-        native.rm_photoionization([h], E, e0, sigma=sig, status=st)
+        native.rm_photoionization([h], E, e0, opts, sigma=sig, status=st)
     torch.cuda.synchronize()
     native.rm_profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        native.rm_photoionization([h], E, e0, sigma=sig, status=st)
+        native.rm_photoionization([h], E, e0, opts, sigma=sig, status=st)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     stage = {k: native.rm_profile_query(k)[0] / steps
              for k in ("polesum", "match")}
     native.rm_profile(False)
     idx = workloads.sample_indices(Em.size, n_check, seed=3)
-    ref = oracle.photoionization([w.syms[0].as_dict()], [d], Em[idx], e0)
+    if damped:
+        ref = oracle.photoionization_damped([w.syms[0].as_dict()], [d], [G],
+                                            Em[idx], e0)
+    else:
+        ref = oracle.photoionization([w.syms[0].as_dict()], [d], Em[idx], e0)
     got = sig.cpu().numpy()[idx]
     err = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
     h.free()
-    note("photoionization %s: %.1f ms for %d energies, err %.2e"
-         % (w.name, ms, Em.size, err))
-    return {"workload": w.name, "energies_timed": int(Em.size),
+    note("photoionization %s%s: %.1f ms for %d energies, err %.2e"
+         % (w.name, " damped" if damped else "", ms, Em.size, err))
+    return {"workload": w.name + ("+radiation damping" if damped else ""),
+            "energies_timed": int(Em.size),
             "sample": "every %d-th energy of the %d-point mesh"
                       % (stride, w.mesh.size),
             "value": Em.size / (ms * 1e-3), "unit": "energies/s",
@@ -593,27 +604,29 @@ def main():
             ref = r if ref is None else ref + r
     idx_dev = torch.as_tensor(idx, device=dev)
 
-    def run(name, graph):
+    def run(name, graph, steps=None, warmup=None):
         """Warm up, time `steps` sweeps at one precision, check Omega.
         `name` is a pole-sum precision, optionally with "/s32": the
         matching solve factored in FP32 and refined in FP64."""
+        steps = args.steps if steps is None else steps
+        warmup = args.warmup if warmup is None else warmup
         prec, _, solve = name.partition("/")
         opts = native.make_opts(prec=PREC_CODE[prec],
                                 solve_fp32=1 if solve == "s32" else 0)
-        for i in range(args.warmup):
+        for i in range(warmup):
             native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
             torch.cuda.synchronize()
             note("%s warmup %d done" % (name, i + 1))
         native.rm_profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             native.rm_sweep_energies(hs, n_t, E, opts, omega, status)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         native.rm_profile(False)
-        ms = (t1 - t0) * 1e3 / args.steps
-        note("%s: timed %d steps: %.2f ms/step" % (name, args.steps, ms))
+        ms = (t1 - t0) * 1e3 / steps
+        note("%s: timed %d steps: %.2f ms/step" % (name, steps, ms))
         stage = {k: native.rm_profile_query(k) for k in ("polesum", "match")}
         graph_ms = None
         if graph:
@@ -621,10 +634,10 @@ def main():
             plan.execute()
             torch.cuda.synchronize()
             g0 = time.perf_counter()
-            for i in range(args.steps):
+            for i in range(steps):
                 plan.execute()
             torch.cuda.synchronize()
-            graph_ms = (time.perf_counter() - g0) * 1e3 / args.steps
+            graph_ms = (time.perf_counter() - g0) * 1e3 / steps
             plan.free()
             note("%s: graph replays %.2f ms/step" % (name, graph_ms))
         got = omega[idx_dev].cpu().numpy()
@@ -639,8 +652,8 @@ def main():
                 ("match_kernel", mflops_step, PEAK["fp64"], "match",
                  "match_kernel")):
             ms_tot, launches = stage[stg]
-            lp = launches / args.steps if launches else 0
-            ach = (flops * args.steps / (ms_tot * 1e-3) / 1e12
+            lp = launches / steps if launches else 0
+            ach = (flops * steps / (ms_tot * 1e-3) / 1e12
                    if ms_tot > 0 else None)
             traffic = measured_traffic(tkey, M / lp) if (tkey and lp) else None
             kernels[key] = {
@@ -649,7 +662,7 @@ def main():
                 "traffic": traffic,
                 "flops_per_launch": flops / lp if lp else None,
                 "avg_launch_ms": ms_tot / launches if launches else None,
-                "ms_per_step": ms_tot / args.steps}
+                "ms_per_step": ms_tot / steps}
         mk = kernels["match_kernel"]
         if mk["achieved"]:
             # the LU the kernel runs does 2n^3/3 where the minimal count has
@@ -684,7 +697,8 @@ def main():
                             max(1, args.steps))
     others = {}
     for prec in [p for p in args.also.split(",") if p and p != args.prec]:
-        r = run(prec, False)
+        r = run(prec, False, steps=min(args.steps, 5),
+                warmup=min(args.warmup, 1))
         others[prec] = {
             "value": M / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
             "max_rel_err_omega": r["err"],
@@ -701,6 +715,11 @@ def main():
     if args.photo_M > 0:
         photo = photo_leg(native, torch, oracle, workloads, args.steps,
                           args.warmup, args.photo_M)
+    photo_damped = None
+    if args.photo_M > 0:
+        photo_damped = photo_leg(native, torch, oracle, workloads,
+                                 min(args.steps, 3), min(args.warmup, 1),
+                                 args.photo_M // 4, n_check=3, damped=True)
     photo_ca = None
     if args.photo_ca_M > 0:
         # one untimed-warmup-free step: the headline run has loaded the code
@@ -756,6 +775,7 @@ def main():
         "other_precisions": others,
         "postproc": post,
         "photoionization": photo,
+        "photoionization_damped": photo_damped,
         "photoionization_ca2": photo_ca,
         "outer_propagation": outer_res,
         "inner_region": inner_res,
