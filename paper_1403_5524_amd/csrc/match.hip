@@ -141,6 +141,9 @@ struct Frag {
 constexpr int G_TA = 1;     // A[i][k] stored at A[k * lda + i]
 constexpr int G_TB = 2;     // B[k][j] stored at B[j * ldb + k]
 constexpr int G_LOWER = 4;  // only the tiles of C that meet its lower triangle
+constexpr int G_BSYM = 8;   // B symmetric, only its lower triangle stored
+constexpr int G_KTRI = 16;  // A^T with A lower triangular (wave_gemm_wide,
+                            // with G_TA): a tile's sum starts at its first row
 
 template <int FL, class T>
 __device__ inline void frag_load(Frag<T> &f, const T *A, int lda,
@@ -272,7 +275,9 @@ __device__ void wave_gemm(T *C, int ldc, const T *A, int lda,
 // accumulators and subtracts A B through them (no separate C registers;
 // the next tile's C is prefetched), MODE 1 starts from the identity, MODE 2
 // from zero.  With G_LOWER only tiles whose first column is on or left of
-// their last row are formed.
+// their last row are formed.  G_BSYM reads B[k][j] from B's lower triangle;
+// G_KTRI skips the k-steps below the tile's first row (they multiply the
+// zeros above the diagonal of a lower-triangular A stored transposed).
 template <int MODE, int FL, int BM, int BN, class T = double>
 __device__ void wave_gemm_wide(T *C, int ldc, const T *A, int lda,
                                const T *B, int ldb, int rows, int cols,
@@ -292,6 +297,10 @@ __device__ void wave_gemm_wide(T *C, int ldc, const T *A, int lda,
     while (t < ntile && skip(t)) ++t;
     return t;
   };
+  // first k-step of tile t
+  auto kfirst = [&](int t) {
+    return (FL & G_KTRI) ? min((t / nct) * TH, kd) >> 4 : 0;
+  };
   // fragments of k-step k0 for the tile at (rb, cb)
   auto fload = [&](T (&a)[4][BM], T (&b)[4][BN], int rb, int cb, int k0) {
 #pragma unroll
@@ -308,8 +317,9 @@ __device__ void wave_gemm_wide(T *C, int ldc, const T *A, int lda,
 #pragma unroll
       for (int y = 0; y < BN; ++y) {
         const int j = cb + 16 * y + col;
+        const bool up = (FL & G_TB) || ((FL & G_BSYM) && k < j);
         b[s4][y] = (kv && j < cols)
-                       ? ((FL & G_TB) ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j])
+                       ? (up ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j])
                        : T(0);
       }
     }
@@ -329,7 +339,7 @@ __device__ void wave_gemm_wide(T *C, int ldc, const T *A, int lda,
   if (t < ntile) {
     T ca[4][BM], cbf[4][BN], na[4][BM], nb[4][BN];
     T cc[BM][BN][4];
-    fload(ca, cbf, (t / nct) * TH, (t % nct) * TW, 0);
+    fload(ca, cbf, (t / nct) * TH, (t % nct) * TW, 16 * kfirst(t));
     while (t < ntile) {
       const int tn = next(t);
       const int rb = (t / nct) * TH, cb = (t % nct) * TW;
@@ -347,11 +357,11 @@ __device__ void wave_gemm_wide(T *C, int ldc, const T *A, int lda,
               v = (rb + 16 * x + Mx<T>::row(kq, r) == cb + 16 * y + col) ? T(1) : T(0);
             acc[x][y][r] = v;
           }
-      for (int kc = 0; kc < nk; ++kc) {
+      for (int kc = kfirst(t); kc < nk; ++kc) {
         if (kc + 1 < nk) {
           fload(na, nb, rb, cb, (kc + 1) * 16);
         } else if (tn < ntile) {
-          fload(na, nb, (tn / nct) * TH, (tn % nct) * TW, 0);
+          fload(na, nb, (tn / nct) * TH, (tn % nct) * TW, 16 * kfirst(tn));
         }
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
@@ -993,11 +1003,20 @@ __device__ inline void wave_copy(double *dst, int dl, const double *src,
 }
 
 // ---------------------------------------------------------------------------
-// T step by Cholesky: 1 + K^2 is symmetric positive definite (eigenvalues
-// 1 + k^2 >= 1), so with 1 + K^2 = L L^T and Z = L^-1 K,
-//     Y = (1 + K^2)^-1 K = L^-T Z,   Q = K Y = K L^-T L^-1 K = Z^T Z
-// (K symmetric): no pivoting, only the lower triangle is factored, and
-// Q needs no product with K.
+// T step by Cholesky.  T = 2iK (1 - iK)^-1 = 2(1 - iK)^-1 - 2 and
+// (1 - iK)^-1 = (1 + iK)(1 + K^2)^-1, so with A = (1 + K^2)^-1 (K, A and
+// K A are symmetric and commute)
+//     Re T = -2 Q,  Q = K^2 A = 1 - A,     Im T = 2 Y,  Y = K A,
+// and |T_ij|^2 = 4 (Y_ij^2 + Q_ij^2).  1 + K^2 is symmetric positive
+// definite (eigenvalues 1 + k^2 >= 1): no pivoting, only its lower triangle
+// is formed and factored, 1 + K^2 = L L^T.  A = L^-T L^-1 from the lower
+// triangular L^-1 (forward substitution on the identity, each block only
+// on the columns left of its end) and a product that starts each tile's sum
+// at its first row; Y = K A with A read from its lower triangle.  That is
+// (1 + 1/3 + 1/3 + 1/3 + 1) no^3 flops with the product 1 + K^2; the route
+// Z = L^-1 K, Q = Z^T Z, Y = L^-T Z takes (1 + 1/3 + 1 + 1 + 1) no^3.
+// Off the diagonal Q = -A exactly; on it Q_ii = 1 - A_ii, whose absolute
+// error (unit roundoff) matters only where Q_ii itself is that small.
 
 // Factor the jb x jb (jb <= 32) diagonal block at (j0, j0) of A = L L^T in
 // registers: lane i holds row i in two 16-wide vectors; per column, one
@@ -1143,16 +1162,26 @@ __device__ void wave_photo_forward(const double *Aug, int ld, int j0, int jb,
   wave_sync();
 }
 
-// want_t: form Y and Q (collision strengths); pv: dipole amplitudes to be
-// replaced by L^-1 pv (photoionization), or null.
+// want_t: form Y and A (collision strengths); pv: dipole amplitudes to be
+// replaced by L^-1 pv (photoionization), or null.  On return with want_t,
+// the lower triangle of A is in columns [0, no) of Aug and the lower
+// triangle of Y in columns [no, 2 no); Kb (K) is free.
 __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
                           WaveLds &W, bool want_t, double *pv) {
   int flag = 0;
-  // lower triangle of 1 + K^2, and K as the right-hand side
+  // lower triangle of 1 + K^2, and the identity as the right-hand side
   wave_gemm_wide<1, G_LOWER, 2, 4>(Aug, ld, Kb, lk, Kb, lk, no, no, no);
-  if (want_t) wave_copy(Aug + no, ld, Kb, lk, no, no);
+  if (want_t) {
+    const int nsq = no * no;
+    const int lane = lane_id();
+    for (int q = lane; q < nsq; q += WT) {
+      const int i = q / no, j = q % no;
+      Aug[(int64_t)i * ld + no + j] = i == j ? 1.0 : 0.0;
+    }
+  }
   wave_sync();
-  // right-looking blocked Cholesky with the forward substitution Z = L^-1 K
+  // right-looking blocked Cholesky with the forward substitution L^-1 I:
+  // rows of block b have nonzeros only in columns left of the block's end
   for (int j0 = 0; j0 < no; j0 += NB2) {
     const int jb = min(NB2, no - j0);
     flag |= wave_chol_diag(Aug, ld, j0, jb, W);
@@ -1160,7 +1189,7 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
     const int r0 = j0 + jb;
     if (r0 < no) wave_rows_times_tit(Aug, ld, r0, no, j0, jb, W);
     if (pv) wave_photo_forward(Aug, ld, j0, jb, no, W, pv);
-    if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, 2 * no, W, false);
+    if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, no + r0, W, false);
     if (r0 < no) {
       wave_gemm_wide<0, G_TB | G_LOWER, 2, 4>(
           Aug + (int64_t)r0 * ld + r0, ld, Aug + (int64_t)r0 * ld + j0, ld,
@@ -1169,27 +1198,16 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
         wave_gemm_wide<0, 0, 2, 4>(Aug + (int64_t)r0 * ld + no, ld,
                                    Aug + (int64_t)r0 * ld + j0, ld,
                                    Aug + (int64_t)j0 * ld + no, ld, no - r0,
-                                   no, jb);
+                                   r0, jb);
     }
   }
   if (!want_t) return flag;
-  // Q = Z^T Z in K's place: symmetric, so only its lower triangle
-  wave_gemm_wide<2, G_TA | G_LOWER, 2, 4>(Kb, lk, Aug + no, ld, Aug + no, ld,
-                                          no, no, no);
-  // Y = L^-T Z, blocks from the bottom
-  for (int j0 = ((no - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
-    const int jb = min(NB2, no - j0);
-    const int r1 = j0 + jb;
-    // left-looking, as the LU's back substitution: Z_b -= L[>b, b]^T Y[>b]
-    if (r1 < no)
-      wave_gemm_wide<0, G_TA, 2, 4>(Aug + (int64_t)j0 * ld + no, ld,
-                                    Aug + (int64_t)r1 * ld + j0, ld,
-                                    Aug + (int64_t)r1 * ld + no, ld, jb, no,
-                                    no - r1);
-    wave_tile_stage<NB2>(Aug, ld, j0, jb, W, TILE_LOWER);
-    wave_tile_invert<NB2>(W, TILE_LOWER);
-    wave_tile_apply<NB2, true>(Aug, ld, j0, jb, no, 2 * no, W, false);
-  }
+  // A = (L^-1)^T L^-1, lower triangle, over L's place
+  wave_gemm_wide<2, G_TA | G_LOWER | G_KTRI, 2, 4>(Aug, ld, Aug + no, ld,
+                                                   Aug + no, ld, no, no, no);
+  // Y = K A, lower triangle, over L^-1's place
+  wave_gemm_wide<2, G_BSYM | G_LOWER, 2, 4>(Aug + no, ld, Kb, lk, Aug, ld, no,
+                                            no, no);
   return flag;
 }
 
@@ -1226,12 +1244,11 @@ __device__ inline void tri_decode(int64_t p, int m, int &i, int &j) {
   j = r + (int)(p - tri_row_start(r, m));
 }
 
-// Y (leading dimension ldy) and the lower triangle of Q (ldq) over the open
-// block in; V (ldv, disjoint from Y) is scratch, and so is Q once V is
-// formed.  Returns 1 if a
-// contribution was not finite.
+// The lower triangles of Y (leading dimension ldy) and A (lda) over the
+// open block in, Q = 1 - A; V (ldv, disjoint from both) is scratch, and so
+// is A once V is formed.  Returns 1 if a contribution was not finite.
 __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
-                          double *Q, int ldq, double *V, int ldv, int no,
+                          double *Am, int lda, double *V, int ldv, int no,
                           double *om) {
   const int lane = lane_id();
   const double g2 = 2.0 * S.g;
@@ -1255,8 +1272,10 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
         const bool in = p0 + (int64_t)u * WT < npair;
         ti[u] = in ? S.tgt[ii[u]] : 0;
         tj[u] = in ? S.tgt[jj[u]] : 0;
-        qv[u] = in ? Q[(int64_t)jj[u] * ldq + ii[u]] : 0.0;  // lower triangle
-        yv[u] = in ? Y[(int64_t)ii[u] * ldy + jj[u]] : 0.0;
+        // lower triangles: row jj >= column ii
+        qv[u] = in ? (ii[u] == jj[u] ? 1.0 : 0.0) - Am[(int64_t)jj[u] * lda + ii[u]]
+                   : 0.0;
+        yv[u] = in ? Y[(int64_t)jj[u] * ldy + ii[u]] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
@@ -1281,9 +1300,10 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int q = q0 + u * WT;
-      const int qi = q / no, qj = q % no;  // Q holds its lower triangle
-      qv[u] = q < nsq ? Q[(int64_t)max(qi, qj) * ldq + min(qi, qj)] : 0.0;
-      yv[u] = q < nsq ? Y[(int64_t)(q / no) * ldy + q % no] : 0.0;
+      const int qi = q / no, qj = q % no;
+      const int64_t lo = (int64_t)max(qi, qj), co = min(qi, qj);
+      qv[u] = q < nsq ? (qi == qj ? 1.0 : 0.0) - Am[lo * lda + co] : 0.0;
+      yv[u] = q < nsq ? Y[lo * ldy + co] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
@@ -1294,9 +1314,9 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
   }
   wave_sync();
   const int nt = S.ntu;
-  // W1 = G^T V (nt x no) into Q's place, then Omega_u = W1 G (nt x nt) into V
-  wave_gemm<2>(Q, ldq, S.GT, S.n, V, ldv, nt, no, no);
-  wave_gemm<2>(V, ldv, Q, ldq, S.G, nt, nt, nt, no);
+  // W1 = G^T V (nt x no) into A's place, then Omega_u = W1 G (nt x nt) into V
+  wave_gemm<2>(Am, lda, S.GT, S.n, V, ldv, nt, no, no);
+  wave_gemm<2>(V, ldv, Am, lda, S.G, nt, nt, nt, no);
   const int64_t npair = (int64_t)nt * (nt + 1) / 2;
   for (int64_t p0 = lane; p0 < npair; p0 += UNR * WT) {
     int ta[UNR], tb[UNR];
@@ -1676,13 +1696,13 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     }
   }
   if (L.do_t) {
-    // Y in Aug's columns [no, 2 no), Q in K's place
+    // A in Aug's columns [0, no), Y in [no, 2 no), V in K's place
     double *pv = (L.sigma && !k_given) ? Aug + (int64_t)3 * n * n + n : nullptr;
     wave_sync();
     if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv))
       bits |= RM_E_SINGULAR;
     if (L.omega)
-      nonfinite |= wave_omega(S, L.n_target_out, Aug + no, ld, Kb, n, Aug, ld,
+      nonfinite |= wave_omega(S, L.n_target_out, Aug + no, ld, Aug, ld, Kb, n,
                               no, L.omega + (int64_t)e * L.omega_stride);
     if (pv) {
       // sigma += (4 pi^2 alpha a0^2 / 3) omega (1/pi) |L^-1 v|^2
