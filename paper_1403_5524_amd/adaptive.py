@@ -80,12 +80,14 @@ class FineSweep:
     swept mesh."""
 
     def __init__(self, integrals, variation, total, mesh_size,
-                 curvature=None):
+                 curvature=None, nonfinite=None):
         self.integrals = integrals      # [P] float64 (numpy)
         self.variation = variation      # [nw] float64
         self.curvature = curvature      # [nw] float64: max |second difference|
         self.total = total
         self.mesh_size = mesh_size
+        # energies whose Omega row the sweep flagged RM_E_NONFINITE
+        self.nonfinite = nonfinite if nonfinite is not None else []
 
 
 def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
@@ -107,9 +109,13 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
     curv = np.zeros(nw if nw else 1)
     prev_E, prev_om = None, None
     h = (hi - lo) / nw if nw else None
+    nonfinite = []
     for c0 in range(0, M, chunk):
         Ec = E[c0:c0 + chunk]
-        om, _ = native.rm_sweep_energies(handles, n_target, Ec, opts)
+        om, st = native.rm_sweep_energies(handles, n_target, Ec, opts)
+        bad = ((st & native.RM_E_NONFINITE) != 0).nonzero().flatten()
+        if bad.numel():
+            nonfinite += [float(x) for x in Ec[bad[:8]].cpu().numpy()]
         if prev_E is not None:
             Ec2 = torch.cat([prev_E.view(1), Ec])
             om2 = torch.cat([prev_om.view(1, -1), om])
@@ -135,8 +141,8 @@ def sweep_integrals(handles, n_target, E, lo, hi, nw=None, chunk=25000,
     integ += prev_om * (hi - prev_E)
     torch.cuda.synchronize()
     return FineSweep(integ.cpu().numpy(), var.cpu().numpy() if nw else None,
-                 float(integ.sum().item()), M,
-                 curv if nw else None)
+                     float(integ.sum().item()), M,
+                     curv if nw else None, nonfinite)
 
 
 def labels_from_variation(variation, scale="mean"):
@@ -381,6 +387,8 @@ def run_experiment(train_seeds, test_seed, n=200, n_poles=8000, n_narrow=50,
         miss, tot = missed_resonances(E.cpu().numpy(), truth[ok], min_w)
         out[name] = {"int_err_max": mx, "int_err_mean": mean,
                      "missed": miss, "resonances": tot}
+        if r.nonfinite:
+            out[name]["nonfinite_energies"] = r.nonfinite[:8]
         log("%-16s int err max %.3e mean %.3e missed %d/%d"
             % (name, mx, mean, miss, tot))
     h.free()
