@@ -49,8 +49,8 @@ PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # A figure applies only while its kernel source is the one measured.
 PMC_TRAFFIC = {
     "match_kernel": {"src": "paper_1403_5524_amd/csrc/match.hip",
-                     "sha256_16": "6a670543afa0e68d",
-                     "bytes_per_energy": 21.65e6 + 8.147e6},
+                     "sha256_16": "29b40e275f09c282",
+                     "bytes_per_energy": 19.29e6 + 6.992e6},
     "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
                      "sha256_16": "63e41f950c81571c",
                      "bytes_per_energy": 0.1926e6 + 0.3227e6},
@@ -85,10 +85,11 @@ def match_flops(n, n_open):
 
 
 def match_flops_executed(n, n_open):
-    """The flops the kernel runs: the LU (2 n^3 / 3 instead of n^3/3), the
-    substitutions (2 n^2 m) and its T step (3 m^3: lower triangle of
-    1 + K^2 m^3, Cholesky m^3/3, L^-1 m^3/3, A = L^-T L^-1 m^3/3, lower
-    triangle of Y = K A m^3)."""
+    """The flops the kernel runs at most energies: the LU (2 n^3 / 3 instead
+    of n^3/3), the substitutions (2 n^2 m) and its T step (3 m^3: lower
+    triangle of 1 + K^2 m^3, Cholesky m^3/3, L^-1 m^3/3, A = L^-T L^-1
+    m^3/3, lower triangle of Y = K A m^3; energies with large K take a
+    route of 13 m^3 / 3)."""
     no = n_open.astype(np.float64)
     f = (2.0 / 3.0) * n ** 3 + 2.0 * n * n * no + 3.0 * no ** 3
     return float(np.where(no > 0, f, 0.0).sum())

@@ -1017,6 +1017,13 @@ __device__ inline void wave_copy(double *dst, int dl, const double *src,
 // Z = L^-1 K, Q = Z^T Z, Y = L^-T Z takes (1 + 1/3 + 1 + 1 + 1) no^3.
 // Off the diagonal Q = -A exactly; on it Q_ii = 1 - A_ii, whose absolute
 // error (unit roundoff) matters only where Q_ii itself is that small.
+// The product K A multiplies the rounding of A by |K|, so its error grows
+// as the square of K's largest row norm (about 3e-17 |K|_row^2 against the
+// exact T, where the route through Z grows more slowly): energies where
+// 1 + K^2 has a diagonal entry (1 + that row norm squared) above
+// kTInvMax take the route through Z, which keeps them as accurate as
+// before (about one energy in twenty at 200 channels).
+constexpr double kTInvMax = 1e6;
 
 // Factor the jb x jb (jb <= 32) diagonal block at (j0, j0) of A = L L^T in
 // registers: lane i holds row i in two 16-wide vectors; per column, one
@@ -1162,34 +1169,46 @@ __device__ void wave_photo_forward(const double *Aug, int ld, int j0, int jb,
   wave_sync();
 }
 
-// want_t: form Y and A (collision strengths); pv: dipole amplitudes to be
-// replaced by L^-1 pv (photoionization), or null.  On return with want_t,
-// the lower triangle of A is in columns [0, no) of Aug and the lower
-// triangle of Y in columns [no, 2 no); Kb (K) is free.
+// want_t: form Y and Q or A (collision strengths); pv: dipole amplitudes to
+// be replaced by L^-1 pv (photoionization), or null.  On return with want_t,
+// the lower triangle of Y is in columns [no, 2 no) of Aug and `inv` says
+// where Q is: true, A = 1 - Q (lower triangle) in columns [0, no) of Aug
+// and Kb is free; false, the lower triangle of Q in Kb and Aug's columns
+// [0, no) are free.
 __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
-                          WaveLds &W, bool want_t, double *pv) {
+                          WaveLds &W, bool want_t, double *pv, bool &inv) {
   int flag = 0;
-  // lower triangle of 1 + K^2, and the identity as the right-hand side
+  const int lane = lane_id();
+  // lower triangle of 1 + K^2
   wave_gemm_wide<1, G_LOWER, 2, 4>(Aug, ld, Kb, lk, Kb, lk, no, no, no);
-  if (want_t) {
+  // route: the largest diagonal entry 1 + sum_j K_ij^2 (wavefront-uniform)
+  double gmax = 0.0;
+  for (int i = lane; i < no; i += WT) gmax = fmax(gmax, Aug[(int64_t)i * ld + i]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
+  inv = gmax <= kTInvMax;
+  // right-hand side: the identity (route through A) or K (route through Z)
+  if (want_t && inv) {
     const int nsq = no * no;
-    const int lane = lane_id();
     for (int q = lane; q < nsq; q += WT) {
       const int i = q / no, j = q % no;
       Aug[(int64_t)i * ld + no + j] = i == j ? 1.0 : 0.0;
     }
+  } else if (want_t) {
+    wave_copy(Aug + no, ld, Kb, lk, no, no);
   }
   wave_sync();
-  // right-looking blocked Cholesky with the forward substitution L^-1 I:
-  // rows of block b have nonzeros only in columns left of the block's end
+  // right-looking blocked Cholesky with the forward substitution; with the
+  // identity, rows of block b have nonzeros only left of the block's end
   for (int j0 = 0; j0 < no; j0 += NB2) {
     const int jb = min(NB2, no - j0);
     flag |= wave_chol_diag(Aug, ld, j0, jb, W);
     wave_tile_invert<NB2>(W, TILE_LOWER);
     const int r0 = j0 + jb;
+    const int rc = inv ? r0 : no;  // right-hand-side columns in play
     if (r0 < no) wave_rows_times_tit(Aug, ld, r0, no, j0, jb, W);
     if (pv) wave_photo_forward(Aug, ld, j0, jb, no, W, pv);
-    if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, no + r0, W, false);
+    if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, no + rc, W, false);
     if (r0 < no) {
       wave_gemm_wide<0, G_TB | G_LOWER, 2, 4>(
           Aug + (int64_t)r0 * ld + r0, ld, Aug + (int64_t)r0 * ld + j0, ld,
@@ -1198,16 +1217,36 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
         wave_gemm_wide<0, 0, 2, 4>(Aug + (int64_t)r0 * ld + no, ld,
                                    Aug + (int64_t)r0 * ld + j0, ld,
                                    Aug + (int64_t)j0 * ld + no, ld, no - r0,
-                                   r0, jb);
+                                   rc, jb);
     }
   }
   if (!want_t) return flag;
-  // A = (L^-1)^T L^-1, lower triangle, over L's place
-  wave_gemm_wide<2, G_TA | G_LOWER | G_KTRI, 2, 4>(Aug, ld, Aug + no, ld,
-                                                   Aug + no, ld, no, no, no);
-  // Y = K A, lower triangle, over L^-1's place
-  wave_gemm_wide<2, G_BSYM | G_LOWER, 2, 4>(Aug + no, ld, Kb, lk, Aug, ld, no,
-                                            no, no);
+  if (inv) {
+    // A = (L^-1)^T L^-1, lower triangle, over L's place
+    wave_gemm_wide<2, G_TA | G_LOWER | G_KTRI, 2, 4>(Aug, ld, Aug + no, ld,
+                                                     Aug + no, ld, no, no, no);
+    // Y = K A, lower triangle, over L^-1's place
+    wave_gemm_wide<2, G_BSYM | G_LOWER, 2, 4>(Aug + no, ld, Kb, lk, Aug, ld,
+                                              no, no, no);
+    return flag;
+  }
+  // Q = Z^T Z (= K^2 A) in K's place, lower triangle
+  wave_gemm_wide<2, G_TA | G_LOWER, 2, 4>(Kb, lk, Aug + no, ld, Aug + no, ld,
+                                          no, no, no);
+  // Y = L^-T Z, blocks from the bottom
+  for (int j0 = ((no - 1) / NB2) * NB2; j0 >= 0; j0 -= NB2) {
+    const int jb = min(NB2, no - j0);
+    const int r1 = j0 + jb;
+    // left-looking, as the LU's back substitution: Z_b -= L[>b, b]^T Y[>b]
+    if (r1 < no)
+      wave_gemm_wide<0, G_TA, 2, 4>(Aug + (int64_t)j0 * ld + no, ld,
+                                    Aug + (int64_t)r1 * ld + j0, ld,
+                                    Aug + (int64_t)r1 * ld + no, ld, jb, no,
+                                    no - r1);
+    wave_tile_stage<NB2>(Aug, ld, j0, jb, W, TILE_LOWER);
+    wave_tile_invert<NB2>(W, TILE_LOWER);
+    wave_tile_apply<NB2, true>(Aug, ld, j0, jb, no, 2 * no, W, false);
+  }
   return flag;
 }
 
@@ -1244,12 +1283,13 @@ __device__ inline void tri_decode(int64_t p, int m, int &i, int &j) {
   j = r + (int)(p - tri_row_start(r, m));
 }
 
-// The lower triangles of Y (leading dimension ldy) and A (lda) over the
-// open block in, Q = 1 - A; V (ldv, disjoint from both) is scratch, and so
-// is A once V is formed.  Returns 1 if a contribution was not finite.
+// The lower triangles of Y (leading dimension ldy) and of Q, or of A with
+// Q = 1 - A (q_is_a), in Qm (ldq) over the open block in; V (ldv, disjoint
+// from both) is scratch, and so is Qm once V is formed.  Returns 1 if a
+// contribution was not finite.
 __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
-                          double *Am, int lda, double *V, int ldv, int no,
-                          double *om) {
+                          double *Qm, int ldq, bool q_is_a, double *V, int ldv,
+                          int no, double *om) {
   const int lane = lane_id();
   const double g2 = 2.0 * S.g;
   int nonfinite = 0;
@@ -1273,8 +1313,8 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
         ti[u] = in ? S.tgt[ii[u]] : 0;
         tj[u] = in ? S.tgt[jj[u]] : 0;
         // lower triangles: row jj >= column ii
-        qv[u] = in ? (ii[u] == jj[u] ? 1.0 : 0.0) - Am[(int64_t)jj[u] * lda + ii[u]]
-                   : 0.0;
+        const double qa = in ? Qm[(int64_t)jj[u] * ldq + ii[u]] : 0.0;
+        qv[u] = q_is_a ? (in && ii[u] == jj[u] ? 1.0 : 0.0) - qa : qa;
         yv[u] = in ? Y[(int64_t)jj[u] * ldy + ii[u]] : 0.0;
       }
 #pragma unroll
@@ -1302,7 +1342,8 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
       const int q = q0 + u * WT;
       const int qi = q / no, qj = q % no;
       const int64_t lo = (int64_t)max(qi, qj), co = min(qi, qj);
-      qv[u] = q < nsq ? (qi == qj ? 1.0 : 0.0) - Am[lo * lda + co] : 0.0;
+      const double qa = q < nsq ? Qm[lo * ldq + co] : 0.0;
+      qv[u] = q_is_a ? (q < nsq && qi == qj ? 1.0 : 0.0) - qa : qa;
       yv[u] = q < nsq ? Y[lo * ldy + co] : 0.0;
     }
 #pragma unroll
@@ -1314,9 +1355,9 @@ __device__ int wave_omega(const SymDev &S, int n_out, const double *Y, int ldy,
   }
   wave_sync();
   const int nt = S.ntu;
-  // W1 = G^T V (nt x no) into A's place, then Omega_u = W1 G (nt x nt) into V
-  wave_gemm<2>(Am, lda, S.GT, S.n, V, ldv, nt, no, no);
-  wave_gemm<2>(V, ldv, Am, lda, S.G, nt, nt, nt, no);
+  // W1 = G^T V (nt x no) into Qm's place, then Omega_u = W1 G (nt x nt) into V
+  wave_gemm<2>(Qm, ldq, S.GT, S.n, V, ldv, nt, no, no);
+  wave_gemm<2>(V, ldv, Qm, ldq, S.G, nt, nt, nt, no);
   const int64_t npair = (int64_t)nt * (nt + 1) / 2;
   for (int64_t p0 = lane; p0 < npair; p0 += UNR * WT) {
     int ta[UNR], tb[UNR];
@@ -1696,14 +1737,20 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     }
   }
   if (L.do_t) {
-    // A in Aug's columns [0, no), Y in [no, 2 no), V in K's place
+    // Y in Aug's columns [no, 2 no); A in [0, no) and V in K's place, or
+    // Q in K's place and V in [0, no)
     double *pv = (L.sigma && !k_given) ? Aug + (int64_t)3 * n * n + n : nullptr;
     wave_sync();
-    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv))
+    bool inv = false;
+    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv, inv))
       bits |= RM_E_SINGULAR;
     if (L.omega)
-      nonfinite |= wave_omega(S, L.n_target_out, Aug + no, ld, Aug, ld, Kb, n,
-                              no, L.omega + (int64_t)e * L.omega_stride);
+      nonfinite |= inv ? wave_omega(S, L.n_target_out, Aug + no, ld, Aug, ld,
+                                    true, Kb, n, no,
+                                    L.omega + (int64_t)e * L.omega_stride)
+                       : wave_omega(S, L.n_target_out, Aug + no, ld, Kb, n,
+                                    false, Aug, ld, no,
+                                    L.omega + (int64_t)e * L.omega_stride);
     if (pv) {
       // sigma += (4 pi^2 alpha a0^2 / 3) omega (1/pi) |L^-1 v|^2
       double s2 = 0.0;
