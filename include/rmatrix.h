@@ -471,10 +471,9 @@ int rm_group_collision_strengths(const double *omega, int64_t M,
  * number of block-pair rotations applied over all of them.  Memory: about
  * 16 (n_chan n_basis)^2 + 8 (n_chan^2 + n_basis) n_quad bytes of device
  * workspace (the matrices, then the quadrature tables), allocated and freed
- * by the call.  Verified against a direct solve up to D = n_chan n_basis =
- * 8192 (at 8192: R(E) between poles, which tests eigenvectors and surface
- * amplitudes); above 8192 only the eigenvalue sums (trace and Frobenius
- * norm of H) are checked, so the amplitudes there are unverified.
+ * by the call.  Checked at D = n_chan n_basis = 8192 and 16384 by R(E)
+ * between poles against a direct solve of (H - E) X = B^T, which tests the
+ * eigenvectors and surface amplitudes, besides the eigenvalue sums.
  * Errors: RM_ERR_ARG (n_chan < 1, n_basis < 1, n_chan n_basis > 16384, a not
  * finite and > 0, z < 0, n_quad > 16384, n_chan^2 n_quad over 1e9 table
  * entries, l outside [0, 12], model arrays not

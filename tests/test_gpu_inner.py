@@ -282,5 +282,36 @@ def test_dimension_8192_against_a_direct_solve(nat):
 
 
 def test_dimension_16384(nat):
-    """D = 16384, the entry point's limit: the invariants."""
-    _invariants(nat, _random_model(8, 91), 2048)
+    """D = 16384, the entry point's limit: the invariants, and R(E) between
+    the two lowest poles against (1/2a) B (H - E)^-1 B^T, as at 8192, which
+    checks the eigenvectors and surface amplitudes.  The direct solve runs
+    as an FP64 LU with partial pivoting from torch's linear algebra on the
+    device (a host solve of this size takes about a minute); its residual
+    is checked first."""
+    import torch
+    m = _random_model(8, 91)
+    N = 2048
+    Eg, wg, H, eta = _invariants(nat, m, N)
+    n, D, a = 8, H.shape[0], m["a"]
+    E = 0.5 * (Eg[0] + Eg[1])
+    B = np.zeros((n, D))
+    phia = np.sqrt(2.0) * np.sqrt(2.0 / a) * (-1.0) ** np.arange(N)
+    for i in range(n):
+        B[i, i * N:(i + 1) * N] = phia
+    dev = torch.device("cuda:0")
+    Ht = torch.as_tensor(H, device=dev)
+    Ht.diagonal().sub_(E)
+    Bt = torch.as_tensor(B.T.copy(), device=dev)
+    Xt = torch.linalg.solve(Ht, Bt)
+    res = float((Ht @ Xt - Bt).abs().max() / (Ht.abs().sum(dim=1).max() * Xt.abs().max()))
+    X = Xt.cpu().numpy()
+    del Ht, Bt, Xt
+    torch.cuda.empty_cache()
+    assert res < 1e-12
+    Rd = B @ X / (2.0 * a)
+    Rg = (wg / (Eg - E)) @ wg.T / (2.0 * a)
+    G = (X * X).sum(axis=0)
+    ratio = (np.abs(Rg - Rd) / (eta / (2.0 * a) * np.sqrt(np.outer(G, G)))).max()
+    log("D=16384: solve residual %.1e; R between the lowest poles %.2e of its "
+        "bound" % (res, ratio))
+    assert ratio < 1.0
