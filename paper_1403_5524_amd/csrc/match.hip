@@ -1017,13 +1017,24 @@ __device__ inline void wave_copy(double *dst, int dl, const double *src,
 // Z = L^-1 K, Q = Z^T Z, Y = L^-T Z takes (1 + 1/3 + 1 + 1 + 1) no^3.
 // Off the diagonal Q = -A exactly; on it Q_ii = 1 - A_ii, whose absolute
 // error (unit roundoff) matters only where Q_ii itself is that small.
-// The product K A multiplies the rounding of A by |K|, so its error grows
-// as the square of K's largest row norm (about 3e-17 |K|_row^2 against the
-// exact T, where the route through Z grows more slowly): energies where
-// 1 + K^2 has a diagonal entry (1 + that row norm squared) above
-// kTInvMax take the route through Z, which keeps them as accurate as
-// before (about one energy in twenty at 200 channels).
-constexpr double kTInvMax = 1e6;
+// Forming 1 + K^2 squares the condition number of 1 - iK, and the product
+// K A multiplies the rounding of A by |K|: this route's error grows as the
+// square of K's largest row norm (about 3e-17 |K|_row^2 against the exact
+// T, 1e-8 at 1e4, 3e-2 at 2.5e7, which a 1e5-point mesh reaches where an
+// eigenphase is within ~1e-8 of pi/2).  Energies where 1 + K^2 has a
+// diagonal entry (1 + that row norm squared) above kTInvMax instead solve
+// (1 - iK) W = 1 directly, as the real system
+//     [ 1  K ] [X]   [1]
+//     [-K  1 ] [Y] = [0],    W = X + iY,  X = A,  Y = K A,
+// by the wavefront LU with partial pivoting: its condition number is that
+// of 1 - iK, about |K|, so the error stays near u |K| (6e-10 at 7e7 in an
+// FP64 emulation).  That takes 6 n^2 more doubles of workspace, present for
+// n <= kTExtMaxN; larger symmetries take the route through Z = L^-1 K
+// (Q = Z^T Z, Y = L^-T Z), whose error grows more slowly than the A route's
+// but still with |K|^2.  At 200 channels about 0.5 % of a uniform mesh's
+// energies are above the threshold.
+constexpr double kTInvMax = 1e8;
+enum TRoute { T_ROUTE_A = 0, T_ROUTE_Z = 1 };
 
 // Factor the jb x jb (jb <= 32) diagonal block at (j0, j0) of A = L L^T in
 // registers: lane i holds row i in two 16-wide vectors; per column, one
@@ -1169,14 +1180,75 @@ __device__ void wave_photo_forward(const double *Aug, int ld, int j0, int jb,
   wave_sync();
 }
 
+// The T step's route for large K: (1 - iK) W = 1 as the real system
+// [1 K; -K 1] [X; Y] = [1; 0] in `ext` (2 no x 3 no, leading dimension
+// 3 no), solved by the wavefront LU; X into Aug's columns [0, no), Y into
+// [no, 2 no).  Kept out of line: it runs at few energies, and inlined it
+// would raise the register pressure of the whole matching kernel.
+__device__ __attribute__((noinline)) int wave_t_complex(
+    double *Aug, int ld, const double *Kb, int lk, int no, double *ext,
+    WaveLds &W) {
+  const int lane = lane_id();
+  // [1 K | 1; -K 1 | 0], leading dimension 3 no, solved in place
+  const int l3 = 3 * no, nq = 2 * no * l3;
+  for (int q0 = lane; q0 < nq; q0 += UNR * WT) {
+    double v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      const int i = q / l3, j = q % l3;
+      const int ib = i < no ? i : i - no, jb = j % no;
+      const int blk = (i < no ? 0 : 3) + j / no;  // 0 1 2 / 3 4 5
+      double x = 0.0;
+      if (q < nq) {
+        if (blk == 1 || blk == 3) x = Kb[(int64_t)ib * lk + jb];
+        if (blk == 3) x = -x;
+        if ((blk == 0 || blk == 2 || blk == 4) && ib == jb) x = 1.0;
+      }
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q < nq) ext[(int64_t)(q / l3) * l3 + q % l3] = v[u];
+    }
+  }
+  wave_sync();
+  const int flag = wave_lu_solve(ext, 2 * no, l3, no, W) ? 1 : 0;
+  // X (rows [0, no)) over 1 + K^2's place, Y (rows [no, 2 no)) beside it
+  const int nsq = no * no;
+  for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+    double x[UNR], y[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      const int i = q / no, j = q % no;
+      x[u] = q < nsq ? ext[(int64_t)i * l3 + 2 * no + j] : 0.0;
+      y[u] = q < nsq ? ext[(int64_t)(no + i) * l3 + 2 * no + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + u * WT;
+      if (q >= nsq) continue;
+      const int i = q / no, j = q % no;
+      Aug[(int64_t)i * ld + j] = x[u];
+      Aug[(int64_t)i * ld + no + j] = y[u];
+    }
+  }
+  wave_sync();
+  return flag;
+}
+
 // want_t: form Y and Q or A (collision strengths); pv: dipole amplitudes to
-// be replaced by L^-1 pv (photoionization), or null.  On return with want_t,
-// the lower triangle of Y is in columns [no, 2 no) of Aug and `inv` says
-// where Q is: true, A = 1 - Q (lower triangle) in columns [0, no) of Aug
-// and Kb is free; false, the lower triangle of Q in Kb and Aug's columns
-// [0, no) are free.
+// be replaced by L^-1 pv (photoionization), or null; ext: the workspace's
+// complex-system part, or null.  On return with want_t, the lower triangle
+// of Y is in columns [no, 2 no) of Aug and `route` says where Q is:
+// T_ROUTE_A, A = 1 - Q (lower triangle) in columns [0, no) of Aug and Kb is
+// free; T_ROUTE_Z, the lower triangle of Q in Kb and Aug's columns [0, no)
+// are free.
 __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
-                          WaveLds &W, bool want_t, double *pv, bool &inv) {
+                          WaveLds &W, bool want_t, double *pv, double *ext,
+                          int &route) {
   int flag = 0;
   const int lane = lane_id();
   // lower triangle of 1 + K^2
@@ -1186,41 +1258,47 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
   for (int i = lane; i < no; i += WT) gmax = fmax(gmax, Aug[(int64_t)i * ld + i]);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
-  inv = gmax <= kTInvMax;
+  const bool inv = gmax <= kTInvMax;
+  const bool cplx = want_t && !inv && ext != nullptr;
+  const bool rhs = want_t && !cplx;
+  route = (inv || cplx) ? T_ROUTE_A : T_ROUTE_Z;
   // right-hand side: the identity (route through A) or K (route through Z)
-  if (want_t && inv) {
+  if (rhs && inv) {
     const int nsq = no * no;
     for (int q = lane; q < nsq; q += WT) {
       const int i = q / no, j = q % no;
       Aug[(int64_t)i * ld + no + j] = i == j ? 1.0 : 0.0;
     }
-  } else if (want_t) {
+  } else if (rhs) {
     wave_copy(Aug + no, ld, Kb, lk, no, no);
   }
   wave_sync();
   // right-looking blocked Cholesky with the forward substitution; with the
   // identity, rows of block b have nonzeros only left of the block's end
-  for (int j0 = 0; j0 < no; j0 += NB2) {
-    const int jb = min(NB2, no - j0);
-    flag |= wave_chol_diag(Aug, ld, j0, jb, W);
-    wave_tile_invert<NB2>(W, TILE_LOWER);
-    const int r0 = j0 + jb;
-    const int rc = inv ? r0 : no;  // right-hand-side columns in play
-    if (r0 < no) wave_rows_times_tit(Aug, ld, r0, no, j0, jb, W);
-    if (pv) wave_photo_forward(Aug, ld, j0, jb, no, W, pv);
-    if (want_t) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, no + rc, W, false);
-    if (r0 < no) {
-      wave_gemm_wide<0, G_TB | G_LOWER, 2, 4>(
-          Aug + (int64_t)r0 * ld + r0, ld, Aug + (int64_t)r0 * ld + j0, ld,
-          Aug + (int64_t)r0 * ld + j0, ld, no - r0, no - r0, jb);
-      if (want_t)
-        wave_gemm_wide<0, 0, 2, 4>(Aug + (int64_t)r0 * ld + no, ld,
-                                   Aug + (int64_t)r0 * ld + j0, ld,
-                                   Aug + (int64_t)j0 * ld + no, ld, no - r0,
-                                   rc, jb);
+  if (pv || rhs) {
+    for (int j0 = 0; j0 < no; j0 += NB2) {
+      const int jb = min(NB2, no - j0);
+      flag |= wave_chol_diag(Aug, ld, j0, jb, W);
+      wave_tile_invert<NB2>(W, TILE_LOWER);
+      const int r0 = j0 + jb;
+      const int rc = inv ? r0 : no;  // right-hand-side columns in play
+      if (r0 < no) wave_rows_times_tit(Aug, ld, r0, no, j0, jb, W);
+      if (pv) wave_photo_forward(Aug, ld, j0, jb, no, W, pv);
+      if (rhs) wave_tile_apply<NB2>(Aug, ld, j0, jb, no, no + rc, W, false);
+      if (r0 < no) {
+        wave_gemm_wide<0, G_TB | G_LOWER, 2, 4>(
+            Aug + (int64_t)r0 * ld + r0, ld, Aug + (int64_t)r0 * ld + j0, ld,
+            Aug + (int64_t)r0 * ld + j0, ld, no - r0, no - r0, jb);
+        if (rhs)
+          wave_gemm_wide<0, 0, 2, 4>(Aug + (int64_t)r0 * ld + no, ld,
+                                     Aug + (int64_t)r0 * ld + j0, ld,
+                                     Aug + (int64_t)j0 * ld + no, ld, no - r0,
+                                     rc, jb);
+      }
     }
   }
   if (!want_t) return flag;
+  if (cplx) return flag | wave_t_complex(Aug, ld, Kb, lk, no, ext, W);
   if (inv) {
     // A = (L^-1)^T L^-1, lower triangle, over L's place
     wave_gemm_wide<2, G_TA | G_LOWER | G_KTRI, 2, 4>(Aug, ld, Aug + no, ld,
@@ -1741,11 +1819,15 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     // Q in K's place and V in [0, no)
     double *pv = (L.sigma && !k_given) ? Aug + (int64_t)3 * n * n + n : nullptr;
     wave_sync();
-    bool inv = false;
-    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv, inv))
+    int route = T_ROUTE_A;
+    double *ext = (L.ext && t_ext_doubles(n) && t_ext_doubles(n) <= L.ext_estride)
+                      ? L.ext + (int64_t)e * L.ext_estride
+                      : nullptr;
+    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv, ext, route))
       bits |= RM_E_SINGULAR;
     if (L.omega)
-      nonfinite |= inv ? wave_omega(S, L.n_target_out, Aug + no, ld, Aug, ld,
+      nonfinite |= route == T_ROUTE_A
+                       ? wave_omega(S, L.n_target_out, Aug + no, ld, Aug, ld,
                                     true, Kb, n, no,
                                     L.omega + (int64_t)e * L.omega_stride)
                        : wave_omega(S, L.n_target_out, Aug + no, ld, Kb, n,

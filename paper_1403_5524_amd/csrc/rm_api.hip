@@ -394,6 +394,8 @@ struct Plan {
   int n_chunks = 0;
   // workspace
   double *work = nullptr;
+  double *ext = nullptr;           // T step's complex systems (nullable)
+  int64_t ext_estride = 0;
   ChanSlot *chan = nullptr;
   int *counters = nullptr;         // one per chunk (match kernel)
   int match_grid = 0;
@@ -435,6 +437,7 @@ static void plan_free_device(Plan &p) {
     p.d_syms = nullptr;
     p.d_work_off = p.d_chan_off = nullptr;
     p.work = nullptr;
+    p.ext = nullptr;
     p.chan = nullptr;
     p.counters = nullptr;
     return;
@@ -450,7 +453,7 @@ static void plan_free_device(Plan &p) {
   p.d_syms = nullptr;
   p.d_work_off = p.d_chan_off = nullptr;
   p.d_rre_off = p.d_rim_off = nullptr;
-  void *ws[] = {p.work, p.chan, p.counters};
+  void *ws[] = {p.work, p.ext, p.chan, p.counters};
   for (void *q : ws) {
     if (!q) continue;
     if (p.owns_async)
@@ -822,9 +825,14 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   }
   p.work_estride = wacc;
   p.chan_estride = cacc;
+  // one complex-system part per energy, for the largest symmetry that has one
+  p.ext_estride = 0;
+  if (!p.damped)
+    for (const Sym *s : v) p.ext_estride = std::max(p.ext_estride, t_ext_doubles(s->n));
   p.h_work_off = woff;
   for (const Sym *q : v) p.propagate = p.propagate || q->n_sec > 0;
-  const double per_energy = 8.0 * wacc + 32.0 * cacc;  // workspace + slots
+  // workspace, complex-system part, slots
+  const double per_energy = 8.0 * (wacc + p.ext_estride) + 32.0 * cacc;
   int64_t C;
   if (arena) {
     // what the arena holds after the tables (bounded by the item tables of
@@ -851,8 +859,13 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
                   "of scratch, over the %zu-byte limit", per + tables, arena->cap);
     C = std::min<int64_t>(C, 4096);
   } else {
+    // up to 16384 energies per chunk (about 8 per resident wavefront of the
+    // matching at 200 channels): the few energies whose T step takes the
+    // complex route cost about three ordinary ones, and with only two
+    // energies per wavefront a chunk would end with whichever of them came
+    // last (24 % more matching time at 4096, 3 % at 16384)
     C = o.chunk > 0 ? o.chunk : (int64_t)(ws_budget / (per_energy + 64.0));
-    C = std::max<int64_t>(1, std::min<int64_t>(C, 4096));
+    C = std::max<int64_t>(1, std::min<int64_t>(C, 16384));
     if (o.chunk <= 0) C = std::max<int64_t>(std::min<int64_t>(64, M), C);
   }
   C = std::min<int64_t>(C, std::max<int64_t>(M, 1));
@@ -916,30 +929,33 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
                                          : RM_ERR_HIP,
                 "plan tables: %s", hipGetErrorString(e));
   const size_t wbytes = (size_t)(C * wacc) * sizeof(double);
+  const size_t xbytes = (size_t)(C * p.ext_estride) * sizeof(double);
   const size_t cbytes = (size_t)(C * cacc) * sizeof(ChanSlot);
   const size_t kbytes = (size_t)std::max(1, p.n_chunks) * sizeof(int);
   p.owns_async = async && !arena;
   p.alloc_stream = st;
   if (arena) {
-    e = arena->take(&p.work, wbytes) && arena->take(&p.chan, cbytes) &&
-                arena->take(&p.counters, kbytes)
+    e = arena->take(&p.work, wbytes) && (!xbytes || arena->take(&p.ext, xbytes)) &&
+                arena->take(&p.chan, cbytes) && arena->take(&p.counters, kbytes)
             ? hipSuccess
             : hipErrorOutOfMemory;
     if (e != hipSuccess)
       return fail(RM_ERR_ARG, "workspace of %zu bytes does not fit the "
-                  "%zu-byte scratch", wbytes + cbytes, arena->cap);
+                  "%zu-byte scratch", wbytes + xbytes + cbytes, arena->cap);
   } else if (async) {
     e = hipMallocAsync((void **)&p.work, wbytes, st);
+    if (e == hipSuccess && xbytes) e = hipMallocAsync((void **)&p.ext, xbytes, st);
     if (e == hipSuccess) e = hipMallocAsync((void **)&p.chan, cbytes, st);
     if (e == hipSuccess) e = hipMallocAsync((void **)&p.counters, kbytes, st);
   } else {
     e = hipMalloc((void **)&p.work, wbytes);
+    if (e == hipSuccess && xbytes) e = hipMalloc((void **)&p.ext, xbytes);
     if (e == hipSuccess) e = hipMalloc((void **)&p.chan, cbytes);
     if (e == hipSuccess) e = hipMalloc((void **)&p.counters, kbytes);
   }
   if (e != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
-                "workspace of %zu bytes: %s", wbytes + cbytes,
+                "workspace of %zu bytes: %s", wbytes + xbytes + cbytes,
                 hipGetErrorString(e));
   p.match_grid = match_grid_size();
   return RM_OK;
@@ -1014,6 +1030,8 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.work = p.work;
     L.work_estride = p.work_estride;
     L.work_off = p.d_work_off;
+    L.ext = p.ext;
+    L.ext_estride = p.ext_estride;
     L.chan = p.chan;
     L.chan_estride = p.chan_estride;
     L.chan_off = p.d_chan_off;
@@ -1629,10 +1647,12 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
   if (m == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
   const Sym &s = *sym;
-  const int64_t ws = work_doubles(s.n);
-  const int64_t C = std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)(8.0e9 / (8.0 * ws))));
-  DevBuf work, tabs, chan;
+  const int64_t ws = work_doubles(s.n), xs = t_ext_doubles(s.n);
+  const int64_t C = std::max<int64_t>(
+      1, std::min<int64_t>(m, (int64_t)(8.0e9 / (8.0 * (ws + xs)))));
+  DevBuf work, tabs, chan, ext;
   if ((rc = dev_alloc(work, (size_t)(C * ws) * sizeof(double), st))) return rc;
+  if (xs && (rc = dev_alloc(ext, (size_t)(C * xs) * sizeof(double), st))) return rc;
   if ((rc = dev_alloc(chan, (size_t)(C * s.n) * sizeof(ChanSlot), st))) return rc;
   if ((rc = dev_alloc(tabs, sizeof(SymDev) + sizeof(int64_t), st))) return rc;
   const SymDev sd = s.dev();
@@ -1651,6 +1671,8 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
     L.m = (int)mc;
     L.work = (double *)work.p;
     L.work_estride = ws;
+    L.ext = (double *)ext.p;
+    L.ext_estride = xs;
     L.work_off = (const int64_t *)((char *)tabs.p + sizeof(SymDev));
     L.chan = (ChanSlot *)chan.p;           // rank table of the K input
     L.chan_estride = s.n;

@@ -15,6 +15,14 @@ namespace rmx {
 constexpr int kChanPad = 32;
 constexpr int kPolePad = 64;
 constexpr double kPadPole = 1.0e30;  // padding poles sit far from any energy
+// Symmetries of up to kTExtMaxN channels get, per energy of a chunk, 6 n^2
+// doubles of a separate buffer for the T step's well-conditioned route: the
+// real 2n x 2n form of (1 - iK) W = 1 with its right-hand sides (apart
+// from the main workspace, whose per-energy stride it would triple).
+constexpr int kTExtMaxN = 600;
+__host__ __device__ inline int64_t t_ext_doubles(int n) {
+  return n <= kTExtMaxN ? (int64_t)6 * n * n : 0;
+}
 
 // Device-side view of one symmetry (plain data, copied into a descriptor
 // table that the grouped kernels index by symmetry number).
@@ -208,6 +216,11 @@ struct MatchLaunch {
   // 2n x 2n real form of the complex driven system (leading dimension
   // 2n + 2), then R_re, R_im (n x n each) and g_re, g_im (n each)
   int damped;
+  // the T step's complex-system buffer (nullable): energy e's part at
+  // ext + e * ext_estride, at least t_ext_doubles(n) for every symmetry
+  // that uses it
+  double *ext;
+  int64_t ext_estride;
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
 // R(a) -> R(A) for the symmetries with outer-region sectors (same launch

@@ -194,6 +194,66 @@ def test_sweep_c2_full_mesh_sampled(torch_dev, nat, c2):
     assert torch.isfinite(om).all()
 
 
+def _eigenphase_sum(sym, E):
+    """Sum of atan(k) over the eigenvalues k of the oracle's K at E, and the
+    number of open channels."""
+    K, P = oracle.sweep(sym, [E], keep=("K",))["K"][0]
+    if P.size == 0:
+        return 0.0, 0
+    return float(np.arctan(np.linalg.eigvalsh(0.5 * (K + K.T))).sum()), P.size
+
+
+def _k_poles(sym, mesh, width=1e-8):
+    """Brackets [a, b] of width `width` around the energies where an
+    eigenvalue of K passes through infinity (the eigenphase sum drops by
+    pi there at a fixed number of open channels), found on the mesh and
+    narrowed by bisection, all with the oracle."""
+    r = oracle.sweep(sym, mesh, keep=("K",))["K"]
+    S, no = [], []
+    for K, P in r:
+        no.append(P.size)
+        S.append(np.arctan(np.linalg.eigvalsh(0.5 * (K + K.T))).sum()
+                 if P.size else 0.0)
+    S, no = np.array(S), np.array(no)
+    out = []
+    for i in np.nonzero((np.diff(S) < -np.pi / 2) & (no[1:] == no[:-1]))[0]:
+        a, b, sa = mesh[i], mesh[i + 1], S[i]
+        while b - a > width:
+            m = 0.5 * (a + b)
+            sm, nm = _eigenphase_sum(sym, m)
+            if nm == no[i] and sm - sa < -np.pi / 2:
+                b = m
+            else:
+                a, sa = m, sm
+        out.append((a, b))
+    return out
+
+
+def test_sweep_near_k_poles_c1(torch_dev, nat, c1):
+    """Energies within 1e-8 Ry of where an eigenvalue of K passes through
+    infinity (an eigenphase through pi/2): there 1 + K^2 is ill-conditioned
+    enough (its largest row norm above 1e4) that the T step solves
+    (1 - iK) W = 1 as its real 2n x 2n form instead of going through
+    (1 + K^2)^-1; Omega must still meet the FP64 tolerance.  The energies
+    are found with the oracle alone (eigenphase sum on the mesh, then
+    bisection)."""
+    w, h = c1
+    sym = w.syms[0].as_dict()
+    brackets = _k_poles(sym, w.mesh)
+    assert len(brackets) >= 3
+    E = np.array([x for ab in brackets for x in ab])
+    ref = oracle.sweep(sym, E, keep=("K",))
+    rn = np.array([np.sqrt((K * K).sum(axis=1).max()) for K, _ in ref["K"]])
+    log("near K poles: %d energies, K row norms %.1e .. %.1e"
+        % (E.size, rn.min(), rn.max()))
+    assert (rn > 1e4).all()
+    om, st = nat.rm_sweep_energies([h], 8, _dev(torch_dev, E))
+    err, num, den = omega_normwise_err(om.cpu().numpy(), ref["omega"])
+    log("near K poles: omega normwise err %.3e" % err)
+    assert err < OMEGA_TOL_FP64
+    assert np.array_equal(st.cpu().numpy(), ref["status"])
+
+
 def test_collision_strengths_from_k(torch_dev, nat, c1):
     """rm_collision_strengths(rm_kmatrix(E)) equals the fused sweep."""
     torch, _ = torch_dev
