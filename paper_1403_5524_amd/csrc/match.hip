@@ -40,7 +40,7 @@ namespace rmx {
 constexpr int WT = 64;   // lanes per wavefront
 constexpr int NB = 16;   // panel (factorisation) width
 constexpr int NB2 = 32;  // update width: two panels per trailing update
-constexpr int WPB = 4;   // wavefronts per workgroup
+constexpr int WPB = kMatchWpb;   // wavefronts per workgroup
 constexpr int UNR = 4;   // independent elements per lane per batch
 
 typedef double d4 __attribute__((ext_vector_type(4)));

@@ -394,8 +394,9 @@ struct Plan {
   int n_chunks = 0;
   // workspace
   double *work = nullptr;
-  double *ext = nullptr;           // T step's complex systems (nullable)
-  int64_t ext_estride = 0;
+  double *ext = nullptr;           // T step's complex systems (nullable),
+  int64_t ext_estride = 0;         // one part per energy of a chunk
+  bool want_t = true;              // the sweep forms T (set before building)
   ChanSlot *chan = nullptr;
   int *counters = nullptr;         // one per chunk (match kernel)
   int match_grid = 0;
@@ -825,10 +826,12 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   }
   p.work_estride = wacc;
   p.chan_estride = cacc;
-  // one complex-system part per energy, for the largest symmetry that has one
+  // one complex-system part per energy, for the largest symmetry that has
+  // one (sweeps that form T only)
   p.ext_estride = 0;
-  if (!p.damped)
+  if (!p.damped && p.want_t)
     for (const Sym *s : v) p.ext_estride = std::max(p.ext_estride, t_ext_doubles(s->n));
+  p.match_grid = match_grid_size();
   p.h_work_off = woff;
   for (const Sym *q : v) p.propagate = p.propagate || q->n_sec > 0;
   // workspace, complex-system part, slots
@@ -865,7 +868,7 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
     // energies per wavefront a chunk would end with whichever of them came
     // last (24 % more matching time at 4096, 3 % at 16384)
     C = o.chunk > 0 ? o.chunk : (int64_t)(ws_budget / (per_energy + 64.0));
-    C = std::max<int64_t>(1, std::min<int64_t>(C, 16384));
+    C = std::max<int64_t>(1, std::min<int64_t>(C, p.want_t ? 16384 : 4096));
     if (o.chunk <= 0) C = std::max<int64_t>(std::min<int64_t>(64, M), C);
   }
   C = std::min<int64_t>(C, std::max<int64_t>(M, 1));
@@ -957,7 +960,6 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
     return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
                 "workspace of %zu bytes: %s", wbytes + xbytes + cbytes,
                 hipGetErrorString(e));
-  p.match_grid = match_grid_size();
   return RM_OK;
 }
 
@@ -1591,6 +1593,7 @@ int rm_photoionization(const rm_sym_t *syms, int32_t n_sym, const double *E,
   if (M == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
   Plan p;
+  p.want_t = false;
   rc = plan_build(p, syms, n_sym, n_tgt, E, M, o, st, true,
                   workspace_budget(16.0e9));
   if (!rc) {
@@ -1618,6 +1621,7 @@ int rm_kmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
   if (m == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
   Plan p;
+  p.want_t = false;
   rm_sym_t one[1] = {sym};
   rc = plan_build(p, one, 1, sym->n_target, E, m, o, st, true, 8.0e9);
   if (!rc) {
@@ -1701,6 +1705,7 @@ int rm_rmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
   if (m == 0) return RM_OK;
   hipStream_t st = (hipStream_t)stream;
   Plan p;
+  p.want_t = false;
   rm_sym_t one[1] = {sym};
   rc = plan_build(p, one, 1, sym->n_target, E, m, o, st, true, 8.0e9);
   if (!rc) {

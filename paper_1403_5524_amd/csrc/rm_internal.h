@@ -17,9 +17,12 @@ constexpr int kPolePad = 64;
 constexpr double kPadPole = 1.0e30;  // padding poles sit far from any energy
 // Symmetries of up to kTExtMaxN channels get, per energy of a chunk, 6 n^2
 // doubles of a separate buffer for the T step's well-conditioned route: the
-// real 2n x 2n form of (1 - iK) W = 1 with its right-hand sides (apart
-// from the main workspace, whose per-energy stride it would triple).
-constexpr int kTExtMaxN = 600;
+// real 2n x 2n form of (1 - iK) W = 1 with its right-hand sides (apart from
+// the main workspace, whose per-energy stride it would triple).  (One part
+// per wavefront would need less memory but timed 5 % slower at 200
+// channels.)
+constexpr int kTExtMaxN = 400;
+constexpr int kMatchWpb = 4;  // wavefronts per matching workgroup
 __host__ __device__ inline int64_t t_ext_doubles(int n) {
   return n <= kTExtMaxN ? (int64_t)6 * n * n : 0;
 }
