@@ -49,14 +49,14 @@ PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # A figure applies only while its kernel source is the one measured.
 PMC_TRAFFIC = {
     "match_kernel": {"src": "paper_1403_5524_amd/csrc/match.hip",
-                     "sha256_16": "29b40e275f09c282",
-                     "bytes_per_energy": 19.29e6 + 6.992e6},
+                     "sha256_16": "c2da52c91e767f1c",
+                     "bytes_per_energy": 23.22e6 + 7.622e6},
     "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
                      "sha256_16": "63e41f950c81571c",
-                     "bytes_per_energy": 0.1926e6 + 0.3227e6},
+                     "bytes_per_energy": 0.1942e6 + 0.3228e6},
     "polesum_bf16x3": {"src": "paper_1403_5524_amd/csrc/polesum_pd.hip",
                        "sha256_16": "045eb073247d461b",
-                       "bytes_per_energy": 0.3176e6 + 0.6998e6},
+                       "bytes_per_energy": 0.2359e6 + 0.7140e6},
 }
 
 
