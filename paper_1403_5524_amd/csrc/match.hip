@@ -1930,11 +1930,14 @@ __device__ int match_one_damped(const MatchLaunch &L, int s, int e,
 
 #ifndef RM_MATCH_DEVICE_ONLY
 // MODE 0: FP64 solve; 1: FP32 solve refined in FP64; 2: damped
-// photoionization.  Separate instantiations keep each kernel's registers
-// its own.  The FP64 kernel runs two wavefronts per SIMD (256 registers
-// each, some spilled): its serial phases (panels, diagonal blocks) wait on
-// memory round trips that the second wavefront covers, 4 % faster at 200
-// channels than one wavefront per SIMD with every register.
+// photoionization; 3: FP64 solve for symmetries of more than 600 channels.
+// Separate instantiations keep each kernel's registers its own.  MODE 0
+// runs two wavefronts per SIMD (256 registers each, some spilled): its
+// serial phases (panels, diagonal blocks) wait on memory round trips that
+// the second wavefront covers, 4 % faster at 200 channels than one
+// wavefront per SIMD with every register; at 1815 channels the spills of
+// the larger panels cost more than that (10 % slower), so MODE 3 is the
+// same code at one wavefront per SIMD.
 template <int MODE>
 __global__ __launch_bounds__(WT *WPB)
 __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 2 : 1, MODE == 0 ? 2 : 1)))
@@ -1971,6 +1974,8 @@ hipError_t launch_match(const MatchLaunch &L, hipStream_t st) {
     hipLaunchKernelGGL(match_kernel<2>, dim3(blocks), dim3(WT * WPB), 0, st, L);
   else if (L.solve_fp32)
     hipLaunchKernelGGL(match_kernel<1>, dim3(blocks), dim3(WT * WPB), 0, st, L);
+  else if (L.n_max > 600)
+    hipLaunchKernelGGL(match_kernel<3>, dim3(blocks), dim3(WT * WPB), 0, st, L);
   else
     hipLaunchKernelGGL(match_kernel<0>, dim3(blocks), dim3(WT * WPB), 0, st, L);
   return hipGetLastError();

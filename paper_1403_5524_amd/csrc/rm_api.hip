@@ -1052,6 +1052,8 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.solve_fp32 = p.o.solve_fp32;
     L.refine_iters = p.o.refine_iters;
     L.damped = p.damped ? 1 : 0;
+    L.n_max = 0;
+    for (const Sym *q : p.syms) L.n_max = std::max(L.n_max, q->n);
     if (p.propagate) {
       StageTimer tp(7, st);
       RM_HIP(launch_propagate(L, st));
@@ -1677,6 +1679,7 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
     L.work_estride = ws;
     L.ext = (double *)ext.p;
     L.ext_estride = xs;
+    L.n_max = s.n;
     L.work_off = (const int64_t *)((char *)tabs.p + sizeof(SymDev));
     L.chan = (ChanSlot *)chan.p;           // rank table of the K input
     L.chan_estride = s.n;

@@ -224,6 +224,7 @@ struct MatchLaunch {
   // that uses it
   double *ext;
   int64_t ext_estride;
+  int n_max;                  // the largest symmetry's channels (kernel choice)
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
 // R(a) -> R(A) for the symmetries with outer-region sectors (same launch
