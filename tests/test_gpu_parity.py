@@ -254,6 +254,56 @@ def test_sweep_near_k_poles_c1(torch_dev, nat, c1):
     assert np.array_equal(st.cpu().numpy(), ref["status"])
 
 
+def test_sweep_near_k_poles_c2_decoupled_channel(torch_dev, nat):
+    """The 200-channel, 8000-pole case with channel 0 decoupled (it couples
+    only to the even poles, every other channel only to the odd ones), so
+    that R and K are block diagonal and channel 0's K is the one-channel K
+    of its own poles: its poles in E are found by bisection on that scalar
+    with the oracle, and within 1e-8 Ry of them the full system's K has row
+    norms of 1e6-1e7.  The sweep there takes the T step's complex route at
+    this size; Omega must meet the FP64 tolerance."""
+    w = wl.config2()
+    sym = dict(w.syms[0].as_dict())
+    W = np.array(sym["w"], copy=True)
+    even = (np.arange(W.shape[1]) % 2) == 0
+    W[0, ~even] = 0.0
+    W[1:, even] = 0.0
+    sym["w"] = W
+    one = {"E_pole": sym["E_pole"][even], "w": W[0:1, even], "a": sym["a"],
+           "e_thr": sym["e_thr"][:1], "l": sym["l"][:1], "z": sym["z"],
+           "g": 1.0, "target": None}
+
+    def k0(E):
+        K, P = oracle.sweep(one, [E], keep=("K",))["K"][0]
+        return float(K[0, 0])
+
+    grid = np.linspace(3.0, 3.2, 801) + 1.234e-6
+    kv = np.array([k0(e) for e in grid])
+    E = []
+    for i in np.nonzero((kv[:-1] > 10.0) & (kv[1:] < -10.0))[0][:2]:
+        a, b = grid[i], grid[i + 1]
+        while b - a > 1e-8:
+            m = 0.5 * (a + b)
+            if k0(m) > 0.0:
+                a = m
+            else:
+                b = m
+        E += [a, b]
+    E = np.array(E)
+    assert E.size == 4
+    ref = oracle.sweep(sym, E, keep=("K",))
+    rn = np.array([np.sqrt((K * K).sum(axis=1).max()) for K, _ in ref["K"]])
+    log("c2 near K poles: E %s, K row norms %s" % (E, rn))
+    assert (rn > 1e4).all()
+    h = nat.load_symmetry(sym)
+    om, st = nat.rm_sweep_energies([h], 200, _dev(torch_dev, E))
+    err, num, den = omega_normwise_err(om.cpu().numpy(), ref["omega"])
+    log("c2 near K poles: omega normwise err %.3e" % err)
+    assert err < OMEGA_TOL_FP64
+    assert np.array_equal(st.cpu().numpy(), ref["status"])
+    h.free()
+
+
 def test_collision_strengths_from_k(torch_dev, nat, c1):
     """rm_collision_strengths(rm_kmatrix(E)) equals the fused sweep."""
     torch, _ = torch_dev
