@@ -1028,11 +1028,12 @@ __device__ inline void wave_copy(double *dst, int dl, const double *src,
 //     [-K  1 ] [Y] = [0],    W = X + iY,  X = A,  Y = K A,
 // by the wavefront LU with partial pivoting: its condition number is that
 // of 1 - iK, about |K|, so the error stays near u |K| (6e-10 at 7e7 in an
-// FP64 emulation).  That takes 6 n^2 more doubles of workspace, present for
-// n <= kTExtMaxN; larger symmetries take the route through Z = L^-1 K
+// FP64 emulation).  That takes a slot of 6 n^2 doubles from the launch's
+// pool; without one the energy takes the route through Z = L^-1 K
 // (Q = Z^T Z, Y = L^-T Z), whose error grows more slowly than the A route's
-// but still with |K|^2.  At 200 channels about 0.5 % of a uniform mesh's
-// energies are above the threshold.
+// but still with |K|^2; the latter also serves when every slot of the
+// complex route's buffer pool is taken.  At 200 channels about 0.5 % of a
+// uniform mesh's energies are above the threshold.
 constexpr double kTInvMax = 1e8;
 enum TRoute { T_ROUTE_A = 0, T_ROUTE_Z = 1 };
 
@@ -1247,8 +1248,8 @@ __device__ __attribute__((noinline)) int wave_t_complex(
 // free; T_ROUTE_Z, the lower triangle of Q in Kb and Aug's columns [0, no)
 // are free.
 __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
-                          WaveLds &W, bool want_t, double *pv, double *ext,
-                          int &route) {
+                          WaveLds &W, bool want_t, double *pv,
+                          const MatchLaunch &L, int e, int &route) {
   int flag = 0;
   const int lane = lane_id();
   // lower triangle of 1 + K^2
@@ -1259,7 +1260,23 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
   const bool inv = gmax <= kTInvMax;
-  const bool cplx = want_t && !inv && ext != nullptr;
+  // a slot of the complex route's pool, taken by lane 0 (the loop is
+  // bounded: with every slot taken the energy goes through Z instead)
+  int slot = -1;
+  if (want_t && !inv && L.ext && t_ext_doubles(no) <= L.ext_estride) {
+    if (lane == 0) {
+      for (int t = 0; t < L.ext_slots; ++t) {
+        const int q = (e + t) % L.ext_slots;
+        if (atomicCAS(&L.ext_flags[q], 0, 1) == 0) {
+          slot = q;
+          break;
+        }
+      }
+    }
+    slot = __builtin_amdgcn_readfirstlane(slot);
+  }
+  const bool cplx = slot >= 0;
+  double *ext = cplx ? L.ext + (int64_t)slot * L.ext_estride : nullptr;
   const bool rhs = want_t && !cplx;
   route = (inv || cplx) ? T_ROUTE_A : T_ROUTE_Z;
   // right-hand side: the identity (route through A) or K (route through Z)
@@ -1298,7 +1315,14 @@ __device__ int wave_tstep(double *Aug, int ld, double *Kb, int lk, int no,
     }
   }
   if (!want_t) return flag;
-  if (cplx) return flag | wave_t_complex(Aug, ld, Kb, lk, no, ext, W);
+  if (cplx) {
+    flag |= wave_t_complex(Aug, ld, Kb, lk, no, ext, W);
+    // every read of the slot is done (its values were stored into Aug)
+    // before the slot is given back
+    __threadfence();
+    if (lane == 0) atomicExch(&L.ext_flags[slot], 0);
+    return flag;
+  }
   if (inv) {
     // A = (L^-1)^T L^-1, lower triangle, over L's place
     wave_gemm_wide<2, G_TA | G_LOWER | G_KTRI, 2, 4>(Aug, ld, Aug + no, ld,
@@ -1820,10 +1844,7 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     double *pv = (L.sigma && !k_given) ? Aug + (int64_t)3 * n * n + n : nullptr;
     wave_sync();
     int route = T_ROUTE_A;
-    double *ext = (L.ext && t_ext_doubles(n) && t_ext_doubles(n) <= L.ext_estride)
-                      ? L.ext + (int64_t)e * L.ext_estride
-                      : nullptr;
-    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv, ext, route))
+    if (wave_tstep(Aug, ld, Kb, n, no, W, L.omega != nullptr, pv, L, e, route))
       bits |= RM_E_SINGULAR;
     if (L.omega)
       nonfinite |= route == T_ROUTE_A

@@ -394,8 +394,10 @@ struct Plan {
   int n_chunks = 0;
   // workspace
   double *work = nullptr;
-  double *ext = nullptr;           // T step's complex systems (nullable),
-  int64_t ext_estride = 0;         // one part per energy of a chunk
+  double *ext = nullptr;           // T step's complex-system pool (nullable)
+  int64_t ext_estride = 0;         // doubles per slot
+  int *ext_flags = nullptr;        // one per slot, 0 = free
+  int ext_slots = 0;
   bool want_t = true;              // the sweep forms T (set before building)
   ChanSlot *chan = nullptr;
   int *counters = nullptr;         // one per chunk (match kernel)
@@ -439,6 +441,7 @@ static void plan_free_device(Plan &p) {
     p.d_work_off = p.d_chan_off = nullptr;
     p.work = nullptr;
     p.ext = nullptr;
+    p.ext_flags = nullptr;
     p.chan = nullptr;
     p.counters = nullptr;
     return;
@@ -455,6 +458,7 @@ static void plan_free_device(Plan &p) {
   p.d_work_off = p.d_chan_off = nullptr;
   p.d_rre_off = p.d_rim_off = nullptr;
   p.ext = nullptr;  // part of p.work
+  p.ext_flags = nullptr;
   void *ws[] = {p.work, p.chan, p.counters};
   for (void *q : ws) {
     if (!q) continue;
@@ -827,23 +831,36 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
   }
   p.work_estride = wacc;
   p.chan_estride = cacc;
-  // one complex-system part per energy, for the largest symmetry that has
-  // one (sweeps that form T only)
+  // the complex-system pool: slots for the largest symmetry (sweeps that
+  // form T only), at most 16 GB of them
   p.ext_estride = 0;
-  if (!p.damped && p.want_t)
+  p.ext_slots = 0;
+  if (!p.damped && p.want_t) {
     for (const Sym *s : v) p.ext_estride = std::max(p.ext_estride, t_ext_doubles(s->n));
+    p.ext_slots = arena ? kTExtSlotsArena : kTExtSlots;
+    while (p.ext_slots > 1 && 8.0 * p.ext_slots * (double)p.ext_estride > 16.0e9)
+      p.ext_slots /= 2;
+    // in an arena at most a quarter of it (none at all for very large
+    // symmetries: those energies then take the route through Z)
+    if (arena)
+      while (p.ext_slots > 0 &&
+             (8.0 * p.ext_estride + 4.0) * p.ext_slots > 0.25 * (double)arena->cap)
+        p.ext_slots /= 2;
+  }
   p.match_grid = match_grid_size();
   p.h_work_off = woff;
   for (const Sym *q : v) p.propagate = p.propagate || q->n_sec > 0;
-  // workspace, complex-system part, slots
-  const double per_energy = 8.0 * (wacc + p.ext_estride) + 32.0 * cacc;
+  // workspace and channel slots
+  const double per_energy = 8.0 * wacc + 32.0 * cacc;
   int64_t C;
   if (arena) {
     // what the arena holds after the tables (bounded by the item tables of
     // the largest chunk: at most one item per tile and energy, 16 bytes,
     // plus a counter per chunk)
     const double tables = (double)sd.size() * (sizeof(SymDev) + 16) + 65536.0;
-    const double room = (double)arena->cap - tables;
+    // less the complex-system pool and its flags
+    const double room = (double)arena->cap - tables -
+                        (8.0 * p.ext_estride + 4.0) * p.ext_slots - 256.0;
     double tiles = 0.0;
     {
       std::vector<std::pair<int, int>> tl;
@@ -933,14 +950,16 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
                                          : RM_ERR_HIP,
                 "plan tables: %s", hipGetErrorString(e));
   const size_t wbytes = (size_t)(C * wacc) * sizeof(double);
-  const size_t xbytes = (size_t)(C * p.ext_estride) * sizeof(double);
+  // the pool and its flags after the workspace, in one allocation
+  const size_t xbytes = (size_t)(p.ext_slots * p.ext_estride) * sizeof(double) +
+                        (size_t)p.ext_slots * sizeof(int);
   const size_t cbytes = (size_t)(C * cacc) * sizeof(ChanSlot);
   const size_t kbytes = (size_t)std::max(1, p.n_chunks) * sizeof(int);
   p.owns_async = async && !arena;
   p.alloc_stream = st;
-  // the complex-system part is carved from the end of the workspace's own
-  // allocation: at 200 channels the matching timed 4 % faster so than with
-  // a second allocation of its own
+  // the complex-system pool is carved from the end of the workspace's own
+  // allocation (a part per energy there timed 4 % faster at 200 channels
+  // than in an allocation of its own)
   if (arena) {
     e = arena->take(&p.work, wbytes + xbytes) && arena->take(&p.chan, cbytes) &&
                 arena->take(&p.counters, kbytes)
@@ -958,7 +977,10 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
     if (e == hipSuccess) e = hipMalloc((void **)&p.chan, cbytes);
     if (e == hipSuccess) e = hipMalloc((void **)&p.counters, kbytes);
   }
-  if (e == hipSuccess && xbytes) p.ext = p.work + C * wacc;
+  if (e == hipSuccess && p.ext_slots) {
+    p.ext = p.work + C * wacc;
+    p.ext_flags = (int *)(p.ext + (int64_t)p.ext_slots * p.ext_estride);
+  }
   if (e != hipSuccess)
     return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
                 "workspace of %zu bytes: %s", wbytes + xbytes + cbytes,
@@ -973,6 +995,7 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
   if (p.status) RM_HIP(launch_fill_i32(p.status, p.M, 0, st));
   if (p.sigma) RM_HIP(launch_fill(p.sigma, p.M, 0.0, st));
   RM_HIP(launch_fill_i32(p.counters, std::max(1, p.n_chunks), 0, st));
+  if (p.ext_flags) RM_HIP(launch_fill_i32(p.ext_flags, p.ext_slots, 0, st));
   for (int c = 0; c < p.n_chunks; ++c) {
     const int64_t c0 = (int64_t)c * p.C;
     const int64_t m = std::min(p.C, p.M - c0);
@@ -1037,6 +1060,8 @@ static int plan_enqueue(Plan &p, hipStream_t st) {
     L.work_off = p.d_work_off;
     L.ext = p.ext;
     L.ext_estride = p.ext_estride;
+    L.ext_flags = p.ext_flags;
+    L.ext_slots = p.ext_slots;
     L.chan = p.chan;
     L.chan_estride = p.chan_estride;
     L.chan_off = p.d_chan_off;
@@ -1657,11 +1682,15 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
   hipStream_t st = (hipStream_t)stream;
   const Sym &s = *sym;
   const int64_t ws = work_doubles(s.n), xs = t_ext_doubles(s.n);
-  const int64_t C = std::max<int64_t>(
-      1, std::min<int64_t>(m, (int64_t)(8.0e9 / (8.0 * (ws + xs)))));
+  const int64_t C = std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)(8.0e9 / (8.0 * ws))));
+  int slots = kTExtSlots;
+  while (slots > 1 && 8.0 * slots * (double)xs > 16.0e9) slots /= 2;
   DevBuf work, tabs, chan, ext;
   if ((rc = dev_alloc(work, (size_t)(C * ws) * sizeof(double), st))) return rc;
-  if (xs && (rc = dev_alloc(ext, (size_t)(C * xs) * sizeof(double), st))) return rc;
+  if ((rc = dev_alloc(ext, (size_t)(slots * xs) * sizeof(double) + slots * sizeof(int), st)))
+    return rc;
+  int *ext_flags = (int *)((double *)ext.p + (int64_t)slots * xs);
+  RM_HIP(launch_fill_i32(ext_flags, slots, 0, st));
   if ((rc = dev_alloc(chan, (size_t)(C * s.n) * sizeof(ChanSlot), st))) return rc;
   if ((rc = dev_alloc(tabs, sizeof(SymDev) + sizeof(int64_t), st))) return rc;
   const SymDev sd = s.dev();
@@ -1682,6 +1711,8 @@ int rm_collision_strengths(rm_sym_t sym, const double *K, const int32_t *n_open,
     L.work_estride = ws;
     L.ext = (double *)ext.p;
     L.ext_estride = xs;
+    L.ext_flags = ext_flags;
+    L.ext_slots = slots;
     L.n_max = s.n;
     L.work_off = (const int64_t *)((char *)tabs.p + sizeof(SymDev));
     L.chan = (ChanSlot *)chan.p;           // rank table of the K input

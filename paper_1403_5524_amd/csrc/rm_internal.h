@@ -15,16 +15,17 @@ namespace rmx {
 constexpr int kChanPad = 32;
 constexpr int kPolePad = 64;
 constexpr double kPadPole = 1.0e30;  // padding poles sit far from any energy
-// Symmetries of up to kTExtMaxN channels get, per energy of a chunk, 6 n^2
-// doubles of a separate buffer for the T step's well-conditioned route: the
-// real 2n x 2n form of (1 - iK) W = 1 with its right-hand sides (apart from
-// the main workspace, whose per-energy stride it would triple).  (One part
-// per wavefront would need less memory but timed 5 % slower at 200
-// channels.)
-constexpr int kTExtMaxN = 400;
-constexpr int kMatchWpb = 4;  // wavefronts per matching workgroup
+// The T step's well-conditioned route (the real 2n x 2n form of
+// (1 - iK) W = 1 with its right-hand sides, 6 n^2 doubles) runs at few
+// energies, so its buffers form a small pool of slots that a wavefront
+// takes by compare-and-swap on a flag and gives back when done; with every
+// slot taken the energy takes the route through Z = L^-1 K instead (no
+// wavefront ever waits).
+constexpr int kMatchWpb = 4;     // wavefronts per matching workgroup
+constexpr int kTExtSlots = 64;   // pool slots of an allocating sweep
+constexpr int kTExtSlotsArena = 16;  // of a sweep that may not allocate
 __host__ __device__ inline int64_t t_ext_doubles(int n) {
-  return n <= kTExtMaxN ? (int64_t)6 * n * n : 0;
+  return (int64_t)6 * n * n;
 }
 
 // Device-side view of one symmetry (plain data, copied into a descriptor
@@ -219,11 +220,14 @@ struct MatchLaunch {
   // 2n x 2n real form of the complex driven system (leading dimension
   // 2n + 2), then R_re, R_im (n x n each) and g_re, g_im (n each)
   int damped;
-  // the T step's complex-system buffer (nullable): energy e's part at
-  // ext + e * ext_estride, at least t_ext_doubles(n) for every symmetry
-  // that uses it
+  // the T step's complex-system pool (nullable): ext_slots slots of
+  // ext_estride doubles (at least t_ext_doubles(n) of every symmetry) at
+  // ext + slot * ext_estride, slot q free while ext_flags[q] == 0 (the
+  // flags start at zero)
   double *ext;
   int64_t ext_estride;
+  int *ext_flags;
+  int ext_slots;
   int n_max;                  // the largest symmetry's channels (kernel choice)
 };
 hipError_t launch_match(const MatchLaunch &L, hipStream_t st);
