@@ -30,6 +30,8 @@ Collisions", 2011, Ch. 2-3, for the steps the paper leaves implicit):
 * ``photo.photoionization_damped`` the same with radiatively damped poles
 * ``outer.sweep_propagated``      Omega with the R-matrix propagated beyond
                                    r = a through long-range multipole coupling
+* ``outer.gailitis``              coupled asymptotic solutions beyond the
+                                   propagation radius (the multipole tail)
 * ``resonance.measure_resonance`` position and width of a resonance from the
                                    slope of the eigenphase sum
 * ``inner.inner_region``          poles and surface amplitudes from the full

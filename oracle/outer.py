@@ -22,9 +22,16 @@ outwards before matching.  Read here as:
   are cos and sin);
 * at A, R(A) = Rr(A)/A is matched to the Coulomb (open) and Whittaker
   (closed) functions at r = A by the same matching as at r = a; the
-  multipole terms beyond A are dropped.
+  multipole terms beyond A are dropped;
+* or, with the asymptotic expansion switched on, the open-channel
+  solutions at A are the coupled asymptotic series of Gailitis (J. Phys. B
+  9 (1976) 843; Burke, "R-Matrix Theory of Atomic Collisions", 2011,
+  Ch. 2), which keeps the multipole terms beyond A (see ``gailitis``); the
+  closed channels keep their decaying Whittaker functions.  The paper is
+  silent on all of this.
 """
 import numpy as np
+from scipy.special import loggamma
 
 from .rmatrix import (r_matrix, channel_data, k_matrix, t_matrix,
                       collision_strengths)
@@ -115,7 +122,10 @@ def k_matrix_propagated(sym, prop, E):
 
 
 def sweep_propagated(sym, prop, E, n_target=None):
-    """Omega [m, P] over a mesh with the outer propagation."""
+    """Omega [m, P] over a mesh with the outer propagation (with the
+    asymptotic expansion when prop has "gailitis_terms" > 0)."""
+    if prop.get("gailitis_terms", 0) > 0:
+        return sweep_propagated_gailitis(sym, prop, E, n_target)[0]
     E = np.atleast_1d(np.asarray(E, dtype=np.float64))
     n = sym["w"].shape[0]
     target = sym.get("target")
@@ -139,3 +149,177 @@ def sweep_propagated(sym, prop, E, n_target=None):
         out[m] = collision_strengths(t_matrix(K), Pk, target, n_target,
                                      sym.get("g", 1.0))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Asymptotic expansion beyond A.
+#
+# For r >= A the equations u'' = (W(r) - E) u keep their multipole terms.
+# A solution that behaves as exp(i theta_j) in open channel j is written
+#     u_i(r) = g_ij(r) exp(i theta_j(r)),  g_ij(r) = sum_p c^p_ij r^-p,
+#     theta_j = k_j r - eta_j ln(2 k_j r) - l_j pi/2 + sigma_j,
+# with k_j^2 = E - e_j, eta_j = -z/k_j and sigma_j = arg Gamma(l_j + 1 +
+# i eta_j).  Putting this into the equations and collecting the powers of
+# 1/r gives, with br_i(p) = (p + i eta_j - l_i - 1)(p + i eta_j + l_i) and
+# V^p_i = sum_lam sum_m beta^lam_im c^(p - lam)_m,
+#     (k_i^2 - k_j^2) c^(p+1)_i = 2 i k_j p c^p_i - br_i(p) c^(p-1)_i + V^p_i
+# for every p >= 0.  Where k_i = k_j (e_i = e_j, channel j itself among
+# them) the left side vanishes and the same relation, taken at p + 1 and
+# solved for c^p_i, gives c^p_i = (br_i(p) c^(p-1)_i - V^p_i)/(2 i k_j p).
+# c^0_ij = delta_ij, c^p = 0 for p < 0.  Without coupling the series is the
+# asymptotic series of the Coulomb function H+ = G + iF (DLMF 33.11.1).
+# The series is asymptotic: it is summed up to its smallest term.
+# ---------------------------------------------------------------------------
+
+GAILITIS_CONV = 1e-16   # a term this small (relative to g ~ 1) ends the sum
+GAILITIS_FLAG = 1e-6    # a first omitted term above this flags the channel
+
+
+def coulomb_phase(l, eta):
+    """sigma_l(eta) = arg Gamma(l + 1 + i eta), the Coulomb phase shift."""
+    return np.asarray(loggamma(np.asarray(l, dtype=np.float64) + 1.0
+                               + 1j * np.asarray(eta, dtype=np.float64)).imag)
+
+
+def gailitis_column(j, E, e_thr, l, z, beta, r, max_terms):
+    """(g [n], g' [n], nonconv) of the solution that starts as exp(i theta_j)
+    in open channel j, summed at radius r.  A term is added while its size
+    T_p = max_i |c^p_i| r^-p does not exceed the last one's (T_0 = 1): the
+    first term that grows ends the sum unadded (the smallest-term
+    truncation of an asymptotic series); a term below GAILITIS_CONV ends it
+    after being added.  nonconv: the first omitted term (or, at max_terms,
+    the last added one) exceeds GAILITIS_FLAG."""
+    e_thr = np.asarray(e_thr, dtype=np.float64)
+    l = np.asarray(l, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    n = e_thr.size
+    k2 = E - e_thr
+    kj = np.sqrt(k2[j])
+    eta = -float(z) / kj
+    deg = e_thr == e_thr[j]
+
+    def br(p):
+        return (p + 1j * eta - l - 1.0) * (p + 1j * eta + l)
+
+    c = {0: np.zeros(n, dtype=complex)}
+    c[0][j] = 1.0
+
+    def cget(p):
+        return c[p] if p >= 0 else np.zeros(n, dtype=complex)
+
+    def V(p):
+        v = np.zeros(n, dtype=complex)
+        for lam in range(1, beta.shape[0] + 1):
+            v = v + beta[lam - 1] @ cget(p - lam)
+        return v
+
+    g = c[0].copy()
+    gp = np.zeros(n, dtype=complex)
+    t_prev = 1.0
+    nonconv = False
+    for p in range(1, max_terms + 1):
+        cp = np.empty(n, dtype=complex)
+        Vp = V(p)
+        cp[deg] = (br(p)[deg] * cget(p - 1)[deg] - Vp[deg]) / (2j * kj * p)
+        Vq = V(p - 1)
+        nd = ~deg
+        cp[nd] = ((2j * kj * (p - 1)) * cget(p - 1)[nd]
+                  - br(p - 1)[nd] * cget(p - 2)[nd] + Vq[nd]) / (k2[nd] - k2[j])
+        c[p] = cp
+        t = float(np.max(np.abs(cp))) * r ** (-p)
+        if t > t_prev:
+            nonconv = t > GAILITIS_FLAG
+            return g, gp, nonconv
+        g = g + cp * r ** (-p)
+        gp = gp - p * cp * r ** (-p - 1)
+        if t <= GAILITIS_CONV:
+            return g, gp, False
+        t_prev = t
+    nonconv = t_prev > GAILITIS_FLAG
+    return g, gp, nonconv
+
+
+def gailitis(E, e_thr, l, z, beta, r, max_terms=40):
+    """Asymptotic solutions at radius r, one per open channel j (ascending
+    channel index), normalised like s = k^-1/2 F and c = k^-1/2 G:
+        S_ij = k_j^-1/2 Im(g_ij e^{i theta_j}),  C_ij = k_j^-1/2 Re(...),
+    and their r-derivatives Sp, Cp (u' = (g' + i theta_j' g) e^{i theta_j},
+    theta_j' = k_j - eta_j / r).  Returns (S, C, Sp, Cp [n, n_o], P,
+    nonconv [n_o])."""
+    e_thr = np.asarray(e_thr, dtype=np.float64)
+    l = np.asarray(l, dtype=np.float64)
+    P = np.nonzero(E > e_thr)[0]
+    n = e_thr.size
+    S = np.zeros((n, P.size))
+    C = np.zeros((n, P.size))
+    Sp = np.zeros((n, P.size))
+    Cp = np.zeros((n, P.size))
+    flags = np.zeros(P.size, dtype=bool)
+    for col, j in enumerate(P):
+        kj = np.sqrt(E - e_thr[j])
+        eta = -float(z) / kj
+        theta = (kj * r - eta * np.log(2.0 * kj * r) - l[j] * np.pi / 2.0
+                 + coulomb_phase(l[j], eta))
+        g, gp, flags[col] = gailitis_column(j, E, e_thr, l, z, beta, r,
+                                            max_terms)
+        ph = np.exp(1j * theta) / np.sqrt(kj)
+        u = g * ph
+        up = (gp + 1j * (kj - eta / r) * g) * ph
+        S[:, col], C[:, col] = u.imag, u.real
+        Sp[:, col], Cp[:, col] = up.imag, up.real
+    return S, C, Sp, Cp, P, flags
+
+
+def k_matrix_asymptotic(R, r, S, C, Sp, Cp, P, L):
+    """Open-open K-matrix from u(r) = R r u'(r) with coupled open-channel
+    solutions: every open column j is S_j + sum_i C_i K_ij plus the closed
+    channels' decaying functions (e, r e') = (1, L)/sqrt(1 + L^2) with
+    coefficients X, so
+        [C - R r Cp | diag(e_Q) - R diag(r e'_Q)] [K; X] = R r Sp - S
+    with the columns of C in the places of the open channels.  L [n] holds
+    the closed channels' r W'/W (ignored elsewhere).  Returns K [n_o, n_o]."""
+    n = R.shape[0]
+    if P.size == 0:
+        return np.zeros((0, 0))
+    A = np.zeros((n, n))
+    closed = np.setdiff1d(np.arange(n), P)
+    A[:, P] = C - r * (R @ Cp)
+    if closed.size:
+        L = np.asarray(L, dtype=np.float64)
+        nrm = np.hypot(1.0, L[closed])
+        A[closed, closed] += 1.0 / nrm
+        A[:, closed] -= R[:, closed] * (L[closed] / nrm)[None, :]
+    B = r * (R @ Sp) - S
+    Z = np.linalg.solve(A, B)
+    return Z[P, :]
+
+
+def sweep_propagated_gailitis(sym, prop, E, n_target=None):
+    """(Omega [m, P], nonconv [m] bool) over a mesh: propagation to A, then
+    matching to the asymptotic expansion with prop["gailitis_terms"] terms
+    at most."""
+    E = np.atleast_1d(np.asarray(E, dtype=np.float64))
+    n = sym["w"].shape[0]
+    target = sym.get("target")
+    target = np.arange(n) if target is None else np.asarray(target)
+    if n_target is None:
+        n_target = int(target.max()) + 1
+    Pn = n_target * (n_target + 1) // 2
+    secs = outer_sectors(sym, prop)
+    A = prop["A"]
+    beta = np.asarray(prop["beta"], dtype=np.float64)
+    cd = channel_data(E, sym["e_thr"], sym["l"], sym["z"], A)
+    out = np.zeros((E.size, Pn))
+    flags = np.zeros(E.size, dtype=bool)
+    for m, Ee in enumerate(E):
+        Ra = r_matrix(sym["E_pole"], sym["w"], sym["a"], Ee)[0]
+        RA = propagate(sym["a"] * Ra, secs, Ee) / A
+        S, C, Sp, Cp, P, nc = gailitis(Ee, sym["e_thr"], sym["l"], sym["z"],
+                                       beta, A, prop["gailitis_terms"])
+        if P.size == 0:
+            continue
+        flags[m] = bool(nc.any())
+        K = k_matrix_asymptotic(RA, A, S, C, Sp, Cp, P, cd["L"][m])
+        out[m] = collision_strengths(t_matrix(0.5 * (K + K.T)), P, target,
+                                     n_target, sym.get("g", 1.0))
+    return out, flags

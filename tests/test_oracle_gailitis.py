@@ -1,0 +1,148 @@
+"""Pins of the oracle's asymptotic expansion beyond A (``oracle.outer.
+gailitis``): without coupling it is the Coulomb function of the oracle's
+continued fractions; with coupling its solutions satisfy the coupled
+equations (checked by integrating them numerically between two radii) and
+have the canonical Wronskian; matched after the propagation, it carries the
+multipole tail that matching to Coulomb functions at A drops."""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import outer, coulomb
+from oracle.rmatrix import r_matrix, channel_data, k_matrix
+from paper_1403_5524_amd import workloads as wl
+
+
+def _beta(n, seed, scales):
+    rng = np.random.default_rng(seed)
+    out = []
+    for sc in scales:
+        M = rng.normal(0.0, sc, (n, n))
+        out.append(0.5 * (M + M.T))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("l,z,k,r", [(0, 1.0, 1.0, 200.0), (3, 2.0, 0.7, 300.0),
+                                     (1, 0.0, 2.0, 150.0), (5, -1.0, 1.5, 400.0),
+                                     (2, 3.0, 0.5, 500.0)])
+def test_uncoupled_expansion_is_the_coulomb_function(l, z, k, r):
+    S, C, Sp, Cp, P, nc = outer.gailitis(k * k, [0.0], [l], z,
+                                         np.zeros((0, 1, 1)), r, 60)
+    s, c, sp, cp = coulomb.open_channel_functions(l, z, np.array([k]), r)
+    scale = 1.0 / np.sqrt(k)
+    for x, y in ((S, s), (C, c), (Sp, sp), (Cp, cp)):
+        assert abs(x[0, 0] - y[0]) < 1e-12 * max(scale, 1.0)
+    assert not nc[0]
+
+
+def _integrate(e, l, z, beta, E, r1, r2, beta_ode=None):
+    """Solutions of the expansion at r1, carried to r2 by a DOP853 integration
+    of u'' = (W - E) u, against the expansion at r2."""
+    n = e.size
+    S1, C1, Sp1, Cp1, P, _ = outer.gailitis(E, e, l, z, beta, r1, 60)
+    S2, C2, _, _, _, nc2 = outer.gailitis(E, e, l, z, beta, r2, 60)
+    bo = beta if beta_ode is None else beta_ode
+    m = 2 * P.size
+
+    def rhs(r, y):
+        U = y[:n * m].reshape(n, m)
+        Up = y[n * m:].reshape(n, m)
+        W = outer.potential_matrix(r, e, l, z, bo)
+        return np.concatenate([Up.ravel(), ((W - E * np.eye(n)) @ U).ravel()])
+
+    y0 = np.concatenate([np.hstack([S1, C1]).ravel(), np.hstack([Sp1, Cp1]).ravel()])
+    sol = solve_ivp(rhs, (r1, r2), y0, method="DOP853", rtol=1e-13, atol=1e-16)
+    U = sol.y[:n * m, -1].reshape(n, m)
+    return np.abs(U - np.hstack([S2, C2])).max(), nc2
+
+
+# two pairs of degenerate channels (one target level each) with dipole and
+# quadrupole coupling inside and between them
+_E5 = np.array([0.0, 0.0, 0.3, 0.3, 0.7])
+_L5 = np.array([0, 2, 1, 3, 1])
+_B5 = _beta(5, 3, (1.0, 1.0))
+
+
+def test_expansion_solves_the_coupled_equations_open_channels():
+    err, nc = _integrate(_E5, _L5, 1.0, _B5, 1.1, 150.0, 170.0)
+    assert err < 1e-10 and not nc.any()
+
+
+def test_expansion_solves_the_coupled_equations_with_a_closed_channel():
+    """A closed channel's algebraic tail (its growing solution limits the
+    integration to a short stretch)."""
+    e = _E5.copy()
+    e[4] = 2.5
+    err, nc = _integrate(e, _L5, 1.0, _B5, 1.1, 150.0, 151.5)
+    assert err < 1e-10 and not nc.any()
+
+
+def test_the_equation_check_sees_the_coupling():
+    """A 1 % change of the coupling in the integrated equations is seen."""
+    err, _ = _integrate(_E5, _L5, 1.0, _B5, 1.1, 150.0, 170.0,
+                        beta_ode=1.01 * _B5)
+    assert err > 1e-7
+
+
+def test_wronskian_is_canonical():
+    """S'^T C - S^T C' = 1 and S, C each Lagrangian, so the K-matrix of any
+    real symmetric R is symmetric."""
+    S, C, Sp, Cp, P, _ = outer.gailitis(1.1, _E5, _L5, 1.0, _B5, 160.0, 60)
+    assert np.abs(Sp.T @ C - S.T @ Cp - np.eye(P.size)).max() < 1e-12
+    assert np.abs(S.T @ Sp - Sp.T @ S).max() < 1e-12
+    assert np.abs(C.T @ Cp - Cp.T @ C).max() < 1e-12
+
+
+def test_small_radius_is_flagged():
+    """Near a threshold at a small radius the series diverges at once: the
+    channel is flagged; far out it is not."""
+    _, _, _, _, P, nc = outer.gailitis(0.31, _E5, _L5, 1.0, _B5, 30.0, 60)
+    assert nc[P.tolist().index(2)]
+    _, _, _, _, P, nc = outer.gailitis(4.0, _E5, _L5, 1.0, _B5, 300.0, 60)
+    assert not nc.any()
+
+
+def test_matching_reduces_to_coulomb_matching_without_coupling():
+    """With beta = 0 the coupled matching (full asymptotic matrices and the
+    closed channels' columns) is the diagonal matching of k_matrix."""
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    n = sym["w"].shape[0]
+    A = 200.0
+    for E in (0.9, 3.0, 8.0):
+        R = r_matrix(sym["E_pole"], sym["w"], sym["a"], E)[0]
+        cd = channel_data(np.array([E]), sym["e_thr"], sym["l"], sym["z"], A)
+        c1 = {k: v[0] for k, v in cd.items()}
+        K0, P0 = k_matrix(R, A, c1["open"], c1["s"], c1["c"], c1["sp"],
+                          c1["cp"], c1["L"])
+        S, C, Sp, Cp, P, _ = outer.gailitis(E, sym["e_thr"], sym["l"],
+                                            sym["z"], np.zeros((0, n, n)), A, 60)
+        K1 = outer.k_matrix_asymptotic(R, A, S, C, Sp, Cp, P, c1["L"])
+        assert np.array_equal(P, P0)
+        assert np.abs(K1 - K0).max() < 1e-9 * max(1.0, np.abs(K0).max())
+
+
+def test_expansion_carries_the_multipole_tail():
+    """K from propagating to A = 120 and to A = 240: matched to Coulomb
+    functions the two differ by the dropped tail; matched to the expansion
+    they agree at least ten times better."""
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    beta = _beta(8, 1, (0.3, 0.6))
+
+    def K_at(A, nsec, E, gl):
+        prop = {"A": A, "n_sec": nsec, "beta": beta, "gailitis_terms": gl}
+        if not gl:
+            return outer.k_matrix_propagated(sym, prop, E)[0]
+        secs = outer.outer_sectors(sym, prop)
+        Ra = r_matrix(sym["E_pole"], sym["w"], sym["a"], E)[0]
+        RA = outer.propagate(sym["a"] * Ra, secs, E) / A
+        S, C, Sp, Cp, P, _ = outer.gailitis(E, sym["e_thr"], sym["l"],
+                                            sym["z"], beta, A, gl)
+        cd = channel_data(np.array([E]), sym["e_thr"], sym["l"], sym["z"], A)
+        return outer.k_matrix_asymptotic(RA, A, S, C, Sp, Cp, P, cd["L"][0])
+
+    for E in (6.0, 9.0):
+        d0 = np.abs(K_at(120.0, 400, E, 0) - K_at(240.0, 880, E, 0)).max()
+        d1 = np.abs(K_at(120.0, 400, E, 40) - K_at(240.0, 880, E, 40)).max()
+        assert d1 < 0.1 * d0
