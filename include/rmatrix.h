@@ -84,6 +84,9 @@ enum rm_precision {
 #define RM_E_REFINE_NOCONV  0x20  /* FP32 solve: refinement did not reach
                                      the FP64 test; the energy was solved
                                      again in FP64 (below)                 */
+#define RM_E_ASYM_NOCONV    0x40  /* asymptotic expansion at A: a channel's
+                                     first omitted term exceeds 1e-6
+                                     (rm_set_gailitis)                     */
 
 typedef struct rm_sym *rm_sym_t;  /* one symmetry, device-resident, opaque */
 
@@ -337,6 +340,31 @@ int rm_mesh_from_density(const float *dens, int32_t nw, double lo, double hi,
  * symmetric), RM_ERR_STATE, RM_ERR_NOMEM, RM_ERR_HIP. */
 int rm_set_propagation(rm_sym_t sym, double A, int32_t n_sec, int32_t lmax,
                        const double *beta, void *stream);
+
+/* rm_set_gailitis keeps the multipole terms beyond A as well: the open-
+ * channel solutions matched at A become the coupled asymptotic series of
+ * Gailitis (J. Phys. B 9 (1976) 843), the standard outer-region expansion
+ * (the paper says nothing of the region beyond a).  For the solution that
+ * behaves as exp(i theta_j) in open channel j,
+ *   u_i = g_ij exp(i theta_j),  g_ij = sum_p c^p_ij r^-p,
+ *   theta_j = k_j r - eta_j ln(2 k_j r) - l_j pi/2 + sigma_j,
+ * the coefficients follow from the equations above by powers of 1/r (a
+ * three-term recurrence coupled through beta; channels of equal threshold
+ * take the relation one order up); s = Im, c = Re of u / sqrt(k_j), and the
+ * matching at A solves [C - R A C' | closed] [K; X] = R A S' - S with these
+ * n x n_o matrices in place of the diagonal Coulomb functions (closed
+ * channels keep their decaying Whittaker functions).  Each channel's series
+ * is summed to its smallest term, at most max_terms terms: the first term
+ * larger than the one before ends the sum unadded, a term below 1e-16 after
+ * adding it; an energy whose first omitted term exceeds 1e-6 in some
+ * channel gets RM_E_ASYM_NOCONV (A too small for its energies: near
+ * thresholds, or between close thresholds, k r must be large against the
+ * couplings).  max_terms = 0 switches the expansion off; rm_set_propagation
+ * with n_sec = 0 switches both off.  Sweeps with solve_fp32 reject such
+ * symmetries (the FP64 solve only).  Synchronises `stream`.  Errors:
+ * RM_ERR_ARG (null handle, max_terms outside [0, 200]), RM_ERR_STATE (no
+ * propagation set). */
+int rm_set_gailitis(rm_sym_t sym, int32_t max_terms, void *stream);
 
 /* ---- Photoionization ---------------------------------------------------
  * The photoionization runs of the paper (Sec. 2-3: one dipole per pair of

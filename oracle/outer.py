@@ -294,6 +294,22 @@ def k_matrix_asymptotic(R, r, S, C, Sp, Cp, P, L):
     return Z[P, :]
 
 
+def k_matrix_propagated_gailitis(sym, prop, E):
+    """(K, P, nonconv) at one energy: propagation to A, matching to the
+    asymptotic expansion with prop["gailitis_terms"] terms at most (K
+    symmetrised, as the sweep uses it)."""
+    A = prop["A"]
+    RA = r_matrix_at_A(sym, prop, E)
+    S, C, Sp, Cp, P, nc = gailitis(E, sym["e_thr"], sym["l"], sym["z"],
+                                   np.asarray(prop["beta"], dtype=np.float64),
+                                   A, prop["gailitis_terms"])
+    if P.size == 0:
+        return np.zeros((0, 0)), P, False
+    cd = channel_data(np.array([E]), sym["e_thr"], sym["l"], sym["z"], A)
+    K = k_matrix_asymptotic(RA, A, S, C, Sp, Cp, P, cd["L"][0])
+    return 0.5 * (K + K.T), P, bool(nc.any())
+
+
 def sweep_propagated_gailitis(sym, prop, E, n_target=None):
     """(Omega [m, P], nonconv [m] bool) over a mesh: propagation to A, then
     matching to the asymptotic expansion with prop["gailitis_terms"] terms

@@ -1710,33 +1710,37 @@ __device__ int match_one(const MatchLaunch &L, int s, int e, WaveLds &W) {
     wave_sync();
     bits |= wave_solve_fp32(L, S, Aug, Kb, ch, no, W);
   } else if (!k_given) {
-    bits |= wave_channel_functions(S, Ee, ch);
-    wave_sync();
-    // [D1 - R D2 | R[:, P] diag(a s'_P) - diag(s_P)], R already in place
-    const int nsq = n * n;
-    for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
-      double r[UNR], d2[UNR], asp[UNR], d1[UNR], sv[UNR];
+    // with the asymptotic expansion the propagation kernel has assembled
+    // the system at A (and set the channel-function bits)
+    if (S.gl_terms == 0) {
+      bits |= wave_channel_functions(S, Ee, ch);
+      wave_sync();
+      // [D1 - R D2 | R[:, P] diag(a s'_P) - diag(s_P)], R already in place
+      const int nsq = n * n;
+      for (int q0 = lane; q0 < nsq; q0 += UNR * WT) {
+        double r[UNR], d2[UNR], asp[UNR], d1[UNR], sv[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = q0 + u * WT;
-        const bool in = q < nsq;
-        const int i = q / n, j = q % n;
-        r[u] = in ? Aug[(int64_t)i * ld + j] : 0.0;
-        d2[u] = in ? ch[j].d2 : 0.0;
-        asp[u] = (in && j < no) ? ch[j].asp : 0.0;
-        d1[u] = (in && i == j) ? ch[i].d1 : 0.0;
-        sv[u] = (in && i == j) ? ch[i].s : 0.0;
-      }
+        for (int u = 0; u < UNR; ++u) {
+          const int q = q0 + u * WT;
+          const bool in = q < nsq;
+          const int i = q / n, j = q % n;
+          r[u] = in ? Aug[(int64_t)i * ld + j] : 0.0;
+          d2[u] = in ? ch[j].d2 : 0.0;
+          asp[u] = (in && j < no) ? ch[j].asp : 0.0;
+          d1[u] = (in && i == j) ? ch[i].d1 : 0.0;
+          sv[u] = (in && i == j) ? ch[i].s : 0.0;
+        }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = q0 + u * WT;
-        if (q >= nsq) continue;
-        const int i = q / n, j = q % n;
-        Aug[(int64_t)i * ld + j] = d1[u] - r[u] * d2[u];
-        if (j < no) Aug[(int64_t)i * ld + n + j] = r[u] * asp[u] - sv[u];
+        for (int u = 0; u < UNR; ++u) {
+          const int q = q0 + u * WT;
+          if (q >= nsq) continue;
+          const int i = q / n, j = q % n;
+          Aug[(int64_t)i * ld + j] = d1[u] - r[u] * d2[u];
+          if (j < no) Aug[(int64_t)i * ld + n + j] = r[u] * asp[u] - sv[u];
+        }
       }
+      wave_sync();
     }
-    wave_sync();
     if (wave_lu_solve(Aug, n, ld, no, W)) bits |= RM_E_SINGULAR;
   }
   if (!k_given) {

@@ -364,7 +364,7 @@ static int free_sym(Sym *s);
 
 // [Aug n x 2n | K n x n | g n | v n | pivots n]: g and v serve
 // photoionization, the pivots (as int) the FP32 solve's refinement
-static int64_t work_doubles(int n) { return (int64_t)3 * n * n + 3 * n; }
+static int64_t work_doubles(int n) { return match_work_doubles(n); }
 // damped photoionization: [2n x 2n real driven system, leading dimension
 // 2n + 2 | R_re n x n | R_im n x n | g_re n | g_im n]
 static int64_t sys_doubles_damped(int n) { return (int64_t)2 * n * (2 * n + 2); }
@@ -827,6 +827,13 @@ static int plan_build(Plan &p, const rm_sym_t *syms, int n_sym, int n_target,
     woff.push_back(wacc);
     coff.push_back(cacc);
     wacc += p.damped ? work_doubles_damped(s->n) : work_doubles(s->n);
+    // the asymptotic expansion's scratch follows the symmetry's workspace
+    if (!p.damped && s->n_sec > 0 && s->gl_terms > 0) {
+      if (o.solve_fp32)
+        return fail(RM_ERR_ARG, "the asymptotic expansion at A (rm_set_gailitis) "
+                                "runs with the FP64 solve only");
+      wacc += gl_doubles(s->n, s->lmax);
+    }
     cacc += s->n;
   }
   p.work_estride = wacc;
@@ -1117,7 +1124,7 @@ static int free_sym(Sym *s) {
   void *ptrs[] = {s->E_pole, s->Wt, s->W32c, s->Whc, s->Wlc, s->e_thr,
                   s->l,      s->perm, s->inv, s->tgt,  s->ut,  s->G, s->GT,
                   s->pair_ij, s->Ph, s->Pl, s->P32, s->P64, s->dip,
-                  s->prop_O, s->prop_eps, s->gam};
+                  s->prop_O, s->prop_eps, s->gam, s->gl_beta};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete[] s->h_e_thr;
@@ -1429,6 +1436,7 @@ int rm_set_propagation(rm_sym_t sym, double A, int32_t n_sec, int32_t lmax,
   RM_HIP(hipStreamSynchronize(st));  // queued sweeps may still read the old sectors
   if (n_sec == 0) {
     sym->n_sec = 0;
+    sym->gl_terms = 0;
     return RM_OK;
   }
   if (!(A > sym->a) || !std::isfinite(A)) return fail(RM_ERR_ARG, "A must be finite and > a");
@@ -1549,13 +1557,53 @@ int rm_set_propagation(rm_sym_t sym, double A, int32_t n_sec, int32_t lmax,
     return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
                 "propagation tables: %s", hipGetErrorString(e));
   }
+  // couplings for the asymptotic expansion: row i of [n][lmax n] holds
+  // beta^lam_im / A^lam (sorted order) for lam = 1..lmax
+  double *dB = nullptr;
+  if (lmax > 0) {
+    std::vector<double> Bc((size_t)n * lmax * n);
+    for (int i = 0; i < n; ++i)
+      for (int lam = 0; lam < lmax; ++lam) {
+        const double sc = std::pow(A, -(double)(lam + 1));
+        for (int m = 0; m < n; ++m)
+          Bc[((size_t)i * lmax + lam) * n + m] =
+              beta[((int64_t)lam * n + sym->h_perm[i]) * n + sym->h_perm[m]] * sc;
+      }
+    e = hipMalloc((void **)&dB, Bc.size() * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpy(dB, Bc.data(), Bc.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (dB) (void)hipFree(dB);
+      (void)hipFree(dO);
+      (void)hipFree(de);
+      return fail(e == hipErrorOutOfMemory ? RM_ERR_NOMEM : RM_ERR_HIP,
+                  "propagation couplings: %s", hipGetErrorString(e));
+    }
+  }
   if (sym->prop_O) (void)hipFree(sym->prop_O);
   if (sym->prop_eps) (void)hipFree(sym->prop_eps);
+  if (sym->gl_beta) (void)hipFree(sym->gl_beta);
   sym->prop_O = dO;
   sym->prop_eps = de;
+  sym->gl_beta = dB;
+  sym->lmax = lmax;
   sym->n_sec = n_sec;
   sym->A = A;
   sym->h_sec = h;
+  return RM_OK;
+}
+
+int rm_set_gailitis(rm_sym_t sym, int32_t max_terms, void *stream) {
+  if (!sym) return fail(RM_ERR_ARG, "null handle");
+  if (max_terms < 0 || max_terms > kGlMaxTerms)
+    return fail(RM_ERR_ARG, "max_terms outside [0, %d]", kGlMaxTerms);
+  int rc = check_device(sym);
+  if (rc) return rc;
+  if (max_terms > 0 && sym->n_sec == 0)
+    return fail(RM_ERR_STATE, "the asymptotic expansion needs the propagation "
+                              "(rm_set_propagation) first");
+  RM_HIP(hipStreamSynchronize((hipStream_t)stream));  // queued sweeps read it
+  sym->gl_terms = max_terms;
   return RM_OK;
 }
 

@@ -28,6 +28,24 @@ __host__ __device__ inline int64_t t_ext_doubles(int n) {
   return (int64_t)6 * n * n;
 }
 
+// The asymptotic expansion beyond A works on blocks of kGlCols open
+// channels; its per-energy scratch (after the symmetry's workspace) holds a
+// doubled ring of 2 Q coefficient slots (Q = max(lmax, 2) + 1), two slots
+// of the coupling products, the sums g and g', and two slots for the final
+// product with R, each slot n rows of 2 kGlCols doubles (real | imaginary).
+// Doubles of one energy's matching workspace of an n-channel symmetry:
+// [M | B] n x 2n, K n x n, 2n for photoionization, n pivots.
+__host__ __device__ inline int64_t match_work_doubles(int n) {
+  return (int64_t)3 * n * n + 3 * n;
+}
+
+constexpr int kGlCols = 16;
+constexpr int kGlMaxTerms = 200;
+__host__ __device__ inline int gl_ring(int lmax) { return (lmax > 2 ? lmax : 2) + 1; }
+__host__ __device__ inline int64_t gl_doubles(int n, int lmax) {
+  return (int64_t)(2 * gl_ring(lmax) + 6) * n * 2 * kGlCols;
+}
+
 // Device-side view of one symmetry (plain data, copied into a descriptor
 // table that the grouped kernels index by symmetry number).
 struct SymDev {
@@ -62,6 +80,10 @@ struct SymDev {
   double r_match;             // radius of the matching: A with sectors, else a
   const double *prop_O;       // [n_sec + 1][n][n]
   const double *prop_eps;     // [n_sec][n]
+  // asymptotic expansion at A (gl_terms = 0: matching to Coulomb functions):
+  // gl_beta [n][lmax n], row i holds beta^lam_im / A^lam for lam = 1..lmax
+  int gl_terms, lmax;
+  const double *gl_beta;
 };
 
 // A symmetry resident on one device.  Channels are stored sorted by
@@ -95,6 +117,8 @@ struct Sym {
   int n_sec = 0;          // outer-region sectors (0: match at r = a)
   double A = 0.0, h_sec = 0.0;
   double *prop_O = nullptr, *prop_eps = nullptr;  // owned
+  int lmax = 0, gl_terms = 0;   // multipole order; expansion terms (0: off)
+  double *gl_beta = nullptr;    // [n][lmax n] beta / A^lam, sorted (owned)
   // host copies
   double *h_e_thr;      // [n] sorted
   int32_t *h_perm;
@@ -110,6 +134,9 @@ struct Sym {
     d.n_sec = n_sec; d.A = A; d.h_sec = h_sec;
     d.r_match = n_sec > 0 ? A : a;
     d.prop_O = prop_O; d.prop_eps = prop_eps;
+    d.gl_terms = n_sec > 0 ? gl_terms : 0;
+    d.lmax = lmax;
+    d.gl_beta = gl_beta;
     return d;
   }
 };

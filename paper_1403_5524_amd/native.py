@@ -21,6 +21,7 @@ RM_E_CF_NOCONV = 0x04
 RM_E_NONFINITE = 0x08
 RM_E_ON_THRESHOLD = 0x10
 RM_E_REFINE_NOCONV = 0x20
+RM_E_ASYM_NOCONV = 0x40
 RM_FLAG_AUTOTUNE = 0x1
 RM_FLAG_NO_PAIR_PRODUCTS = 0x2
 RM_FLAG_PAIR_PRODUCTS = 0x4
@@ -34,7 +35,8 @@ EXPORTED = ("rm_load_poles", "rm_free", "rm_sym_info", "rm_sweep_energies",
             "rm_mlp_get_params", "rm_mlp_set_params", "rm_mlp_forward",
             "rm_mlp_grad", "rm_mlp_adam_step", "rm_mesh_from_density",
             "rm_plan_create", "rm_plan_execute", "rm_plan_info",
-            "rm_plan_free", "rm_set_propagation", "rm_load_dipoles",
+            "rm_plan_free", "rm_set_propagation", "rm_set_gailitis",
+            "rm_load_dipoles",
             "rm_load_widths",
             "rm_photoionization",
             "rm_convolve_gaussian",
@@ -117,6 +119,7 @@ def lib():
         L.rm_plan_info.argtypes = [vp, vp, vp, vp, i32]
         L.rm_plan_free.argtypes = [vp]
         L.rm_set_propagation.argtypes = [vp, f64, i32, i32, vp, vp]
+        L.rm_set_gailitis.argtypes = [vp, i32, vp]
         L.rm_load_dipoles.argtypes = [vp, vp, vp]
         L.rm_load_widths.argtypes = [vp, vp, vp]
         L.rm_photoionization.argtypes = [vp, i32, vp, i64, f64,
@@ -633,3 +636,10 @@ def rm_set_propagation(sym, A, n_sec, beta=None):
                                     int(b.shape[0]),
                                     b.ctypes.data if b.size else None,
                                     _stream()))
+
+
+def rm_set_gailitis(sym, max_terms):
+    """Match sym at A to the coupled asymptotic expansion (at most max_terms
+    terms per channel; 0 switches it off); needs rm_set_propagation."""
+    _check(lib().rm_set_gailitis(sym.handle if sym is not None else None,
+                                 int(max_terms), _stream()))

@@ -191,6 +191,11 @@ def test_propagation_rejects_invalid(L):
                                 None) == native.RM_ERR_ARG
 
 
+def test_gailitis_rejects_invalid(L):
+    assert L.rm_set_gailitis(None, 20, None) == native.RM_ERR_ARG
+    assert L.rm_set_gailitis(None, -1, None) == native.RM_ERR_ARG
+
+
 class _Poison:
     """A library stand-in that fails the test if any entry point is called:
     the binding must reject bad tensors before it reaches the C ABI."""

@@ -1,0 +1,124 @@
+"""Matching at A to the coupled asymptotic expansion (rm_set_gailitis)
+through the C ABI against the FP64 oracle (needs an MI355X).  Both sides sum
+the same terms (the smallest-term truncation decides alike), so they agree
+to rounding: K within 1e-8 of max(1, |K|), Omega within 1e-6 normwise, and
+the energies flagged RM_E_ASYM_NOCONV are those the oracle flags."""
+import numpy as np
+import pytest
+
+from oracle import outer
+from gpu_helpers import log, omega_normwise_err
+from paper_1403_5524_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_1403_5524_amd import native
+    native.lib()
+    return native
+
+
+def _beta(n, seed, scales):
+    rng = np.random.default_rng(seed)
+    out = []
+    for sc in scales:
+        M = rng.normal(0.0, sc, (n, n))
+        out.append(0.5 * (M + M.T))
+    return np.stack(out)
+
+
+def _dev(torch, dev, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64,
+                           device=dev)
+
+
+def test_sweep_with_expansion_c1(torch_dev, nat):
+    """8 channels, propagated to A = 120 through 200 sectors, expansion of
+    up to 40 terms: Omega and the non-convergence flags."""
+    torch, dev = torch_dev
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    h = nat.load_symmetry(w.syms[0])
+    prop = {"A": 120.0, "n_sec": 200, "beta": _beta(8, 1, (0.3, 0.6)),
+            "gailitis_terms": 40}
+    nat.rm_set_propagation(h, prop["A"], prop["n_sec"], prop["beta"])
+    nat.rm_set_gailitis(h, prop["gailitis_terms"])
+    E = w.mesh[::29]
+    om, st = nat.rm_sweep_energies([h], 8, _dev(torch, dev, E),
+                                   nat.make_opts(chunk=61))
+    ref, flags = outer.sweep_propagated_gailitis(sym, prop, E, n_target=8)
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref)
+    got = (st.cpu().numpy() & nat.RM_E_ASYM_NOCONV) != 0
+    log("expansion Omega, %d energies: %.2e; flagged %d (oracle %d)"
+        % (E.size, err, int(got.sum()), int(flags.sum())))
+    assert err < 1e-6
+    assert np.array_equal(got, flags)
+    assert 0 < flags.sum() < E.size  # both kinds of energy are covered
+    h.free()
+
+
+def test_kmatrix_200_channels_expansion_sampled(torch_dev, nat):
+    """The 200-channel symmetry (degenerate channel groups, dipole coupling
+    inside them) at sampled mesh energies: more than one column block."""
+    torch, dev = torch_dev
+    w = wl.config2()
+    sym = w.syms[0].as_dict()
+    h = nat.load_symmetry(w.syms[0])
+    prop = {"A": sym["a"] + 60.0, "n_sec": 60,
+            "beta": _beta(200, 3, (0.5, 2.0)), "gailitis_terms": 30}
+    nat.rm_set_propagation(h, prop["A"], prop["n_sec"], prop["beta"])
+    nat.rm_set_gailitis(h, prop["gailitis_terms"])
+    idx = wl.sample_indices(w.mesh.size, 4, seed=8)
+    E = w.mesh[idx]
+    K, no, _, st = nat.rm_kmatrix(h, _dev(torch, dev, E))
+    K, no, st = K.cpu().numpy(), no.cpu().numpy(), st.cpu().numpy()
+    worst = 0.0
+    for m, Ee in enumerate(E):
+        Kr, P, fl = outer.k_matrix_propagated_gailitis(sym, prop, Ee)
+        assert no[m] == P.size
+        assert bool(st[m] & nat.RM_E_ASYM_NOCONV) == fl
+        if P.size == 0:
+            continue
+        Kg = K[m, :P.size, :P.size]
+        worst = max(worst, np.abs(Kg - Kr).max() / max(1.0, np.abs(Kr).max()))
+    log("expansion K, 200 channels, open %s: %.2e" % (no.tolist(), worst))
+    assert worst < 1e-8
+    h.free()
+
+
+def test_expansion_without_coupling_and_switches(torch_dev, nat):
+    """No multipoles and A far out: the expansion is the Coulomb function,
+    so K equals the Coulomb matching at A; max_terms = 0 restores that K bit
+    for bit; the expansion needs the propagation; the FP32 solve refuses
+    it."""
+    torch, dev = torch_dev
+    w = wl.config1()
+    h = nat.load_symmetry(w.syms[0])
+    E = _dev(torch, dev, w.mesh[700::130])  # 3.5 Ry and up
+    with pytest.raises(nat.RmError) as ex:
+        nat.rm_set_gailitis(h, 20)
+    assert ex.value.code == nat.RM_ERR_STATE
+    nat.rm_set_propagation(h, 400.0, 400)
+    K0, _, _, _ = nat.rm_kmatrix(h, E)
+    nat.rm_set_gailitis(h, 60)
+    K1, _, _, st = nat.rm_kmatrix(h, E)
+    assert not (st.cpu().numpy() & nat.RM_E_ASYM_NOCONV).any()
+    d = (K1 - K0).abs().max().item() / max(1.0, K0.abs().max().item())
+    log("uncoupled expansion vs Coulomb matching at A = 400: %.2e" % d)
+    assert d < 1e-9
+    with pytest.raises(nat.RmError) as ex:
+        nat.rm_sweep_energies([h], 8, E, nat.make_opts(solve_fp32=1))
+    assert ex.value.code == nat.RM_ERR_ARG
+    nat.rm_set_gailitis(h, 0)
+    K2, _, _, _ = nat.rm_kmatrix(h, E)
+    assert torch.equal(K2, K0)
+    h.free()
