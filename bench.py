@@ -21,7 +21,9 @@ channels, every 50th energy of 409,600) under "photoionization" and on the
 Ca II shape of its Table 2 (1815 channels, every 3rd energy of 6000) under
 "photoionization_ca2", and an
 outer-region leg sweeps the headline symmetry with the R-matrix propagated
-through multipole coupling (rm_set_propagation) under "outer_propagation".
+through multipole coupling (rm_set_propagation) under "outer_propagation",
+and a 200-channel, 10-level target propagated to A = 200 and matched there
+to the asymptotic expansion (rm_set_gailitis) under "outer_expansion".
 An inner-region leg times the full eigen-solve that supplies poles and
 amplitudes (rm_inner_region, 8 channels x 512 sine functions, D = 4096) under
 "inner_region", with the oracle's solve of the same model as its CPU baseline.
@@ -300,12 +302,14 @@ def photo_leg(native, torch, oracle, workloads, steps, warmup, count,
 
 
 def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
-              n_sec=20, width=20.0):
-    """The headline symmetry with the outer-region propagation switched on
-    (dipole and quadrupole coupling, A = a + 20, 20 sectors): `count`
-    energies spread over the mesh, Omega checked against the oracle on 3."""
+              n_sec=20, width=20.0, w=None, gl_terms=0):
+    """The headline symmetry (or the workload w) with the outer-region
+    propagation switched on (dipole and quadrupole coupling, A = a + width,
+    n_sec sectors; with gl_terms > 0 matched at A to the asymptotic
+    expansion): `count` energies spread over the mesh, Omega checked against
+    the oracle on 3."""
     from oracle import outer
-    w = workloads.config2()
+    w = workloads.config2() if w is None else w
     sym = w.syms[0]
     beta = workloads.outer_coupling(sym.n)
     A = sym.a + width
@@ -314,6 +318,8 @@ def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
     h = native.load_symmetry(sym)
     t0 = time.perf_counter()
     native.rm_set_propagation(h, A, n_sec, beta)
+    if gl_terms:
+        native.rm_set_gailitis(h, gl_terms)
     setup = time.perf_counter() - t0
     E = torch.as_tensor(Em, dtype=torch.float64, device="cuda:0")
     P = w.n_target * (w.n_target + 1) // 2
@@ -333,8 +339,9 @@ def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
              for k in ("polesum", "propagate", "match")}
     native.rm_profile(False)
     idx = workloads.sample_indices(Em.size, 3, seed=4)
-    prop = {"A": A, "n_sec": n_sec, "beta": beta}
+    prop = {"A": A, "n_sec": n_sec, "beta": beta, "gailitis_terms": gl_terms}
     ref = outer.sweep_propagated(sym.as_dict(), prop, Em[idx], w.n_target)
+    flagged = float(((st.cpu().numpy() & native.RM_E_ASYM_NOCONV) != 0).mean())
     got = om.cpu().numpy()[idx]
     err = float((np.abs(got - ref).max(axis=1)
                  / np.maximum(np.abs(ref).max(axis=1), 1e-300)).max())
@@ -345,10 +352,12 @@ def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
     # basis change (4 n^3)
     flops = Em.size * (n_sec * (4.0 + 2.0 / 3.0 + 2.0) + 4.0) * n ** 3
     ach = flops / (stage["propagate"] * 1e-3) / 1e12 if stage["propagate"] else None
-    note("outer propagation: %.1f ms for %d energies (propagation %.1f ms), "
-         "err %.2e" % (ms, Em.size, stage["propagate"], err))
-    return {"workload": w.name + "+outer(A=a+%g, %d sectors, lmax 2)"
-                        % (width, n_sec),
+    note("outer propagation%s: %.1f ms for %d energies (propagation %.1f ms), "
+         "err %.2e" % (" + expansion" if gl_terms else "", ms, Em.size,
+                       stage["propagate"], err))
+    res = {"workload": w.name + "+outer(A=a+%g, %d sectors, lmax 2%s)"
+                        % (width, n_sec,
+                           ", expansion %d terms" % gl_terms if gl_terms else ""),
             "energies_timed": int(Em.size), "value": Em.size / (ms * 1e-3),
             "unit": "energies/s", "ms_per_step": ms,
             "stage_ms_per_step": stage, "setup_s": setup,
@@ -357,6 +366,11 @@ def outer_leg(native, torch, oracle, workloads, steps, warmup, count,
                                      "peak": 78.6, "unit": "TFLOP/s",
                                      "frac": ach / 78.6 if ach else None,
                                      "flops_per_step": flops}}
+    if gl_terms:
+        res["asym_noconv_fraction"] = flagged
+        res["propagation_roofline"]["note"] = (
+            "flops count the sectors only; the stage also runs the expansion")
+    return res
 
 
 def inner_leg(native, oracle, workloads, steps, n_basis, no_cpu):
@@ -713,10 +727,17 @@ def main():
             "status_flagged": r["flagged"],
             "speedup_over_%s" % args.prec: head["ms"] / r["ms"],
             "stage_ms_per_step": r["stage"], "kernels": r["kernels"]}
-    outer_res = None
+    outer_res = outer_gl_res = None
     if args.outer_M > 0:
         outer_res = outer_leg(native, torch, oracle, workloads, args.steps,
                               args.warmup, args.outer_M)
+        # matched to the asymptotic expansion at A = 200: a target of 10
+        # levels 0.5 Ry apart, propagated through 90 sectors of 2 a0
+        outer_gl_res = outer_leg(native, torch, oracle, workloads, args.steps,
+                                 args.warmup, args.outer_M, n_sec=90,
+                                 width=180.0,
+                                 w=workloads.outer_levels(M=args.outer_M),
+                                 gl_terms=40)
     photo = None
     if args.photo_M > 0:
         photo = photo_leg(native, torch, oracle, workloads, args.steps,
@@ -784,6 +805,7 @@ def main():
         "photoionization_damped": photo_damped,
         "photoionization_ca2": photo_ca,
         "outer_propagation": outer_res,
+        "outer_expansion": outer_gl_res,
         "inner_region": inner_res,
         "learned_mesh": c5,
         "table3": table3,

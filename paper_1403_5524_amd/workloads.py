@@ -202,6 +202,22 @@ def table3_symmetry(n, m, M, seed=8):
     return sym, uniform_mesh(0.0, 20.0, M)
 
 
+def outer_levels(n=200, n_levels=10, spacing=0.5, n_poles=8000, M=2048,
+                 seed=9):
+    """200 channels on 10 target levels spaced 0.5 Ry (20 channels of
+    random l per level, channel c on level c mod 10), 8000 poles in
+    [-5, 200], M energies in [0, 20]: a target whose levels lie far enough
+    apart for the asymptotic expansion beyond A, seeded."""
+    rng = np.random.default_rng(seed)
+    spec = (0.0, 20.0, M)
+    levels = spacing * np.arange(n_levels)
+    target = np.arange(n) % n_levels
+    sym = random_symmetry(rng, n, n_poles, -5.0, 200.0, mesh=spec,
+                          thresholds=levels, target=target)
+    return Workload("levels_n%d_t%d_nh%d_m%d" % (n, n_levels, n_poles, M),
+                    [sym], uniform_mesh(*spec), n_levels, spec)
+
+
 def outer_coupling(n, lmax=2, seed=6, scales=(1.0, 4.0)):
     """Long-range multipole coefficients beta [lmax, n, n] (symmetric,
     N(0, scale^2) off and on the diagonal; lam = 1 dipole, 2 quadrupole) for
