@@ -85,6 +85,31 @@ def test_noalloc_equals_sweep_c2_two_calls(env, prec):
     h.free()
 
 
+def test_noalloc_with_propagation_and_expansion(env):
+    """c1 propagated to A = 120 and matched to the asymptotic expansion:
+    the expansion's scratch comes from the same array; 600 then 250
+    energies, each equal to the allocating sweep bit for bit."""
+    torch, nat = env
+    w = wl.config1()
+    h = nat.load_symmetry(w.syms[0])
+    rng = np.random.default_rng(1)
+    beta = rng.normal(0.0, 1.0, (2, 8, 8)) * np.array([0.3, 0.6])[:, None, None]
+    beta = 0.5 * (beta + beta.transpose(0, 2, 1))
+    nat.rm_set_propagation(h, 120.0, 200, beta)
+    nat.rm_set_gailitis(h, 40)
+    opts = nat.make_opts(chunk=200)
+    for count in (600, 250):
+        E = torch.as_tensor(w.mesh[::3][:count], dtype=torch.float64,
+                            device="cuda:0")
+        log("noalloc c1 expansion m=%d" % count)
+        a_om, a_st = _noalloc(torch, nat, [h], 8, E, opts)
+        b_om, b_st = _alloc(torch, nat, [h], 8, E, opts)
+        assert np.array_equal(a_om, b_om)
+        assert np.array_equal(a_st, b_st)
+        assert (a_st & nat.RM_E_ASYM_NOCONV).any()
+    h.free()
+
+
 def test_noalloc_rejects_autotune_and_oversized(env):
     """Autotuning (which allocates) is refused; so is a symmetry set whose
     one energy needs more than the scratch array."""
