@@ -171,8 +171,12 @@ int rm_free(rm_sym_t sym);
 int rm_sym_info(rm_sym_t sym, int32_t *n_chan, int32_t *n_poles,
                 int32_t *n_target);
 
-/* The fused sweep: for each energy E[e] (device, [M]) and each of the n_sym
- * symmetries, pole sum -> channel functions -> matching -> K -> T, summing
+/* The fused sweep (Sec. 6: the outer-region step repeated over a fine
+ * energy mesh for every symmetry, Eq. 1-2 its pole sum; the matching, K,
+ * T and collision strengths are the standard R-matrix outer region the
+ * paper's codes run, Sec. 2-3): for each energy E[e] (device, [M]) and each
+ * of the n_sym symmetries, pole sum -> channel functions -> matching -> K
+ * -> T, summing
  * (g/2)|T_ij|^2 over symmetries into omega (device,
  * [M][n_target*(n_target+1)/2], FP64, overwritten).  Target pair (t, u),
  * t <= u, sits at t*n_target - t(t-1)/2 + (u - t) of each energy's row.
@@ -191,7 +195,7 @@ int rm_sweep_energies(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
  * channel slots, the pole-sum work tables and counters) lives in one static
  * device array of RM_NOALLOC_SCRATCH_BYTES, which every GPU the library
  * runs on holds until the process ends; the mesh is swept in chunks of as
- * many energies as that array holds (about 270 at 200 channels), so large
+ * many energies as that array holds (about 240 at 200 channels), so large
  * symmetries run with fewer energies in flight than rm_sweep_energies.
  * Differences: RM_FLAG_AUTOTUNE returns RM_ERR_ARG (timing allocates); the
  * pair form of the pole sum is used only where its products are already
@@ -230,7 +234,9 @@ int rm_plan_info(rm_plan_t plan, int64_t *chunk, int32_t *n_chunks,
                  int32_t *variants, int32_t n_variants);
 int rm_plan_free(rm_plan_t plan);
 
-/* K-matrix of one symmetry at m energies (device E [m]).
+/* K-matrix of one symmetry at m energies (device E [m]): the pole sum of
+ * Sec. 6 Eq. 1-2 matched at r = a (or at A, rm_set_propagation) to the
+ * asymptotic channel functions.
  * K (device, [m][n][n] FP64, n = n_chan): the open-open block occupies the
  * leading n_open[e] x n_open[e] rows/columns (row-major, leading dimension
  * n), open channels in ascending input-channel order; other entries are 0.
@@ -241,7 +247,8 @@ int rm_kmatrix(rm_sym_t sym, const double *E, int64_t m, const rm_opts *opts,
                double *K, int32_t *n_open, double *R_opt, int32_t *status,
                void *stream);
 
-/* Collision strengths from given K-matrices (device, layout of rm_kmatrix):
+/* Collision strengths (the Omega of the paper's Sec. 4-5 figures) from
+ * given K-matrices (device, layout of rm_kmatrix):
  * T = 2iK(1 - iK)^-1 and omega[e][pair(t,u)] += (g/2)|T_ij|^2 over open
  * channels i of level t and j of level u (device omega [m][n_target*(
  * n_target+1)/2], accumulated, not cleared).  n_open and E must be the ones

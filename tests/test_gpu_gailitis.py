@@ -122,3 +122,40 @@ def test_expansion_without_coupling_and_switches(torch_dev, nat):
     K2, _, _, _ = nat.rm_kmatrix(h, E)
     assert torch.equal(K2, K0)
     h.free()
+
+
+def test_expansion_beside_a_plain_symmetry_and_in_a_plan(torch_dev, nat):
+    """Two symmetries in one sweep, one matched to the expansion at A and
+    one matched at a (their workspaces differ in size), against the sum of
+    the oracle's two sweeps; then the same sweep captured in a plan and
+    replayed twice equals the eager sweep bit for bit."""
+    import oracle
+    torch, dev = torch_dev
+    w = wl.config1()
+    sym1 = w.syms[0].as_dict()
+    rng = np.random.default_rng(44)
+    s2 = wl.random_symmetry(rng, 5, 150, -2.0, 50.0, mesh=w.mesh_spec,
+                            thresholds=[0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.3, 1.5],
+                            target=[0, 2, 2, 4, 6])
+    h1 = nat.load_symmetry(w.syms[0])
+    h2 = nat.load_symmetry(s2)
+    prop = {"A": 120.0, "n_sec": 150, "beta": _beta(8, 5, (0.3, 0.6)),
+            "gailitis_terms": 40}
+    nat.rm_set_propagation(h1, prop["A"], prop["n_sec"], prop["beta"])
+    nat.rm_set_gailitis(h1, prop["gailitis_terms"])
+    E = w.mesh[5::37]
+    Ed = _dev(torch, dev, E)
+    om, st = nat.rm_sweep_energies([h2, h1], 8, Ed, nat.make_opts(chunk=23))
+    ref1, _ = outer.sweep_propagated_gailitis(sym1, prop, E, n_target=8)
+    ref2 = oracle.sweep(s2.as_dict(), E, n_target=8)["omega"]
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref1 + ref2)
+    log("expansion beside a plain symmetry, %d energies: %.2e" % (E.size, err))
+    assert err < 1e-6
+    plan = nat.Plan([h2, h1], 8, Ed, nat.make_opts(chunk=23))
+    for _ in range(2):
+        pom, pst = plan.execute()
+        torch.cuda.synchronize()
+        assert torch.equal(pom, om) and torch.equal(pst, st)
+    plan.free()
+    h1.free()
+    h2.free()
