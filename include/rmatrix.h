@@ -223,7 +223,11 @@ int rm_sweep_energies_noalloc(const rm_sym_t *syms, int32_t n_sym,
  * overlap.  rm_plan_create synchronises `stream` (autotuning and table
  * uploads); rm_plan_free synchronises the device.
  * rm_plan_info: energies per chunk, chunk count and the tile variant chosen
- * for each symmetry in kernel order (largest first). */
+ * for each symmetry in kernel order (largest first).  A plan holds its
+ * symmetries' descriptors as they were at rm_plan_create: rm_free or
+ * rm_set_propagation on one of them releases device arrays that the plan's
+ * graph still reads, so free the plan first; rm_set_gailitis takes effect
+ * only in plans created after it. */
 typedef struct rm_plan *rm_plan_t;
 int rm_plan_create(const rm_sym_t *syms, int32_t n_sym, int32_t n_target,
                    const double *E, int64_t M, const rm_opts *opts,
