@@ -51,7 +51,7 @@ PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # A figure applies only while its kernel source is the one measured.
 PMC_TRAFFIC = {
     "match_kernel": {"src": "paper_1403_5524_amd/csrc/match.hip",
-                     "sha256_16": "d0cf5b943093d4a2",
+                     "sha256_16": "87d60d344558c9f6",
                      "bytes_per_energy": 23.20e6 + 7.640e6},
     "polesum_fp64": {"src": "paper_1403_5524_amd/csrc/polesum.hip",
                      "sha256_16": "63e41f950c81571c",
