@@ -159,3 +159,52 @@ def test_expansion_beside_a_plain_symmetry_and_in_a_plan(torch_dev, nat):
     plan.free()
     h1.free()
     h2.free()
+
+
+def test_kmatrix_levels_target_converged(torch_dev, nat):
+    """The 200-channel, 10-level target of the expansion leg (groups of 20
+    degenerate channels with dipole coupling inside them), A = 200 through
+    90 sectors, at energies where every column converges (no flags on
+    either side).  K here is sensitive (a relative change of 1e-15 in R(a)
+    or in the sectors' eigenvalues moves it by 1e-10, measured with the
+    oracle), and the two propagations' rounding differs by about 3.5e-10 of
+    max(1, |K|) per sector: from the device's own R(a), 2.3e-9 at 10
+    sectors, 8.8e-9 at 30 and 3.2e-8 at 90, the same with the expansion
+    switched off (so none of it is the expansion's).  Hence: from the
+    device's R(a), the oracle's propagation, expansion and matching give K
+    within 1e-9 per sector; end to end, within 1e-6."""
+    from oracle.rmatrix import channel_data
+    torch, dev = torch_dev
+    w = wl.outer_levels(M=2048)
+    sym = w.syms[0].as_dict()
+    h = nat.load_symmetry(w.syms[0])
+    prop = {"A": sym["a"] + 180.0, "n_sec": 90,
+            "beta": wl.outer_coupling(200), "gailitis_terms": 40}
+    nat.rm_set_propagation(h, prop["A"], prop["n_sec"], prop["beta"])
+    nat.rm_set_gailitis(h, prop["gailitis_terms"])
+    E = w.mesh[[700, 1300, 1900]]  # 6.8, 12.7, 18.6 Ry: all channels open
+    K, no, R, st = nat.rm_kmatrix(h, _dev(torch, dev, E), want_R=True)
+    K, no, R, st = (K.cpu().numpy(), no.cpu().numpy(), R.cpu().numpy(),
+                    st.cpu().numpy())
+    secs = outer.outer_sectors(sym, prop)
+    A = prop["A"]
+    after, end = 0.0, 0.0
+    for m, Ee in enumerate(E):
+        Kr, P, fl = outer.k_matrix_propagated_gailitis(sym, prop, Ee)
+        assert no[m] == P.size == 200
+        assert not fl and not (st[m] & nat.RM_E_ASYM_NOCONV)
+        RA = outer.propagate(sym["a"] * R[m], secs, Ee) / A
+        S, C, Sp, Cp, P2, _ = outer.gailitis(Ee, sym["e_thr"], sym["l"],
+                                             sym["z"], prop["beta"], A, 40)
+        cd = channel_data(np.array([Ee]), sym["e_thr"], sym["l"], sym["z"], A)
+        Kd = outer.k_matrix_asymptotic(RA, A, S, C, Sp, Cp, P2, cd["L"][0])
+        Kd = 0.5 * (Kd + Kd.T)
+        Kg = K[m, :P.size, :P.size]
+        sc = max(1.0, np.abs(Kr).max())
+        after = max(after, np.abs(Kg - Kd).max() / sc)
+        end = max(end, np.abs(Kg - Kr).max() / sc)
+    log("expansion K, 10-level target, converged: %.2e from the device's "
+        "R(a), %.2e end to end" % (after, end))
+    assert after < 1e-9 * prop["n_sec"]
+    assert end < 1e-6
+    h.free()
