@@ -146,3 +146,71 @@ def test_expansion_carries_the_multipole_tail():
         d0 = np.abs(K_at(120.0, 400, E, 0) - K_at(240.0, 880, E, 0)).max()
         d1 = np.abs(K_at(120.0, 400, E, 40) - K_at(240.0, 880, E, 40)).max()
         assert d1 < 0.1 * d0
+
+
+_SWEEP_E = np.array([0.35, 1.1, 1.85, 3.3, 6.7, 9.4])
+
+
+def _c1():
+    return wl.config1().syms[0].as_dict()
+
+
+def test_sweep_with_expansion_uncoupled_is_coulomb_matching_at_A():
+    """The composition sweep_propagated_gailitis with beta = 0: the
+    expansion is the Coulomb function, so Omega equals sweep_propagated's
+    (Coulomb matching at the same A after the same sectors), no flags."""
+    sym = _c1()
+    n = sym["e_thr"].size
+    prop = {"A": 200.0, "n_sec": 60, "beta": np.zeros((1, n, n)),
+            "gailitis_terms": 60}
+    got, flags = outer.sweep_propagated_gailitis(sym, prop, _SWEEP_E)
+    ref = outer.sweep_propagated(sym, {k: prop[k] for k in ("A", "n_sec", "beta")},
+                                 _SWEEP_E)
+    assert not flags.any()
+    err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+    assert err < 1e-9
+
+
+def test_sweep_with_expansion_catches_a_dropped_coulomb_phase(monkeypatch):
+    """Planted mistake: sigma_l left out of theta.  The uncoupled pin above
+    then fails by far more than its bound."""
+    sym = _c1()
+    n = sym["e_thr"].size
+    prop = {"A": 200.0, "n_sec": 60, "beta": np.zeros((1, n, n)),
+            "gailitis_terms": 60}
+    ref = outer.sweep_propagated(sym, {k: prop[k] for k in ("A", "n_sec", "beta")},
+                                 _SWEEP_E)
+    monkeypatch.setattr(outer, "coulomb_phase", lambda l, eta: 0.0 * eta)
+    got, _ = outer.sweep_propagated_gailitis(sym, prop, _SWEEP_E)
+    err = (np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()
+    assert err > 1e-3
+
+
+def test_sweep_with_expansion_is_the_per_energy_chain():
+    """Coupled, with a target map: every Omega row equals
+    k_matrix_propagated_gailitis -> t_matrix -> collision_strengths, the
+    flags are that function's, and the row holds the flux of the open block
+    (pairs within one level count both orders, across two levels one)."""
+    import oracle
+    sym = dict(_c1())
+    n = sym["e_thr"].size
+    sym["target"] = np.array([0, 1, 1, 2, 0, 3, 2, 3], dtype=np.int32)
+    sym["g"] = 3.0
+    prop = {"A": 120.0, "n_sec": 100, "beta": _beta(n, 4, (0.3, 0.6)),
+            "gailitis_terms": 40}
+    got, flags = outer.sweep_propagated_gailitis(sym, prop, _SWEEP_E)
+    for m, E in enumerate(_SWEEP_E):
+        K, P, fl = outer.k_matrix_propagated_gailitis(sym, prop, E)
+        assert flags[m] == fl
+        if P.size == 0:
+            assert np.all(got[m] == 0.0)
+            continue
+        assert np.abs(K - K.T).max() == 0.0
+        T = oracle.t_matrix(K)
+        row = oracle.collision_strengths(T, P, sym["target"], 4, sym["g"])
+        assert np.abs(got[m] - row).max() <= 1e-13 * np.abs(row).max()
+        t = sym["target"][P]
+        same = t[:, None] == t[None, :]
+        T2 = np.abs(T) ** 2
+        flux = 0.5 * sym["g"] * (T2[same].sum() + 0.5 * T2[~same].sum())
+        assert np.isclose(got[m].sum(), flux, rtol=1e-13)
