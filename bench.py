@@ -59,6 +59,9 @@ PMC_TRAFFIC = {
     "polesum_bf16x3": {"src": "paper_1403_5524_amd/csrc/polesum_pd.hip",
                        "sha256_16": "045eb073247d461b",
                        "bytes_per_energy": 0.2359e6 + 0.7140e6},
+    "polesum_fp32": {"src": "paper_1403_5524_amd/csrc/polesum_pd.hip",
+                     "sha256_16": "045eb073247d461b",
+                     "bytes_per_energy": 0.2357e6 + 0.7133e6},
 }
 
 
