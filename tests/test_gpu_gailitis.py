@@ -208,3 +208,25 @@ def test_kmatrix_levels_target_converged(torch_dev, nat):
     assert after < 1e-9 * prop["n_sec"]
     assert end < 1e-6
     h.free()
+
+
+def test_expansion_uncoupled_high_l_and_charge(torch_dev, nat):
+    """Channels up to l = 12 with z = 5 (|eta| up to about 4), no
+    multipoles, A = 1500: the device's series and Coulomb phase reproduce
+    the Coulomb matching at A (its continued fractions) to 1e-9."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(31)
+    s = wl.random_symmetry(rng, 6, 80, -2.0, 40.0, z=5.0, lmax=12,
+                           mesh=(3.0, 10.0, 64))
+    h = nat.load_symmetry(s)
+    E = _dev(torch, dev, wl.uniform_mesh(3.0, 10.0, 64))
+    nat.rm_set_propagation(h, 1500.0, 40)
+    K0, _, _, _ = nat.rm_kmatrix(h, E)
+    nat.rm_set_gailitis(h, 60)
+    K1, _, _, st = nat.rm_kmatrix(h, E)
+    assert not (st.cpu().numpy() & nat.RM_E_ASYM_NOCONV).any()
+    d = (K1 - K0).abs().max().item() / max(1.0, K0.abs().max().item())
+    log("uncoupled expansion, l <= 12, z = 5, A = 1500: %.2e (l %s)"
+        % (d, s.l.tolist()))
+    assert d < 1e-9
+    h.free()

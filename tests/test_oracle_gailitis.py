@@ -24,7 +24,8 @@ def _beta(n, seed, scales):
 
 @pytest.mark.parametrize("l,z,k,r", [(0, 1.0, 1.0, 200.0), (3, 2.0, 0.7, 300.0),
                                      (1, 0.0, 2.0, 150.0), (5, -1.0, 1.5, 400.0),
-                                     (2, 3.0, 0.5, 500.0)])
+                                     (2, 3.0, 0.5, 500.0), (12, 5.0, 0.3, 1500.0),
+                                     (0, 4.0, 0.2, 2500.0)])
 def test_uncoupled_expansion_is_the_coulomb_function(l, z, k, r):
     S, C, Sp, Cp, P, nc = outer.gailitis(k * k, [0.0], [l], z,
                                          np.zeros((0, 1, 1)), r, 60)
