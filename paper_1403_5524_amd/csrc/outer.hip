@@ -31,10 +31,16 @@ __device__ int wave_propagate(const SymDev &S, double Ee, double *Aug, int ld,
   wave_sync();
   for (int t = 0; t <= S.n_sec; ++t) {
     const double *O = S.prop_O + (int64_t)t * nsq;
-    // Kb = O^T (X O)
-    wave_gemm<2>(Aug + n, ld, Aug, ld, O, n, n, n, n);
-    wave_gemm<2, G_TA>(Kb, n, O, n, Aug + n, ld, n, n, n);
-    if (t == S.n_sec) break;
+    // Kb = O^T (X O).  X is symmetric, so inside the sectors only the tiles
+    // that meet the product's lower triangle are formed and the assembly
+    // below reads element (i, j) at (max, min); the final change of basis
+    // forms all of it
+    wave_gemm_wide<2, 0, 2, 4>(Aug + n, ld, Aug, ld, O, n, n, n, n);
+    if (t == S.n_sec) {
+      wave_gemm_wide<2, G_TA, 2, 4>(Kb, n, O, n, Aug + n, ld, n, n, n);
+      break;
+    }
+    wave_gemm_wide<2, G_TA | G_LOWER, 2, 4>(Kb, n, O, n, Aug + n, ld, n, n, n);
     const double *eps = S.prop_eps + (int64_t)t * n;
     const double h = S.h_sec;
     for (int i = lane; i < n; i += WT) {
@@ -64,7 +70,8 @@ __device__ int wave_propagate(const SymDev &S, double Ee, double *Aug, int ld,
         const int q = q0 + u * WT;
         const bool in = q < nsq;
         const int i = in ? q / n : 0, j = in ? q % n : 0;
-        x[u] = in ? Kb[(int64_t)j * n + i] : 0.0;
+        const int hi = i > j ? i : j, lo = i + j - hi;
+        x[u] = in ? Kb[(int64_t)hi * n + lo] : 0.0;
         cj[u] = ch[j].d1;
         sj[u] = ch[j].d2;
         ksj[u] = ch[j].s;
