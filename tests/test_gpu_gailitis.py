@@ -230,3 +230,28 @@ def test_expansion_uncoupled_high_l_and_charge(torch_dev, nat):
         % (d, s.l.tolist()))
     assert d < 1e-9
     h.free()
+
+
+@pytest.mark.parametrize("scales", [(0.3,), (0.3, 0.6, 1.2)])
+def test_sweep_with_expansion_other_multipole_orders(torch_dev, nat, scales):
+    """Dipole only (lmax = 1) and up to octupole (lmax = 3: a ring of four
+    orders, the stacked couplings 3n wide): Omega and flags as the oracle's."""
+    torch, dev = torch_dev
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    h = nat.load_symmetry(w.syms[0])
+    prop = {"A": 120.0, "n_sec": 150, "beta": _beta(8, 9, scales),
+            "gailitis_terms": 40}
+    nat.rm_set_propagation(h, prop["A"], prop["n_sec"], prop["beta"])
+    nat.rm_set_gailitis(h, prop["gailitis_terms"])
+    E = w.mesh[3::41]
+    om, st = nat.rm_sweep_energies([h], 8, _dev(torch, dev, E),
+                                   nat.make_opts(chunk=29))
+    ref, flags = outer.sweep_propagated_gailitis(sym, prop, E, n_target=8)
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref)
+    got = (st.cpu().numpy() & nat.RM_E_ASYM_NOCONV) != 0
+    log("expansion, lmax %d, %d energies: %.2e; flagged %d (oracle %d)"
+        % (len(scales), E.size, err, int(got.sum()), int(flags.sum())))
+    assert err < 1e-6
+    assert np.array_equal(got, flags)
+    h.free()
