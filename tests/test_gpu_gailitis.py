@@ -255,3 +255,30 @@ def test_sweep_with_expansion_other_multipole_orders(torch_dev, nat, scales):
     assert err < 1e-6
     assert np.array_equal(got, flags)
     h.free()
+
+
+@pytest.mark.parametrize("prec", ["RM_PREC_FP32", "RM_PREC_BF16X3"])
+def test_sweep_with_expansion_mixed_pole_sum(torch_dev, nat, prec):
+    """The mixed-precision pole sums (FP32 or split-BF16 far poles, FP64
+    near ones) under the propagation and the expansion: Omega within the
+    mixed path's 1e-4 of the FP64 oracle, flags as the oracle's."""
+    torch, dev = torch_dev
+    w = wl.config1()
+    sym = w.syms[0].as_dict()
+    h = nat.load_symmetry(w.syms[0])
+    prop = {"A": 120.0, "n_sec": 150, "beta": _beta(8, 1, (0.3, 0.6)),
+            "gailitis_terms": 40}
+    nat.rm_set_propagation(h, prop["A"], prop["n_sec"], prop["beta"])
+    nat.rm_set_gailitis(h, prop["gailitis_terms"])
+    E = w.mesh[7::31]
+    om, st = nat.rm_sweep_energies([h], 8, _dev(torch, dev, E),
+                                   nat.make_opts(prec=getattr(nat, prec),
+                                                 near_delta=1e-3))
+    ref, flags = outer.sweep_propagated_gailitis(sym, prop, E, n_target=8)
+    err, _, _ = omega_normwise_err(om.cpu().numpy(), ref)
+    got = (st.cpu().numpy() & nat.RM_E_ASYM_NOCONV) != 0
+    log("expansion, %s pole sum, %d energies: %.2e; flagged %d (oracle %d)"
+        % (prec, E.size, err, int(got.sum()), int(flags.sum())))
+    assert err < 1e-4
+    assert np.array_equal(got, flags)
+    h.free()
