@@ -215,3 +215,32 @@ def test_sweep_with_expansion_is_the_per_energy_chain():
         T2 = np.abs(T) ** 2
         flux = 0.5 * sym["g"] * (T2[same].sum() + 0.5 * T2[~same].sum())
         assert np.isclose(got[m].sum(), flux, rtol=1e-13)
+
+
+def test_coulomb_phase_against_mpmath():
+    """sigma_l(eta) = arg Gamma(l + 1 + i eta) against mpmath's complex
+    log-gamma at 30 digits, modulo 2 pi, for l up to 12 and |eta| up to 50."""
+    import mpmath
+    mpmath.mp.dps = 30
+    for l in (0, 1, 4, 12):
+        for eta in (-50.0, -3.3, -0.2, 0.0, 0.7, 8.0, 50.0):
+            ref = float(mpmath.im(mpmath.loggamma(mpmath.mpc(l + 1, eta))))
+            d = (float(outer.coulomb_phase(l, eta)) - ref + np.pi) % (2 * np.pi) - np.pi
+            assert abs(d) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_expansion_at_large_radius_matches_mpmath_coulomb():
+    """The uncoupled expansion at r = 300 against mpmath's Coulomb F, G
+    (30 digits) with the k^-1/2 normalisation: an anchor outside the
+    oracle's own Coulomb code."""
+    import mpmath
+    mpmath.mp.dps = 30
+    for l, z, k in ((0, 1.0, 1.3), (3, 2.0, 0.8), (7, 0.5, 2.1)):
+        eta = -z / k
+        rho = k * 300.0
+        F = float(mpmath.coulombf(l, eta, rho))
+        G = float(mpmath.coulombg(l, eta, rho))
+        S, C, _, _, _, _ = outer.gailitis(k * k, [0.0], [l], z,
+                                          np.zeros((0, 1, 1)), 300.0, 60)
+        assert abs(S[0, 0] - F / np.sqrt(k)) < 1e-12
+        assert abs(C[0, 0] - G / np.sqrt(k)) < 1e-12
